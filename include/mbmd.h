@@ -1,0 +1,274 @@
+/*
+ * mbmd.h -- preconditioned separable-paraboloidal-surrogate (SPS) iteration
+ * for penalized weighted least-squares CT reconstruction and model-based
+ * material decomposition, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Tivnan, Wang & Stayman, "A Preconditioned Algorithm for
+ * Model-Based Iterative CT Reconstruction and Material Decomposition from
+ * Spectral CT Data" (arXiv 2010.01371).  Section names below refer to it.
+ *
+ * Estimation problem (Methods, "Generalized Models for Data Acquisition and
+ * Estimation", eq:meanModel and eq:mapEstimator):
+ *     ybar(x) = S exp(-(Q (x) A) x),
+ *     Phi(x)  = 1/2 (y - ybar)^T diag(w) (y - ybar) + R(x),
+ * with x the stack of N_k material images, A the 2D projector, Q [N_E x N_k]
+ * the attenuation of each material per energy, S [N_c x N_E] the channel
+ * sensitivities (gain and I0 folded in), w = 1/variance per ray and channel.
+ * Standard CT is N_k = N_E = N_c = 1 with S = I0 and Q = 1 ("Standard CT
+ * Reconstruction"); projection-domain decomposition is the identity geometry
+ * (A = I, "Projection-Domain Decomposition"); one-step MBMD is the general
+ * case ("One-Step Reconstruction and Material Decomposition").
+ *
+ * Conventions for every call:
+ *   - Arrays named *_dev are device pointers (HIP device memory, float32,
+ *     C-contiguous); the caller owns them.  Arrays named *_host are host
+ *     pointers.  Descriptor structs are host memory and are copied by the
+ *     call that receives them.
+ *   - Images are [n_mat][ny][nx] (x fastest).  Sinograms are
+ *     [n][n_views][n_bins] (bins fastest).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  All work is
+ *     enqueued on it asynchronously unless a *_host output is requested,
+ *     in which case the call synchronizes that stream before returning.
+ *   - Return value: MBMD_OK (0) or a negative mbmd_status.  No exception
+ *     crosses this interface.  mbmd_last_error() returns a thread-local
+ *     message for the last failure.  Errors of kernels already enqueued
+ *     surface at the next synchronizing call.
+ *   - The library allocates its own device memory (geometry tables,
+ *     problem state, preconditioner tables) when a problem or geometry is
+ *     first set up, never inside mbmd_sps_step's iteration loop.
+ */
+#ifndef MBMD_H
+#define MBMD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MBMD_OK = 0,
+    MBMD_ERR_ARG = -1,          /* invalid argument (NULL, non-positive size, bad enum) */
+    MBMD_ERR_SHAPE = -2,        /* sizes the library does not support (see each call) */
+    MBMD_ERR_HIP = -3,          /* a HIP runtime call failed */
+    MBMD_ERR_NOT_BUILT = -4,    /* preconditioner requested before mbmd_precond_build */
+    MBMD_ERR_NUMERIC = -5,      /* non-finite objective or step size detected */
+    MBMD_ERR_UNSUPPORTED = -6   /* option combination not implemented */
+} mbmd_status;
+
+typedef enum {
+    MBMD_GEOM_PARALLEL = 0,     /* parallel beam */
+    MBMD_GEOM_FAN_FLAT = 1,     /* fan beam, flat detector */
+    MBMD_GEOM_IDENTITY = 2      /* A = I: the unknown is a sinogram of line integrals */
+} mbmd_geom_kind;
+
+typedef enum {
+    MBMD_PRECOND_NONE = 0,      /* plain SPS */
+    MBMD_PRECOND_FOURIER = 1,   /* (cross-material) modified Fourier: M = M0 U^H L^-1/2 U */
+    MBMD_PRECOND_HAAR = 2,      /* (cross-material) Haar wavelet:     M = M0 U^T K^-1/2 U */
+    MBMD_PRECOND_BLOCKDIAG = 3  /* per-pixel N_k x N_k block diagonal: M = M0 */
+} mbmd_precond;
+
+typedef enum {
+    MBMD_PENALTY_QUADRATIC = 0, /* R = 1/2 x^T (beta (x) Gamma) x */
+    MBMD_PENALTY_HUBER = 1      /* R = beta sum_pairs psi_delta(x_j - x_j'), one material */
+} mbmd_penalty_kind;
+
+/*
+ * 2D geometry.  The projector is distance-driven; the paper only calls A
+ * "the forward projector" (standard-CT and one-step MBMD sections), so the
+ * model is fixed here:
+ *   pixel centre   ((ix-(nx-1)/2) dx, (iy-(ny-1)/2) dy)      [mm]
+ *   view angle     theta_v = theta0 + v dtheta                 [rad]
+ *   detector axis  e = (cos theta, sin theta); central ray d = (-sin, cos)
+ *   bin centre     u_b = (b-(n_bins-1)/2) du + u_offset        [mm]
+ *   parallel ray   { u e + s d };  flat-fan ray from -dso d through
+ *                  (dsd - dso) d + u e
+ * Per view the sweep lines are the rows when |cos theta| >= |sin theta|
+ * (decided in FP64 on the host), else the columns; on each line the weight
+ * of a pixel is the overlap of the pixel with the bin footprint (cut by the
+ * bin's two boundary rays), divided by the footprint width, times the line
+ * spacing over |cos| of the bin-centre ray's angle to the line normal.
+ * For MBMD_GEOM_IDENTITY, nx must equal n_bins and ny n_views, and the
+ * other fields are ignored.
+ */
+typedef struct {
+    int kind;                   /* mbmd_geom_kind */
+    int nx, ny;                 /* image size (pixels) */
+    double dx, dy;              /* pixel size (mm) */
+    int n_views;
+    double theta0, dtheta;      /* first view angle and increment (rad) */
+    int n_bins;
+    double du, u_offset;        /* bin pitch and detector offset (mm) */
+    double dso, dsd;            /* source-isocentre and source-detector (mm), fan only */
+} mbmd_geometry;
+
+/* Spectral model (one-step MBMD section): Q and S are host FP64 arrays,
+ * copied at problem creation.  Limits: n_mat <= 4, n_chan <= 8,
+ * n_energy <= 256. */
+typedef struct {
+    int n_mat, n_energy, n_chan;
+    const double* Q_host;       /* [n_energy][n_mat] attenuation per unit of x */
+    const double* S_host;       /* [n_chan][n_energy] sensitivity incl. gain and I0 */
+} mbmd_spectral;
+
+/* Roughness penalty (eq:quadraticSmoothess, quadReg_summation): 4-neighbour
+ * graph Laplacian Gamma with out-of-image neighbours dropped.  beta is a
+ * host [n_mat][n_mat] symmetric positive semi-definite matrix.  Huber needs
+ * n_mat == 1 and delta > 0. */
+typedef struct {
+    int kind;                   /* mbmd_penalty_kind */
+    const double* beta_host;    /* [n_mat][n_mat] */
+    double delta;               /* Huber threshold (units of x) */
+} mbmd_penalty;
+
+typedef struct mbmd_problem mbmd_problem;
+typedef struct mbmd_batch mbmd_batch;
+
+/* ---------------------------------------------------------------- projector */
+
+/*
+ * sino_dev[m] = A x_dev[m] for m < n_mat  (forward projection, the A of
+ * eq:meanModel in the standard-CT and one-step MBMD sections).
+ * x_dev: [n_mat][ny][nx]; sino_dev: [n_mat][n_views][n_bins]; 1 <= n_mat <= 4.
+ * Geometry tables are built on the first call with a given geometry and
+ * cached per device; concurrent calls with the same geometry on different
+ * streams race on the cached scratch buffer.
+ * Errors: MBMD_ERR_ARG (NULL pointer, bad sizes), MBMD_ERR_SHAPE (fan source
+ * inside the image circle, n_mat out of range), MBMD_ERR_HIP.
+ */
+int mbmd_project(const mbmd_geometry* geom, const float* x_dev, float* sino_dev,
+                 int n_mat, void* stream);
+
+/*
+ * x_dev[m] = A^T sino_dev[m] for m < n_ch (matched back projection with the
+ * same weights; pixel-driven, deterministic, compensated sums over views).
+ * sino_dev: [n_ch][n_views][n_bins]; x_dev: [n_ch][ny][nx] (overwritten);
+ * 1 <= n_ch <= 8.  Same caching and errors as mbmd_project.
+ */
+int mbmd_backproject(const mbmd_geometry* geom, const float* sino_dev, float* x_dev,
+                     int n_ch, void* stream);
+
+/* ---------------------------------------------------------------- problems */
+
+/*
+ * Create a problem: copies the descriptors, y_dev and w_dev
+ * ([n_chan][n_views][n_bins]; w = inverse variance, or NULL for
+ * w = 1/max(y, 1)), allocates device state and computes A 1 (the gamma of
+ * the SPS section).  Errors: MBMD_ERR_ARG, MBMD_ERR_SHAPE (limits above;
+ * identity geometry with nx != n_bins or ny != n_views), MBMD_ERR_HIP.
+ */
+int mbmd_problem_create(const mbmd_geometry* geom, const mbmd_spectral* spectral,
+                        const mbmd_penalty* penalty, const float* y_dev, const float* w_dev,
+                        void* stream, mbmd_problem** out);
+
+/* Free a problem (synchronizes its last stream). NULL is ignored. */
+void mbmd_problem_destroy(mbmd_problem* prob);
+
+/*
+ * Build preconditioner `kind` ("Preconditioned Optimization" and the
+ * Fourier, modified Fourier, wavelet and cross-material sections):
+ *   - Fisher weights with a data-based D (one energy: D = y / I0; several:
+ *     a water-only per-ray Gauss-Newton estimate, the first material playing
+ *     water);
+ *   - M0_j = Htilde_j^-1/2 from the material columns (F + R) 1_k
+ *     (eigenvalues floored at 1e-6 of each block's largest; a pixel no ray
+ *     sees gets M0_j = 0);
+ *   - FOURIER: impulse response of M0 H M0 at (ny/2, nx/2) per material, DFT
+ *     with the phase removed, real part, symmetrised per-frequency blocks,
+ *     eigenvalues floored at 1e-2 of the largest over all frequencies;
+ *   - HAAR: response to U^T 1 per material, Haar-transformed; same floor;
+ *   - BLOCKDIAG: M0 only.
+ * The composition is M = M0 U^H L^-1/2 U (the paper's symmetric sandwich
+ * M0^T U^T L^-1/2 U M0 does not whiten M0^T H M0).  Huber problems build
+ * with the quadratic Hessian beta Gamma.  FOURIER and HAAR need nx and ny
+ * powers of two (HAAR: nx == ny) and a projector geometry.
+ * Errors: MBMD_ERR_ARG, MBMD_ERR_SHAPE, MBMD_ERR_UNSUPPORTED, MBMD_ERR_HIP.
+ */
+int mbmd_precond_build(mbmd_problem* prob, int kind, void* stream);
+
+/*
+ * out_dev = M M^T g_dev for a built preconditioner (the direction operator
+ * of the preconditioned SPS step, without its minus sign); for
+ * MBMD_PRECOND_NONE out = g.  Both [n_mat][ny][nx], distinct buffers.
+ * Errors: MBMD_ERR_NOT_BUILT, MBMD_ERR_ARG, MBMD_ERR_HIP.
+ */
+int mbmd_precond_apply(mbmd_problem* prob, int kind, const float* g_dev, float* out_dev,
+                       void* stream);
+
+/*
+ * Gradient and SPS curvature of Phi at x_dev (SPS section):
+ *   grad = (Q (x) A)^T(-eta t^2 - rho t) + dR/dx
+ *        = A^T [sum_E Q_Ek (-t_E sum_c S_cE w_c (ybar_c - y_c))] + dR/dx,
+ *   curv = A^T [sum_E Q_Ek gamma_E c_E] + d_R   (the separable surrogate
+ *          Hessian diagonal, c_E = max(2 eta_E + rho_E, 0)),
+ * with rho read as S^T W (ybar - y) - eta t (the printed x^(n) stands for
+ * t^(n)).  grad_dev, curv_dev: [n_mat][ny][nx]; curv_dev and
+ * objective_host (Phi(x), FP64) may be NULL.
+ */
+int mbmd_gradient(mbmd_problem* prob, const float* x_dev, float* grad_dev, float* curv_dev,
+                  double* objective_host, void* stream);
+
+/*
+ * Run n_iter SPS iterations in place on x_dev ([n_mat][ny][nx]).
+ *   NONE: x <- x - (g + dR)/(d + d_R) (the SPS update);
+ *   others: p = -M M^T grad Phi(x), q = (Q (x) A) p,
+ *           alpha = -g^T p / (sum_iE c_iE q_iE^2 + p^T R'' p),  x <- x + alpha p
+ *   (unit curvature in x' = M^-1 x, then the exact minimiser of the 1D
+ *   majoriser built from the same maximum curvatures; for the identity
+ *   geometry without penalty alpha is per ray).  Line integrals A x are
+ *   carried across iterations and recomputed every 25.  Reductions are FP64
+ *   and alpha stays on the device.
+ * objective_trace_host: NULL, or n_iter+1 doubles receiving Phi before each
+ * iteration and after the last (synchronizes).  Returns MBMD_ERR_NUMERIC if
+ * a non-finite objective or step was produced.
+ */
+int mbmd_sps_step(mbmd_problem* prob, float* x_dev, int precond, int n_iter,
+                  double* objective_trace_host, void* stream);
+
+/*
+ * Polyenergetic forward model: ybar_dev [n_chan][V][B] = S exp(-(Q (x) A) x);
+ * l_dev (NULL allowed) receives A x [n_mat][V][B] for mbmd_forward_vjp.
+ */
+int mbmd_forward(mbmd_problem* prob, const float* x_dev, float* ybar_dev, float* l_dev,
+                 void* stream);
+
+/*
+ * Backward of mbmd_forward: dx_dev [n_mat][ny][nx] =
+ *   A^T [ sum_E Q_Ek (-t_E) sum_c S_cE gbar_c ],  t_E = exp(-sum_k Q_Ek l_k),
+ * recomputing the energy sums from l_dev = A x (no ray x energy tensor is
+ * stored).  gbar_dev: [n_chan][V][B].
+ */
+int mbmd_forward_vjp(mbmd_problem* prob, const float* l_dev, const float* gbar_dev,
+                     float* dx_dev, void* stream);
+
+/* ---------------------------------------------------------------- batches */
+
+/*
+ * Group problems (uneven sizes allowed, all on the current device) for a
+ * batched iteration.  The problems are borrowed and must outlive the batch.
+ */
+int mbmd_batch_create(mbmd_problem* const* probs, int n, mbmd_batch** out);
+void mbmd_batch_destroy(mbmd_batch* batch);
+
+/*
+ * n_iter iterations of every problem of the batch (x_dev[i] belongs to
+ * problem i).  use_graph != 0 captures one iteration over all problems in a
+ * hipGraph on the first call and replays it; the same x pointers must be
+ * passed on later calls (a change re-captures).  Preconditioners must have
+ * been built.  No objective trace.
+ */
+int mbmd_batch_sps_step(mbmd_batch* batch, float* const* x_dev, int precond, int n_iter,
+                        int use_graph, void* stream);
+
+/* ---------------------------------------------------------------- misc */
+
+const char* mbmd_status_string(int status);
+const char* mbmd_last_error(void);
+int mbmd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MBMD_H */

@@ -1,0 +1,9 @@
+"""MI355X-native preconditioned SPS for PWLS CT reconstruction and model-based
+material decomposition (Tivnan, Wang & Stayman, arXiv 2010.01371).
+
+The compute path is ``libmbmd.so`` (HIP kernels for gfx950, C-ABI in
+include/mbmd.h); this package only marshals arguments to it.
+"""
+
+from .api import Batch, Problem, backproject, project, PRECONDS  # noqa: F401
+from .autograd import PolyForward, poly_forward  # noqa: F401

@@ -1,0 +1,201 @@
+"""Python front of the C-ABI in include/mbmd.h (argument marshalling only).
+
+Torch supplies device memory and the stream; every step of the method runs in
+the HIP kernels of libmbmd.so.  Geometries are dicts with the fields of
+``mbmd_geometry`` (``kind`` as 'parallel' | 'fan' | 'identity').
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+KINDS = {"parallel": 0, "fan": 1, "identity": 2}
+PRECONDS = {"none": 0, "fourier": 1, "haar": 2, "blockdiag": 3}
+PENALTIES = {"quadratic": 0, "huber": 1}
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_f32(t, shape=None, name="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != torch.float32:
+        raise TypeError("%s must be float32" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+    return t
+
+
+def geometry_struct(g):
+    k = g["kind"]
+    return _lib.Geometry(KINDS[k] if isinstance(k, str) else int(k), int(g["nx"]), int(g["ny"]),
+                         float(g.get("dx", 1.0)), float(g.get("dy", 1.0)), int(g["n_views"]),
+                         float(g.get("theta0", 0.0)), float(g.get("dtheta", 0.0)), int(g["n_bins"]),
+                         float(g.get("du", 1.0)), float(g.get("u_offset", 0.0)), float(g.get("dso", 0.0)),
+                         float(g.get("dsd", 0.0)))
+
+
+def project(geom, x):
+    """A x for x [n_mat, ny, nx] (float32, on the GPU) -> [n_mat, V, B]."""
+    lib = _lib.load()
+    x = x if x.dim() == 3 else x.unsqueeze(0)
+    _dev_f32(x, (x.shape[0], geom["ny"], geom["nx"]), "x")
+    out = torch.empty((x.shape[0], geom["n_views"], geom["n_bins"]), device=x.device, dtype=torch.float32)
+    g = geometry_struct(geom)
+    check(lib.mbmd_project(ctypes.byref(g), _ptr(x), _ptr(out), x.shape[0], _stream()), "mbmd_project")
+    return out
+
+
+def backproject(geom, sino):
+    """A^T s for s [n_ch, V, B] -> [n_ch, ny, nx]."""
+    lib = _lib.load()
+    sino = sino if sino.dim() == 3 else sino.unsqueeze(0)
+    _dev_f32(sino, (sino.shape[0], geom["n_views"], geom["n_bins"]), "sino")
+    out = torch.empty((sino.shape[0], geom["ny"], geom["nx"]), device=sino.device, dtype=torch.float32)
+    g = geometry_struct(geom)
+    check(lib.mbmd_backproject(ctypes.byref(g), _ptr(sino), _ptr(out), sino.shape[0], _stream()),
+          "mbmd_backproject")
+    return out
+
+
+class Problem:
+    """A PWLS / MBMD estimation problem living on the GPU."""
+
+    def __init__(self, geom, Q, S, y, w=None, penalty=None, device="cuda"):
+        lib = _lib.load()
+        self.geom = dict(geom)
+        Q = np.ascontiguousarray(Q, dtype=np.float64)
+        S = np.ascontiguousarray(S, dtype=np.float64)
+        self.n_energy, self.n_mat = Q.shape
+        self.n_chan = S.shape[0]
+        self.image_shape = (self.n_mat, geom["ny"], geom["nx"])
+        self.sino_shape = (geom["n_views"], geom["n_bins"])
+        penalty = penalty or dict(kind="quadratic", beta=np.zeros((self.n_mat, self.n_mat)), delta=0.0)
+        beta = np.ascontiguousarray(penalty.get("beta", np.zeros((self.n_mat, self.n_mat))), dtype=np.float64)
+        if not torch.is_tensor(y):
+            y = torch.as_tensor(np.asarray(y, dtype=np.float32), device=device)
+        y = _dev_f32(y.contiguous(), (self.n_chan,) + self.sino_shape, "y")
+        if w is not None:
+            if not torch.is_tensor(w):
+                w = torch.as_tensor(np.asarray(w, dtype=np.float32), device=device)
+            w = _dev_f32(w.contiguous(), (self.n_chan,) + self.sino_shape, "w")
+        self.device = y.device
+        g = geometry_struct(geom)
+        sp = _lib.Spectral(self.n_mat, self.n_energy, self.n_chan,
+                           Q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                           S.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        pen = _lib.Penalty(PENALTIES[penalty.get("kind", "quadratic")],
+                           beta.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(penalty.get("delta", 0.0)))
+        h = ctypes.c_void_p()
+        check(lib.mbmd_problem_create(ctypes.byref(g), ctypes.byref(sp), ctypes.byref(pen), _ptr(y),
+                                      _ptr(w) if w is not None else None, _stream(), ctypes.byref(h)),
+              "mbmd_problem_create")
+        self._h = h
+        self._lib = lib
+
+    @classmethod
+    def from_workload(cls, wl, device="cuda"):
+        return cls(wl.geom, wl.Q, wl.S, wl.y, wl.w, wl.penalty, device=device)
+
+    # ------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mbmd_problem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def zeros_image(self):
+        return torch.zeros(self.image_shape, device=self.device, dtype=torch.float32)
+
+    def precond_build(self, kind):
+        check(self._lib.mbmd_precond_build(self._h, PRECONDS[kind], _stream()), "mbmd_precond_build")
+
+    def precond_apply(self, kind, g):
+        _dev_f32(g, self.image_shape, "g")
+        out = torch.empty_like(g)
+        check(self._lib.mbmd_precond_apply(self._h, PRECONDS[kind], _ptr(g), _ptr(out), _stream()),
+              "mbmd_precond_apply")
+        return out
+
+    def gradient(self, x, curvature=False, objective=False):
+        _dev_f32(x, self.image_shape, "x")
+        g = torch.empty_like(x)
+        d = torch.empty_like(x) if curvature else None
+        phi = ctypes.c_double(0.0)
+        check(self._lib.mbmd_gradient(self._h, _ptr(x), _ptr(g), _ptr(d) if d is not None else None,
+                                      ctypes.byref(phi) if objective else None, _stream()), "mbmd_gradient")
+        return g, d, (phi.value if objective else None)
+
+    def sps_step(self, x, precond="none", n_iter=1, trace=False):
+        """Run n_iter iterations in place on x; returns the objective trace (n_iter+1) or None."""
+        _dev_f32(x, self.image_shape, "x")
+        tr = np.zeros(n_iter + 1) if trace else None
+        ptr = tr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if trace else None
+        check(self._lib.mbmd_sps_step(self._h, _ptr(x), PRECONDS[precond], int(n_iter), ptr, _stream()),
+              "mbmd_sps_step")
+        return tr
+
+    def forward(self, x, keep_l=True):
+        _dev_f32(x, self.image_shape, "x")
+        ybar = torch.empty((self.n_chan,) + self.sino_shape, device=x.device, dtype=torch.float32)
+        l = torch.empty((self.n_mat,) + self.sino_shape, device=x.device, dtype=torch.float32) if keep_l else None
+        check(self._lib.mbmd_forward(self._h, _ptr(x), _ptr(ybar), _ptr(l) if keep_l else None, _stream()),
+              "mbmd_forward")
+        return ybar, l
+
+    def forward_vjp(self, l, gbar):
+        _dev_f32(l, (self.n_mat,) + self.sino_shape, "l")
+        _dev_f32(gbar, (self.n_chan,) + self.sino_shape, "gbar")
+        dx = torch.empty(self.image_shape, device=l.device, dtype=torch.float32)
+        check(self._lib.mbmd_forward_vjp(self._h, _ptr(l), _ptr(gbar), _ptr(dx), _stream()), "mbmd_forward_vjp")
+        return dx
+
+
+class Batch:
+    """Several problems iterated together (optionally as one hipGraph per iteration)."""
+
+    def __init__(self, problems):
+        self.problems = list(problems)
+        lib = _lib.load()
+        arr = (ctypes.c_void_p * len(self.problems))(*[p._h for p in self.problems])
+        h = ctypes.c_void_p()
+        check(lib.mbmd_batch_create(arr, len(self.problems), ctypes.byref(h)), "mbmd_batch_create")
+        self._h = h
+        self._lib = lib
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mbmd_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sps_step(self, xs, precond="fourier", n_iter=1, use_graph=True):
+        for p, x in zip(self.problems, xs):
+            _dev_f32(x, p.image_shape, "x")
+        arr = (ctypes.c_void_p * len(xs))(*[x.data_ptr() for x in xs])
+        check(self._lib.mbmd_batch_sps_step(self._h, arr, PRECONDS[precond], int(n_iter), int(bool(use_graph)),
+                                            _stream()), "mbmd_batch_sps_step")

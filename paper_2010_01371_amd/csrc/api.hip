@@ -1,0 +1,708 @@
+// C-ABI of the library (include/mbmd.h): problem state, preconditioner
+// builds, and the schedules of the plain and preconditioned SPS iterations.
+//
+// Every device step of the iteration runs in the kernels of this library; the
+// host only enqueues launches on the caller's stream.  Per-block FP64 partial
+// sums are reduced by one final kernel that also forms the step size alpha on
+// the device, so an iteration has no host synchronisation and can be captured
+// in a hipGraph (batched form).
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+struct mbmd_problem : public mbmd::Problem {};
+
+struct mbmd_batch {
+    std::vector<mbmd_problem*> probs;
+    std::vector<float*> xs;
+    int precond = -1;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    bool captured = false;
+    hipStream_t stream = nullptr;       // caller stream the graphs were last launched on
+    hipStream_t capture = nullptr;      // library-owned stream used only for capture
+};
+
+namespace mbmd {
+
+namespace {
+thread_local std::string g_last_error;
+constexpr int kTraceCap = 4096;
+constexpr double kM0Floor = 1e-6;
+constexpr double kEpsFourier = 1e-2;
+constexpr double kEpsHaar = 1e-2;
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+void Arena::reserve(size_t bytes) {
+    MBMD_HIP(hipMalloc(&base, bytes));
+    size = bytes;
+    used = 0;
+}
+
+void Arena::release() {
+    if (base) (void)hipFree(base);
+    base = nullptr;
+    size = used = 0;
+}
+
+namespace {
+
+template <class F>
+int guarded(F&& f) {
+    (void)hipGetLastError();   // do not attribute an earlier, unrelated failure to this call
+    try {
+        f();
+        return MBMD_OK;
+    } catch (const Error& e) {
+        set_error(e.msg);
+        return e.status;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return MBMD_ERR_HIP;
+    } catch (...) {
+        set_error("unknown error");
+        return MBMD_ERR_HIP;
+    }
+}
+
+bool is_pow2(int n) { return n >= 2 && (n & (n - 1)) == 0; }
+
+RayArgs ray_args(const Problem& P) {
+    return RayArgs{P.ni, P.K, P.E, P.C, P.Q, P.S, P.rowS, P.Qsum, P.y, P.w, P.identity ? nullptr : P.gammaA};
+}
+
+PenaltyArgs pen_args(const Problem& P) {
+    return PenaltyArgs{P.K, P.nx, P.ny, P.pen_kind, P.beta_d, (float)P.delta};
+}
+
+void project(Problem& P, const float* x, float* sino, int nmat, hipStream_t s) {
+    if (P.identity) {
+        MBMD_HIP(hipMemcpyAsync(sino, x, sizeof(float) * (size_t)nmat * P.ni, hipMemcpyDeviceToDevice, s));
+        return;
+    }
+    launch_project(*P.geom, x, sino, nmat, s);
+}
+
+void backproject(Problem& P, const float* sino, float* img, int nch, hipStream_t s) {
+    if (P.identity) {
+        MBMD_HIP(hipMemcpyAsync(img, sino, sizeof(float) * (size_t)nch * P.nj, hipMemcpyDeviceToDevice, s));
+        return;
+    }
+    launch_backproject(*P.geom, sino, img, nch, s);
+}
+
+double* region(Problem& P, int r) { return P.partials + (size_t)r * kMaxPartials; }
+
+// Sizes every buffer; called twice (sizing pass with a null arena base, then for real).
+void carve(Problem& P) {
+    Arena& A = P.arena;
+    const size_t nj = P.nj, ni = P.ni, K = P.K, C = P.C, E = P.E, npk = P.npk;
+    P.Q = A.take<float>(E * K);
+    P.S = A.take<float>(C * E);
+    P.rowS = A.take<float>(C);
+    P.Qsum = A.take<float>(E);
+    P.beta_d = A.take<float>(K * K);
+    P.y = A.take<float>(C * ni);
+    P.w = A.take<float>(C * ni);
+    P.gammaA = A.take<float>(ni);
+    P.l = A.take<float>(K * ni);
+    P.q = A.take<float>(K * ni);
+    P.u = A.take<float>(2 * K * ni);         // u then v, contiguous for one fused back projection
+    P.v = P.u ? P.u + K * ni : nullptr;
+    P.r = A.take<float>(C * ni);
+    const size_t tmp_ch = npk > 2 * K ? npk : 2 * K;
+    P.sino_tmp = A.take<float>(tmp_ch * ni);
+    P.W = A.take<float>(npk * ni);
+    P.g_img = A.take<float>(2 * K * nj);     // g then d, contiguous
+    P.d_img = P.g_img ? P.g_img + K * nj : nullptr;
+    P.p_img = A.take<float>(K * nj);
+    P.t_img = A.take<float>(npk > K ? npk * nj : K * nj);
+    P.t2_img = A.take<float>(K * nj);
+    P.dL_const = A.take<float>(K * nj);
+    P.M0 = A.take<float>(npk * nj);
+    if (!P.identity && is_pow2(P.nx) && is_pow2(P.ny)) {
+        P.spec = A.take<float2>(K * nj);
+        P.Linv = A.take<float>(npk * nj);
+        P.tw_x = A.take<float2>(P.nx / 2);
+        P.tw_y = A.take<float2>(P.ny / 2);
+        if (P.nx == P.ny) {
+            const int T = haar_tile(P.nx), nt = P.nx / T;
+            P.coef = A.take<float>(K * nj);
+            P.coarse = A.take<float>(K * (size_t)nt * nt);
+            P.Kinv = A.take<float>(npk * nj);
+        }
+    }
+    P.partials = A.take<double>((size_t)kRegions * kMaxPartials);
+    P.scal = A.take<double>(kScalars);
+    P.trace = A.take<double>(kTraceCap + 1);
+    P.trace_cap = kTraceCap;
+    P.flags = A.take<int>(4);
+}
+
+// r = M0 H M0 v (or H v when M0 is NULL), H = A^T W A + beta Gamma (quadratic).
+void hessian_apply(Problem& P, const float* v, float* out, const float* M0, hipStream_t s) {
+    const float* src = v;
+    if (M0) {
+        launch_block_apply(P.nj, P.K, M0, v, P.p_img, 1.0f, s);
+        src = P.p_img;
+    }
+    project(P, src, P.q, P.K, s);
+    launch_fisher_mix(P.ni, P.K, P.W, P.q, P.sino_tmp, s);
+    backproject(P, P.sino_tmp, out, P.K, s);
+    if (P.has_penalty) launch_penalty_hess_add(pen_args(P), src, out, s);
+    if (M0) launch_block_apply(P.nj, P.K, M0, out, out, 1.0f, s);
+}
+
+void ensure_fisher_m0(Problem& P, hipStream_t s) {
+    if (P.m0_built) return;
+    launch_fisher(ray_args(P), P.W, s);
+    // Htilde_j = column blocks of (F + R) 1_k = A^T (gamma_A W_kk')  (Gamma 1 = 0)
+    if (P.identity) {
+        launch_scale_copy(P.npk * P.ni, P.W, P.t_img, 1.0f, s);
+    } else {
+        launch_scale_by_vec(P.ni, P.npk, P.W, P.gammaA, P.sino_tmp, s);
+        backproject(P, P.sino_tmp, P.t_img, P.npk, s);
+    }
+    launch_block_invsqrt(P.nj, P.K, P.t_img, P.M0, -0.5, kM0Floor, nullptr, 0.0, P.flags + 1, s);
+    P.m0_built = 1;
+}
+
+void finish_filter(Problem& P, const float* blocks, float* out, double eps, hipStream_t s) {
+    double* lmax = P.scal + S_LMAX;
+    launch_fill_double(1, lmax, -1e300, s);
+    launch_block_lmax(P.nj, P.K, blocks, lmax, s);
+    launch_block_invsqrt(P.nj, P.K, blocks, out, -1.0, 0.0, lmax, eps, P.flags + 2, s);
+}
+
+void build_fourier(Problem& P, hipStream_t s) {
+    MBMD_REQUIRE(P.spec != nullptr, MBMD_ERR_SHAPE, "the Fourier preconditioner needs power-of-two image sizes");
+    const int jy = P.ny / 2, jx = P.nx / 2;
+    float* blocks = P.t_img;                                // [npk][nj], zeroed
+    launch_fill(P.npk * P.nj, blocks, 0.0f, s);
+    for (int k = 0; k < P.K; ++k) {
+        launch_fill(P.K * P.nj, P.t2_img, 0.0f, s);
+        launch_fill(1, P.t2_img + (size_t)k * P.nj + (size_t)jy * P.nx + jx, 1.0f, s);
+        hessian_apply(P, P.t2_img, P.g_img, P.M0, s);       // r_k = M0 H M0 delta_k
+        launch_fft2_forward(P.K, P.nx, P.ny, P.g_img, nullptr, jy, jx, P.spec, P.tw_x, P.tw_y, s);
+        launch_spectrum_real_to_blocks(P.K, P.nj, k, P.spec, blocks, s);
+    }
+    finish_filter(P, blocks, P.Linv, kEpsFourier, s);
+}
+
+void build_haar(Problem& P, hipStream_t s) {
+    MBMD_REQUIRE(P.coef != nullptr, MBMD_ERR_SHAPE, "the Haar preconditioner needs a square power-of-two image");
+    const int n = P.nx;
+    // Delta x = U^T 1 (one material), kept in d_img
+    launch_fill(P.nj, P.coef, 1.0f, s);
+    launch_haar_inverse(1, n, P.coef, P.coarse, nullptr, P.d_img, 1.0f, s);
+    float* blocks = P.t_img;
+    launch_fill(P.npk * P.nj, blocks, 0.0f, s);
+    for (int k = 0; k < P.K; ++k) {
+        launch_fill(P.K * P.nj, P.t2_img, 0.0f, s);
+        launch_scale_copy(P.nj, P.d_img, P.t2_img + (size_t)k * P.nj, 1.0f, s);
+        hessian_apply(P, P.t2_img, P.g_img, P.M0, s);
+        launch_haar_forward(P.K, n, P.g_img, nullptr, P.coef, P.coarse, s);
+        launch_coef_blocks(P.K, n, k, P.coef, blocks, s);
+    }
+    finish_filter(P, blocks, P.Kinv, kEpsHaar, s);
+}
+
+// out = sign * M M^T g, with partials of g.out into `partials` when non-NULL.
+int apply_direction(Problem& P, int kind, const float* g, float* out, float sign, double* partials,
+                    hipStream_t s) {
+    switch (kind) {
+        case MBMD_PRECOND_BLOCKDIAG:
+            launch_block_apply(P.nj, P.K, P.M0, g, P.t2_img, 1.0f, s);
+            launch_block_apply(P.nj, P.K, P.M0, P.t2_img, out, sign, s);
+            return partials ? launch_dot(P.K * P.nj, g, out, partials, s) : 0;
+        case MBMD_PRECOND_FOURIER:
+            return launch_fourier_apply(P.K, P.nx, P.ny, g, P.M0, P.Linv, P.spec, P.tw_x, P.tw_y, out, sign, g,
+                                        partials, s);
+        case MBMD_PRECOND_HAAR:
+            return launch_haar_apply(P.K, P.nx, g, P.M0, P.Kinv, P.coef, P.coarse, out, sign, g, partials, s);
+        default:
+            launch_scale_copy(P.K * P.nj, g, out, sign, s);
+            return partials ? launch_dot(P.K * P.nj, g, out, partials, s) : 0;
+    }
+}
+
+bool single_energy(const Problem& P) { return P.E == 1 && P.C == 1; }
+
+void ensure_dL_const(Problem& P, hipStream_t s) {
+    if (P.dL_valid || !single_energy(P)) return;
+    // c does not depend on x for one energy: evaluate at any line integrals
+    launch_fill(P.K * P.ni, P.l, 0.0f, s);
+    launch_ray_grad(ray_args(P), P.l, P.u, P.v, nullptr, nullptr, s);
+    backproject(P, P.v, P.dL_const, P.K, s);
+    P.dL_valid = 1;
+}
+
+// Phi(x) into *slot (device), recomputing A x.
+void objective_at(Problem& P, const float* x, double* slot, hipStream_t s) {
+    int counts[kRegions] = {0};
+    project(P, x, P.l, P.K, s);
+    counts[R_PHI_L] = launch_ray_grad(ray_args(P), P.l, P.u, nullptr, nullptr, region(P, R_PHI_L), s);
+    counts[R_PHI_R] = launch_penalty_grad(pen_args(P), x, P.t2_img, nullptr, P.t2_img, nullptr,
+                                          region(P, R_PHI_R), s);
+    launch_reduce_final(P.partials, counts, P.scal, slot, 0, P.flags, s);
+}
+
+// One plain SPS iteration: x <- x - (g + dR)/(d + d_R).
+void plain_iteration(Problem& P, float* x, double* trace_slot, hipStream_t s) {
+    int counts[kRegions] = {0};
+    const bool cconst = single_energy(P);
+    project(P, x, P.l, P.K, s);
+    counts[R_PHI_L] = launch_ray_grad(ray_args(P), P.l, P.u, cconst ? nullptr : P.v, nullptr,
+                                      region(P, R_PHI_L), s);
+    backproject(P, P.u, P.g_img, cconst ? P.K : 2 * P.K, s);
+    counts[R_PHI_R] = launch_penalty_grad(pen_args(P), x, P.g_img, cconst ? P.dL_const : P.d_img, P.g_img,
+                                          P.d_img, region(P, R_PHI_R), s);
+    launch_plain_update(P.K * P.nj, x, P.g_img, P.d_img, s);
+    launch_reduce_final(P.partials, counts, P.scal, trace_slot, 0, P.flags, s);
+}
+
+// One preconditioned iteration (l = A x must be current on entry and is kept current).
+void precond_iteration(Problem& P, float* x, int kind, double* trace_slot, hipStream_t s) {
+    int counts[kRegions] = {0};
+    counts[R_PHI_L] = launch_ray_grad(ray_args(P), P.l, P.u, nullptr, P.r, region(P, R_PHI_L), s);
+    backproject(P, P.u, P.g_img, P.K, s);
+    counts[R_PHI_R] = launch_penalty_grad(pen_args(P), x, P.g_img, nullptr, P.g_img, nullptr,
+                                          region(P, R_PHI_R), s);
+    counts[R_GP] = apply_direction(P, kind, P.g_img, P.p_img, -1.0f, region(P, R_GP), s);
+    project(P, P.p_img, P.q, P.K, s);
+    counts[R_CQ2] = launch_ray_curv(ray_args(P), P.l, P.r, P.q, region(P, R_CQ2), s);
+    if (P.has_penalty) counts[R_PRP] = launch_penalty_quadform(pen_args(P), x, P.p_img, region(P, R_PRP), s);
+    launch_reduce_final(P.partials, counts, P.scal, trace_slot, 1, P.flags, s);
+    launch_axpy_alpha(P.K * P.nj, x, P.p_img, P.scal + S_ALPHA, s);
+    launch_axpy_alpha(P.K * P.ni, P.l, P.q, P.scal + S_ALPHA, s);
+}
+
+void check_precond_ready(Problem& P, int precond) {
+    MBMD_REQUIRE(precond >= 0 && precond <= 3, MBMD_ERR_ARG, "unknown preconditioner");
+    if (P.identity) {
+        MBMD_REQUIRE(!P.has_penalty, MBMD_ERR_UNSUPPORTED,
+                     "identity geometry iterations need a zero penalty (the problem separates by ray)");
+        MBMD_REQUIRE(precond == MBMD_PRECOND_NONE || precond == MBMD_PRECOND_BLOCKDIAG, MBMD_ERR_UNSUPPORTED,
+                     "identity geometry supports the plain and block-diagonal iterations");
+    }
+    if (precond != MBMD_PRECOND_NONE) MBMD_REQUIRE(P.built[precond], MBMD_ERR_NOT_BUILT, "preconditioner not built");
+}
+
+void read_flags(Problem& P, hipStream_t s) {
+    int f[4];
+    MBMD_HIP(hipMemcpyAsync(f, P.flags, sizeof(f), hipMemcpyDeviceToHost, s));
+    MBMD_HIP(hipStreamSynchronize(s));
+    if (f[0]) {
+        launch_fill(1, reinterpret_cast<float*>(P.flags), 0.0f, s);
+        MBMD_HIP(hipStreamSynchronize(s));
+        throw Error{MBMD_ERR_NUMERIC, "non-finite objective or step size"};
+    }
+}
+
+void identity_iterate(Problem& P, float* x, int precond, int n_iter, double* trace_host, hipStream_t s) {
+    const int nb = (P.ni + 255) / 256;
+    const int total_slots = kRegions * kMaxPartials;
+    const int chunk_max = total_slots / nb - 1;
+    MBMD_REQUIRE(chunk_max >= 1, MBMD_ERR_SHAPE, "too many rays for the partial-sum buffer");
+    int done = 0;
+    do {
+        const int n = std::min(chunk_max, n_iter - done);
+        launch_identity_iterate(ray_args(P), x, P.M0, precond, n, P.partials, nb, s);
+        if (trace_host) {
+            for (int it = 0; it <= n; ++it) {
+                if (it == n && done + n < n_iter) break;      // next chunk starts from this point
+                int counts[kRegions] = {0};
+                counts[R_PHI_L] = nb;
+                launch_reduce_final(P.partials + (size_t)it * nb, counts, P.scal, P.trace + it, 0, P.flags, s);
+            }
+            const int nvals = (done + n < n_iter) ? n : n + 1;
+            MBMD_HIP(hipMemcpyAsync(trace_host + done, P.trace, sizeof(double) * nvals, hipMemcpyDeviceToHost, s));
+            MBMD_HIP(hipStreamSynchronize(s));
+        }
+        done += n;
+    } while (done < n_iter);
+}
+
+void sps_run(Problem& P, float* x, int precond, int n_iter, double* trace_host, hipStream_t s) {
+    check_precond_ready(P, precond);
+    P.last_stream = s;
+    if (P.identity) {
+        identity_iterate(P, x, precond, n_iter, trace_host, s);
+        if (trace_host) read_flags(P, s);
+        return;
+    }
+    if (precond == MBMD_PRECOND_NONE) ensure_dL_const(P, s);
+    int base = 0;   // trace index of slot 0 of the device trace buffer
+    for (int n = 0; n < n_iter; ++n) {
+        if (trace_host && n - base == P.trace_cap) {
+            MBMD_HIP(hipMemcpyAsync(trace_host + base, P.trace, sizeof(double) * P.trace_cap,
+                                    hipMemcpyDeviceToHost, s));
+            MBMD_HIP(hipStreamSynchronize(s));
+            base = n;
+        }
+        double* slot = trace_host ? P.trace + (n - base) : nullptr;
+        if (precond == MBMD_PRECOND_NONE) {
+            plain_iteration(P, x, slot, s);
+        } else {
+            if (n % kRefreshEvery == 0) project(P, x, P.l, P.K, s);
+            precond_iteration(P, x, precond, slot, s);
+        }
+    }
+    if (trace_host) {
+        if (n_iter - base == P.trace_cap) {
+            MBMD_HIP(hipMemcpyAsync(trace_host + base, P.trace, sizeof(double) * P.trace_cap,
+                                    hipMemcpyDeviceToHost, s));
+            MBMD_HIP(hipStreamSynchronize(s));
+            base = n_iter;
+        }
+        objective_at(P, x, P.trace + (n_iter - base), s);
+        MBMD_HIP(hipMemcpyAsync(trace_host + base, P.trace, sizeof(double) * (n_iter - base + 1),
+                                hipMemcpyDeviceToHost, s));
+        read_flags(P, s);
+    }
+}
+
+}  // namespace
+}  // namespace mbmd
+
+using namespace mbmd;
+
+extern "C" {
+
+int mbmd_version(void) { return 1; }
+
+const char* mbmd_last_error(void) { return g_last_error.c_str(); }
+
+const char* mbmd_status_string(int status) {
+    switch (status) {
+        case MBMD_OK: return "ok";
+        case MBMD_ERR_ARG: return "invalid argument";
+        case MBMD_ERR_SHAPE: return "unsupported shape";
+        case MBMD_ERR_HIP: return "HIP runtime error";
+        case MBMD_ERR_NOT_BUILT: return "preconditioner not built";
+        case MBMD_ERR_NUMERIC: return "non-finite objective or step";
+        case MBMD_ERR_UNSUPPORTED: return "unsupported option";
+        default: return "unknown status";
+    }
+}
+
+int mbmd_project(const mbmd_geometry* geom, const float* x_dev, float* sino_dev, int n_mat, void* stream) {
+    return guarded([&] {
+        MBMD_REQUIRE(geom && x_dev && sino_dev, MBMD_ERR_ARG, "NULL argument");
+        validate_geometry(*geom);
+        MBMD_REQUIRE(n_mat >= 1 && n_mat <= kMaxMat, MBMD_ERR_SHAPE, "n_mat must be in 1..4");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (geom->kind == MBMD_GEOM_IDENTITY) {
+            MBMD_HIP(hipMemcpyAsync(sino_dev, x_dev, sizeof(float) * (size_t)n_mat * geom->nx * geom->ny,
+                                    hipMemcpyDeviceToDevice, s));
+            return;
+        }
+        launch_project(cached_geometry(*geom, kMaxMat), x_dev, sino_dev, n_mat, s);
+    });
+}
+
+int mbmd_backproject(const mbmd_geometry* geom, const float* sino_dev, float* x_dev, int n_ch, void* stream) {
+    return guarded([&] {
+        MBMD_REQUIRE(geom && x_dev && sino_dev, MBMD_ERR_ARG, "NULL argument");
+        validate_geometry(*geom);
+        MBMD_REQUIRE(n_ch >= 1 && n_ch <= kMaxBackCh, MBMD_ERR_SHAPE, "n_ch must be in 1..10");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (geom->kind == MBMD_GEOM_IDENTITY) {
+            MBMD_HIP(hipMemcpyAsync(x_dev, sino_dev, sizeof(float) * (size_t)n_ch * geom->nx * geom->ny,
+                                    hipMemcpyDeviceToDevice, s));
+            return;
+        }
+        launch_backproject(cached_geometry(*geom, kMaxMat), sino_dev, x_dev, n_ch, s);
+    });
+}
+
+int mbmd_problem_create(const mbmd_geometry* geom, const mbmd_spectral* sp, const mbmd_penalty* pen,
+                        const float* y_dev, const float* w_dev, void* stream, mbmd_problem** out) {
+    return guarded([&] {
+        MBMD_REQUIRE(geom && sp && pen && y_dev && out, MBMD_ERR_ARG, "NULL argument");
+        *out = nullptr;
+        validate_geometry(*geom);
+        MBMD_REQUIRE(sp->n_mat >= 1 && sp->n_mat <= kMaxMat && sp->n_chan >= 1 && sp->n_chan <= kMaxChan &&
+                         sp->n_energy >= 1 && sp->n_energy <= kMaxEnergy,
+                     MBMD_ERR_SHAPE, "spectral sizes out of range (n_mat<=4, n_chan<=8, n_energy<=256)");
+        MBMD_REQUIRE(sp->Q_host && sp->S_host, MBMD_ERR_ARG, "NULL spectral table");
+        MBMD_REQUIRE(pen->kind == MBMD_PENALTY_QUADRATIC || pen->kind == MBMD_PENALTY_HUBER, MBMD_ERR_ARG,
+                     "unknown penalty kind");
+        std::unique_ptr<mbmd_problem> P(new mbmd_problem());
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        P->g = *geom;
+        P->identity = geom->kind == MBMD_GEOM_IDENTITY;
+        P->K = sp->n_mat;
+        P->E = sp->n_energy;
+        P->C = sp->n_chan;
+        P->npk = P->K * (P->K + 1) / 2;
+        P->nx = geom->nx;
+        P->ny = geom->ny;
+        P->V = geom->n_views;
+        P->B = geom->n_bins;
+        P->nj = geom->nx * geom->ny;
+        P->ni = geom->n_views * geom->n_bins;
+        P->pen_kind = pen->kind;
+        P->delta = pen->delta;
+        for (int i = 0; i < P->K * P->K; ++i) P->beta[i] = pen->beta_host ? pen->beta_host[i] : 0.0;
+        for (int i = 0; i < P->K; ++i)
+            for (int j = 0; j < P->K; ++j)
+                MBMD_REQUIRE(P->beta[i * P->K + j] == P->beta[j * P->K + i], MBMD_ERR_ARG, "beta must be symmetric");
+        for (int i = 0; i < P->K * P->K; ++i) P->has_penalty |= P->beta[i] != 0.0;
+        if (pen->kind == MBMD_PENALTY_HUBER)
+            MBMD_REQUIRE(P->K == 1 && pen->delta > 0.0, MBMD_ERR_ARG, "Huber needs one material and delta > 0");
+        MBMD_REQUIRE(P->ni <= 256 * kMaxPartials && P->nj <= 256 * kMaxPartials, MBMD_ERR_SHAPE,
+                     "problem too large for the partial-sum buffer");
+        if (!P->identity) {
+            P->geom = new GeomTables();
+            build_geometry(*geom, *P->geom, P->K);
+        }
+        carve(*P);                                // sizing pass
+        P->arena.reserve(P->arena.used + 4096);
+        carve(*P);
+        // spectral model
+        const int K = P->K, E = P->E, C = P->C;
+        std::vector<float> Qf(E * K), Sf(C * E), rowS(C, 0.0f), Qsum(E, 0.0f), bf(K * K);
+        for (int e = 0; e < E; ++e)
+            for (int k = 0; k < K; ++k) {
+                Qf[e * K + k] = (float)sp->Q_host[e * K + k];
+                Qsum[e] += (float)sp->Q_host[e * K + k];
+            }
+        for (int c = 0; c < C; ++c) {
+            double rs = 0.0;
+            for (int e = 0; e < E; ++e) {
+                Sf[c * E + e] = (float)sp->S_host[c * E + e];
+                rs += sp->S_host[c * E + e];
+            }
+            rowS[c] = (float)rs;
+        }
+        for (int i = 0; i < K * K; ++i) bf[i] = (float)P->beta[i];
+        MBMD_HIP(hipMemcpyAsync(P->Q, Qf.data(), sizeof(float) * Qf.size(), hipMemcpyHostToDevice, s));
+        MBMD_HIP(hipMemcpyAsync(P->S, Sf.data(), sizeof(float) * Sf.size(), hipMemcpyHostToDevice, s));
+        MBMD_HIP(hipMemcpyAsync(P->rowS, rowS.data(), sizeof(float) * C, hipMemcpyHostToDevice, s));
+        MBMD_HIP(hipMemcpyAsync(P->Qsum, Qsum.data(), sizeof(float) * E, hipMemcpyHostToDevice, s));
+        MBMD_HIP(hipMemcpyAsync(P->beta_d, bf.data(), sizeof(float) * K * K, hipMemcpyHostToDevice, s));
+        MBMD_HIP(hipMemcpyAsync(P->y, y_dev, sizeof(float) * (size_t)C * P->ni, hipMemcpyDeviceToDevice, s));
+        if (w_dev)
+            MBMD_HIP(hipMemcpyAsync(P->w, w_dev, sizeof(float) * (size_t)C * P->ni, hipMemcpyDeviceToDevice, s));
+        else
+            launch_inv_var(C * P->ni, P->y, P->w, s);
+        launch_fill(4, reinterpret_cast<float*>(P->flags), 0.0f, s);
+        if (P->identity) {
+            launch_fill(P->ni, P->gammaA, 1.0f, s);
+        } else {
+            launch_fill(P->nj, P->t_img, 1.0f, s);
+            launch_project(*P->geom, P->t_img, P->gammaA, 1, s);
+        }
+        if (P->tw_x) {
+            fill_twiddles(P->tw_x, P->nx, s);
+            fill_twiddles(P->tw_y, P->ny, s);
+        }
+        MBMD_HIP(hipStreamSynchronize(s));
+        P->last_stream = s;
+        *out = P.release();
+    });
+}
+
+void mbmd_problem_destroy(mbmd_problem* prob) {
+    if (!prob) return;
+    (void)hipStreamSynchronize(prob->last_stream);
+    prob->arena.release();
+    if (prob->geom) {
+        free_geometry(*prob->geom);
+        delete prob->geom;
+    }
+    delete prob;
+}
+
+int mbmd_precond_build(mbmd_problem* prob, int kind, void* stream) {
+    return guarded([&] {
+        MBMD_REQUIRE(prob, MBMD_ERR_ARG, "NULL problem");
+        MBMD_REQUIRE(kind >= 0 && kind <= 3, MBMD_ERR_ARG, "unknown preconditioner");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        prob->last_stream = s;
+        if (kind == MBMD_PRECOND_NONE) return;
+        if (prob->identity)
+            MBMD_REQUIRE(kind == MBMD_PRECOND_BLOCKDIAG, MBMD_ERR_UNSUPPORTED,
+                         "identity geometry supports the block-diagonal preconditioner only");
+        if (kind == MBMD_PRECOND_FOURIER)
+            MBMD_REQUIRE(prob->spec != nullptr, MBMD_ERR_SHAPE, "the Fourier preconditioner needs power-of-two sizes");
+        if (kind == MBMD_PRECOND_HAAR)
+            MBMD_REQUIRE(prob->coef != nullptr, MBMD_ERR_SHAPE, "the Haar preconditioner needs a square power-of-two image");
+        ensure_fisher_m0(*prob, s);
+        if (kind == MBMD_PRECOND_FOURIER) build_fourier(*prob, s);
+        if (kind == MBMD_PRECOND_HAAR) build_haar(*prob, s);
+        prob->built[kind] = 1;
+    });
+}
+
+int mbmd_precond_apply(mbmd_problem* prob, int kind, const float* g_dev, float* out_dev, void* stream) {
+    return guarded([&] {
+        MBMD_REQUIRE(prob && g_dev && out_dev && g_dev != out_dev, MBMD_ERR_ARG, "bad argument");
+        MBMD_REQUIRE(kind >= 0 && kind <= 3, MBMD_ERR_ARG, "unknown preconditioner");
+        if (kind != MBMD_PRECOND_NONE) MBMD_REQUIRE(prob->built[kind], MBMD_ERR_NOT_BUILT, "preconditioner not built");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        prob->last_stream = s;
+        apply_direction(*prob, kind, g_dev, out_dev, 1.0f, nullptr, s);
+    });
+}
+
+int mbmd_gradient(mbmd_problem* prob, const float* x_dev, float* grad_dev, float* curv_dev, double* objective_host,
+                  void* stream) {
+    return guarded([&] {
+        MBMD_REQUIRE(prob && x_dev && grad_dev, MBMD_ERR_ARG, "NULL argument");
+        Problem& P = *prob;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        P.last_stream = s;
+        int counts[kRegions] = {0};
+        project(P, x_dev, P.l, P.K, s);
+        counts[R_PHI_L] = launch_ray_grad(ray_args(P), P.l, P.u, curv_dev ? P.v : nullptr, nullptr,
+                                          region(P, R_PHI_L), s);
+        backproject(P, P.u, P.g_img, curv_dev ? 2 * P.K : P.K, s);
+        counts[R_PHI_R] = launch_penalty_grad(pen_args(P), x_dev, P.g_img, curv_dev ? P.d_img : nullptr, grad_dev,
+                                              curv_dev, region(P, R_PHI_R), s);
+        if (objective_host) {
+            launch_reduce_final(P.partials, counts, P.scal, nullptr, 0, P.flags, s);
+            MBMD_HIP(hipMemcpyAsync(objective_host, P.scal + S_PHI, sizeof(double), hipMemcpyDeviceToHost, s));
+            MBMD_HIP(hipStreamSynchronize(s));
+        }
+    });
+}
+
+int mbmd_sps_step(mbmd_problem* prob, float* x_dev, int precond, int n_iter, double* trace_host, void* stream) {
+    return guarded([&] {
+        MBMD_REQUIRE(prob && x_dev && n_iter >= 0, MBMD_ERR_ARG, "bad argument");
+        sps_run(*prob, x_dev, precond, n_iter, trace_host, static_cast<hipStream_t>(stream));
+    });
+}
+
+int mbmd_forward(mbmd_problem* prob, const float* x_dev, float* ybar_dev, float* l_dev, void* stream) {
+    return guarded([&] {
+        MBMD_REQUIRE(prob && x_dev && ybar_dev, MBMD_ERR_ARG, "NULL argument");
+        Problem& P = *prob;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        P.last_stream = s;
+        float* l = l_dev ? l_dev : P.l;
+        project(P, x_dev, l, P.K, s);
+        launch_forward_model(ray_args(P), l, ybar_dev, s);
+    });
+}
+
+int mbmd_forward_vjp(mbmd_problem* prob, const float* l_dev, const float* gbar_dev, float* dx_dev, void* stream) {
+    return guarded([&] {
+        MBMD_REQUIRE(prob && l_dev && gbar_dev && dx_dev, MBMD_ERR_ARG, "NULL argument");
+        Problem& P = *prob;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        P.last_stream = s;
+        launch_forward_vjp(ray_args(P), l_dev, gbar_dev, P.u, s);
+        backproject(P, P.u, dx_dev, P.K, s);
+    });
+}
+
+int mbmd_batch_create(mbmd_problem* const* probs, int n, mbmd_batch** out) {
+    return guarded([&] {
+        MBMD_REQUIRE(probs && n > 0 && out, MBMD_ERR_ARG, "bad argument");
+        std::unique_ptr<mbmd_batch> b(new mbmd_batch());
+        for (int i = 0; i < n; ++i) {
+            MBMD_REQUIRE(probs[i] != nullptr, MBMD_ERR_ARG, "NULL problem in batch");
+            MBMD_REQUIRE(!probs[i]->identity, MBMD_ERR_UNSUPPORTED, "batches hold projector geometries");
+            b->probs.push_back(probs[i]);
+        }
+        *out = b.release();
+    });
+}
+
+void mbmd_batch_destroy(mbmd_batch* b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    for (int i = 0; i < 2; ++i) {
+        if (b->exec[i]) (void)hipGraphExecDestroy(b->exec[i]);
+        if (b->graph[i]) (void)hipGraphDestroy(b->graph[i]);
+    }
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    delete b;
+}
+
+int mbmd_batch_sps_step(mbmd_batch* b, float* const* x_dev, int precond, int n_iter, int use_graph, void* stream) {
+    return guarded([&] {
+        MBMD_REQUIRE(b && x_dev && n_iter >= 0, MBMD_ERR_ARG, "bad argument");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const size_t n = b->probs.size();
+        for (size_t i = 0; i < n; ++i) {
+            MBMD_REQUIRE(x_dev[i] != nullptr, MBMD_ERR_ARG, "NULL image in batch");
+            check_precond_ready(*b->probs[i], precond);
+            b->probs[i]->last_stream = s;
+            if (precond == MBMD_PRECOND_NONE) ensure_dL_const(*b->probs[i], s);
+        }
+        auto enqueue = [&](bool refresh) {
+            for (size_t i = 0; i < n; ++i) {
+                Problem& P = *b->probs[i];
+                if (precond == MBMD_PRECOND_NONE) {
+                    plain_iteration(P, x_dev[i], nullptr, s);
+                } else {
+                    if (refresh) project(P, x_dev[i], P.l, P.K, s);
+                    precond_iteration(P, x_dev[i], precond, nullptr, s);
+                }
+            }
+        };
+        if (!use_graph) {
+            for (int it = 0; it < n_iter; ++it) enqueue(it % kRefreshEvery == 0);
+            return;
+        }
+        // Capture on a library-owned stream (the legacy default stream cannot be
+        // captured); the instantiated graphs are then launched on the caller's stream.
+        bool same = b->captured && b->precond == precond && b->xs.size() == n;
+        for (size_t i = 0; same && i < n; ++i) same = b->xs[i] == x_dev[i];
+        if (!same) {
+            for (int i = 0; i < 2; ++i) {
+                if (b->exec[i]) (void)hipGraphExecDestroy(b->exec[i]);
+                if (b->graph[i]) (void)hipGraphDestroy(b->graph[i]);
+                b->exec[i] = nullptr;
+                b->graph[i] = nullptr;
+            }
+            b->captured = false;
+            if (!b->capture) MBMD_HIP(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
+            MBMD_HIP(hipStreamSynchronize(s));   // set-up launches above must not be captured out of order
+            hipStream_t cs = b->capture;
+            for (int i = 0; i < 2; ++i) {
+                MBMD_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+                try {
+                    for (size_t k = 0; k < n; ++k) {
+                        Problem& P = *b->probs[k];
+                        if (precond == MBMD_PRECOND_NONE) {
+                            plain_iteration(P, x_dev[k], nullptr, cs);
+                        } else {
+                            if (i == 1) project(P, x_dev[k], P.l, P.K, cs);
+                            precond_iteration(P, x_dev[k], precond, nullptr, cs);
+                        }
+                    }
+                } catch (...) {
+                    hipGraph_t g = nullptr;
+                    (void)hipStreamEndCapture(cs, &g);
+                    if (g) (void)hipGraphDestroy(g);
+                    (void)hipGetLastError();
+                    throw;
+                }
+                MBMD_HIP(hipStreamEndCapture(cs, &b->graph[i]));
+                MBMD_HIP(hipGraphInstantiate(&b->exec[i], b->graph[i], nullptr, nullptr, 0));
+            }
+            b->captured = true;
+            b->precond = precond;
+            b->xs.assign(x_dev, x_dev + n);
+        }
+        b->stream = s;
+        for (int it = 0; it < n_iter; ++it) {
+            const bool refresh = precond != MBMD_PRECOND_NONE && it % kRefreshEvery == 0;
+            MBMD_HIP(hipGraphLaunch(b->exec[refresh ? 1 : 0], s));
+        }
+    });
+}
+
+}  // extern "C"

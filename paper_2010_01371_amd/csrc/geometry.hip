@@ -1,0 +1,193 @@
+// Host-side (FP64) construction of the distance-driven projector tables.
+//
+// For each view the library stores, in FP32 for the kernels:
+//   * the sweep frame (rows when |cos theta| >= |sin theta|, else columns),
+//     decided here in FP64;
+//   * for every bin boundary b' = 0..B, the along-line position of the
+//     boundary ray on sweep line q as C0 + C1 (q - (Nq-1)/2), in pixel units
+//     centred on the image (intersections of a straight line with a family of
+//     parallel lines are affine in the line index);
+//   * for every bin, the path length per sweep line of the bin-centre ray,
+//     line spacing / |cos(angle to the line normal)|;
+//   * the rational map from a point (K, q) back to its fractional bin index,
+//     used by the pixel-driven back projector to find the bins a pixel sees.
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "internal.h"
+
+namespace mbmd {
+
+void validate_geometry(const mbmd_geometry& g) {
+    MBMD_REQUIRE(g.kind >= 0 && g.kind <= 2, MBMD_ERR_ARG, "geometry kind must be 0, 1 or 2");
+    MBMD_REQUIRE(g.nx > 0 && g.ny > 0 && g.n_views > 0 && g.n_bins > 0, MBMD_ERR_ARG,
+                 "geometry sizes must be positive");
+    if (g.kind == MBMD_GEOM_IDENTITY) {
+        MBMD_REQUIRE(g.nx == g.n_bins && g.ny == g.n_views, MBMD_ERR_SHAPE,
+                     "identity geometry needs nx == n_bins and ny == n_views");
+        return;
+    }
+    MBMD_REQUIRE(g.nx <= 8192 && g.ny <= 8192 && g.n_bins <= 65536 && g.n_views <= 65536,
+                 MBMD_ERR_SHAPE, "geometry too large");
+    MBMD_REQUIRE(g.dx > 0 && g.dy > 0 && g.du > 0, MBMD_ERR_ARG, "pixel and bin sizes must be positive");
+    if (g.kind == MBMD_GEOM_FAN_FLAT) {
+        const double r = 0.5 * std::hypot(g.nx * g.dx, g.ny * g.dy);
+        MBMD_REQUIRE(g.dso > r * 1.0001 && g.dsd > 0, MBMD_ERR_SHAPE,
+                     "fan beam: the source must lie outside the image's circumscribed circle");
+    }
+}
+
+namespace {
+
+struct Ray {
+    double px, py, rx, ry;
+};
+
+Ray boundary_ray(const mbmd_geometry& g, double c, double s, double u) {
+    const double ex = c, ey = s, dxv = -s, dyv = c;
+    if (g.kind == MBMD_GEOM_PARALLEL) return {u * ex, u * ey, dxv, dyv};
+    const double sx = -g.dso * dxv, sy = -g.dso * dyv;
+    const double tx = (g.dsd - g.dso) * dxv + u * ex, ty = (g.dsd - g.dso) * dyv + u * ey;
+    return {sx, sy, tx - sx, ty - sy};
+}
+
+}  // namespace
+
+void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat) {
+    validate_geometry(g);
+    MBMD_REQUIRE(g.kind != MBMD_GEOM_IDENTITY, MBMD_ERR_ARG, "identity geometry has no projector tables");
+    t.g = g;
+    t.V = g.n_views;
+    t.B = g.n_bins;
+    t.nx = g.nx;
+    t.ny = g.ny;
+    const int V = t.V, B = t.B;
+    std::vector<ViewParams> vp(V);
+    std::vector<float2> bound((size_t)V * (B + 1));
+    std::vector<float> path((size_t)V * B);
+    std::vector<int> views[2];
+
+    for (int v = 0; v < V; ++v) {
+        const double th = g.theta0 + v * g.dtheta;
+        const double c = std::cos(th), s = std::sin(th);
+        const int frame = std::fabs(c) >= std::fabs(s) ? 0 : 1;
+        views[frame].push_back(v);
+        const int ia = frame == 0 ? 1 : 0;        // line-normal axis (y for row sweeps)
+        const int it = frame == 0 ? 0 : 1;        // along-line axis
+        const int Nq = frame == 0 ? g.ny : g.nx;
+        const double dq = frame == 0 ? g.dy : g.dx;
+        const double dp = frame == 0 ? g.dx : g.dy;
+        const double qc = 0.5 * (Nq - 1);
+        (void)qc;
+        for (int bb = 0; bb <= B; ++bb) {
+            const double u = (bb - 0.5 * B) * g.du + g.u_offset;
+            const Ray r = boundary_ray(g, c, s, u);
+            const double P[2] = {r.px, r.py}, R[2] = {r.rx, r.ry};
+            const double rn = std::hypot(R[0], R[1]);
+            MBMD_REQUIRE(std::fabs(R[ia]) > 1e-9 * rn, MBMD_ERR_SHAPE,
+                         "a bin boundary ray runs parallel to its sweep lines (fan too wide)");
+            const double slope = R[it] / R[ia];
+            // along-line coordinate on the line at normal coordinate a = qq * dq:
+            //   t = P_t + (a - P_a) * slope
+            const double C0 = (P[it] - P[ia] * slope) / dp;
+            const double C1 = dq * slope / dp;
+            bound[(size_t)v * (B + 1) + bb] = make_float2((float)C0, (float)C1);
+        }
+        for (int b = 0; b < B; ++b) {
+            const double u = (b - 0.5 * (B - 1)) * g.du + g.u_offset;
+            const Ray r = boundary_ray(g, c, s, u);
+            const double R[2] = {r.rx, r.ry};
+            path[(size_t)v * B + b] = (float)(dq * std::hypot(R[0], R[1]) / std::fabs(R[ia]));
+        }
+        // fractional bin index of the point at along position K (pixels, centred)
+        // on line qq: world point with along coordinate K dp and normal qq dq.
+        const double e[2] = {c, s}, d[2] = {-s, c};
+        const double u0 = -0.5 * B * g.du + g.u_offset;     // left edge of bin 0
+        ViewParams p{};
+        if (g.kind == MBMD_GEOM_PARALLEL) {
+            p.n0 = (float)(-u0 / g.du);
+            p.nK = (float)(e[it] * dp / g.du);
+            p.nq = (float)(e[ia] * dq / g.du);
+            p.d0 = 1.0f;
+            p.dK = 0.0f;
+            p.dq = 0.0f;
+        } else {
+            // u = dsd (e.X) / (d.X + dso);  beta = (u - u0) / du
+            p.n0 = (float)(-u0 * g.dso);
+            p.nK = (float)((g.dsd * e[it] - u0 * d[it]) * dp);
+            p.nq = (float)((g.dsd * e[ia] - u0 * d[ia]) * dq);
+            p.d0 = (float)(g.du * g.dso);
+            p.dK = (float)(g.du * d[it] * dp);
+            p.dq = (float)(g.du * d[ia] * dq);
+        }
+        p.frame = frame;
+        vp[v] = p;
+    }
+    t.n_frame_views[0] = (int)views[0].size();
+    t.n_frame_views[1] = (int)views[1].size();
+    std::vector<int> fv(views[0]);
+    fv.insert(fv.end(), views[1].begin(), views[1].end());
+
+    const size_t nj = (size_t)g.nx * g.ny;
+    t.prefix_mat = prefix_mat;
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t b_view = al(sizeof(ViewParams) * V), b_bound = al(sizeof(float2) * bound.size()),
+                 b_path = al(sizeof(float) * path.size()), b_fv = al(sizeof(int) * V),
+                 b_pre = al(sizeof(float2) * nj * 2 * prefix_mat);
+    char* base = nullptr;
+    MBMD_HIP(hipGetDevice(&t.device));
+    MBMD_HIP(hipMalloc(&base, b_view + b_bound + b_path + b_fv + b_pre));
+    t.mem = base;
+    t.view = reinterpret_cast<ViewParams*>(base);
+    t.bound = reinterpret_cast<float2*>(base + b_view);
+    t.path = reinterpret_cast<float*>(base + b_view + b_bound);
+    t.frame_views = reinterpret_cast<int*>(base + b_view + b_bound + b_path);
+    t.prefix = prefix_mat ? reinterpret_cast<float2*>(base + b_view + b_bound + b_path + b_fv) : nullptr;
+    MBMD_HIP(hipMemcpy(t.view, vp.data(), sizeof(ViewParams) * V, hipMemcpyHostToDevice));
+    MBMD_HIP(hipMemcpy(t.bound, bound.data(), sizeof(float2) * bound.size(), hipMemcpyHostToDevice));
+    MBMD_HIP(hipMemcpy(t.path, path.data(), sizeof(float) * path.size(), hipMemcpyHostToDevice));
+    MBMD_HIP(hipMemcpy(t.frame_views, fv.data(), sizeof(int) * V, hipMemcpyHostToDevice));
+}
+
+void free_geometry(GeomTables& t) {
+    if (t.mem) (void)hipFree(t.mem);
+    t.mem = nullptr;
+}
+
+namespace {
+std::mutex g_cache_mu;
+std::map<std::string, GeomTables*> g_cache;
+}
+
+GeomTables& cached_geometry(const mbmd_geometry& g, int prefix_mat) {
+    int dev = 0;
+    MBMD_HIP(hipGetDevice(&dev));
+    // key from the fields (the struct has padding bytes)
+    const double f[] = {(double)g.kind, (double)g.nx, (double)g.ny, g.dx, g.dy, (double)g.n_views,
+                        g.theta0, g.dtheta, (double)g.n_bins, g.du, g.u_offset, g.dso, g.dsd,
+                        (double)dev};
+    std::string key(reinterpret_cast<const char*>(f), sizeof(f));
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end() && it->second->prefix_mat >= prefix_mat) return *it->second;
+    if (it != g_cache.end()) {
+        // a larger prefix scratch is needed: rebuild (hipFree waits for the device)
+        free_geometry(*it->second);
+        delete it->second;
+        g_cache.erase(it);
+    }
+    GeomTables* t = new GeomTables();
+    try {
+        build_geometry(g, *t, prefix_mat < 1 ? 1 : prefix_mat);
+    } catch (...) {
+        delete t;
+        throw;
+    }
+    g_cache[key] = t;
+    return *t;
+}
+
+}  // namespace mbmd

@@ -1,0 +1,477 @@
+// Image-space kernels: roughness penalties, SPS updates, per-pixel material
+// blocks and the final FP64 reductions.
+//
+// Penalties (eq:quadraticSmoothess, quadReg_summation): Gamma is the
+// 4-neighbour graph Laplacian with out-of-image neighbours dropped;
+// R = 1/2 x^T (beta (x) Gamma) x, with separable SPS curvature
+// sum_k' |beta_kk'| 2 |N_j|.  Huber (one material): R = beta sum_pairs
+// psi(x_j - x_j'), gradient beta sum psi'(.), separable curvature
+// 2 beta sum omega(.) with omega(t) = psi'(t)/t (De Pierro split of Huber's
+// quadratic majoriser).  Each unordered pair is charged to its left / upper
+// pixel when a value is summed.
+//
+// Block operations: per-pixel (or per-frequency) symmetric N_k x N_k
+// matrices are stored packed, component-major ([npk][n]) so that loads
+// coalesce.  Inverse square roots use FP64 cyclic Jacobi (N_k <= 4).
+#include <cfloat>
+#include <cmath>
+
+#include "internal.h"
+
+namespace mbmd {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int i = 0; i < nw; ++i) t += sh[i];
+    }
+    return t;
+}
+
+__device__ __forceinline__ float huber_dpsi(float t, float d) { return fminf(fmaxf(t, -d), d); }
+__device__ __forceinline__ float huber_omega(float t, float d) {
+    const float a = fabsf(t);
+    return a <= d ? 1.0f : d / a;
+}
+__device__ __forceinline__ double huber_psi(double t, double d) {
+    const double a = fabs(t);
+    return a <= d ? 0.5 * t * t : d * a - 0.5 * d * d;
+}
+
+// g = gL + dR/dx, d = dL + d_R (d may be NULL), partials of R(x).
+// gL may alias g and dL may alias d (each element is read before it is written).
+__global__ __launch_bounds__(kThreads) void k_penalty_grad(PenaltyArgs a, const float* __restrict__ x,
+                                                           const float* gL, const float* dL, float* g, float* d,
+                                                           double* __restrict__ partials) {
+    __shared__ double sh[kThreads / 64];
+    const int nj = a.nx * a.ny;
+    const int j = blockIdx.x * kThreads + threadIdx.x;
+    double phi = 0.0;
+    if (j < nj) {
+        const int iy = j / a.nx, ix = j - iy * a.nx;
+        const bool L = ix > 0, R = ix + 1 < a.nx, U = iy > 0, D = iy + 1 < a.ny;
+        if (a.kind == MBMD_PENALTY_HUBER) {
+            const float xc = x[j];
+            float gr = 0.0f, om = 0.0f;
+            if (L) { const float t = xc - x[j - 1]; gr += huber_dpsi(t, a.delta); om += huber_omega(t, a.delta); }
+            if (R) { const float t = xc - x[j + 1]; gr += huber_dpsi(t, a.delta); om += huber_omega(t, a.delta);
+                     phi += huber_psi((double)t, (double)a.delta); }
+            if (U) { const float t = xc - x[j - a.nx]; gr += huber_dpsi(t, a.delta); om += huber_omega(t, a.delta); }
+            if (D) { const float t = xc - x[j + a.nx]; gr += huber_dpsi(t, a.delta); om += huber_omega(t, a.delta);
+                     phi += huber_psi((double)t, (double)a.delta); }
+            const float b = a.beta[0];
+            g[j] = gL[j] + b * gr;
+            if (d) d[j] = dL[j] + 2.0f * b * om;
+            phi *= (double)b;
+        } else {
+            const float nn = (float)(L + R + U + D);
+            float lap[kMaxMat];
+            for (int k = 0; k < a.K; ++k) {
+                const float* xk = x + (size_t)k * nj;
+                float s = nn * xk[j];
+                if (L) s -= xk[j - 1];
+                if (R) s -= xk[j + 1];
+                if (U) s -= xk[j - a.nx];
+                if (D) s -= xk[j + a.nx];
+                lap[k] = s;
+            }
+            for (int k = 0; k < a.K; ++k) {
+                float gr = 0.0f, ab = 0.0f;
+                for (int l2 = 0; l2 < a.K; ++l2) {
+                    gr = fmaf(a.beta[k * a.K + l2], lap[l2], gr);
+                    ab += fabsf(a.beta[k * a.K + l2]);
+                }
+                g[(size_t)k * nj + j] = gL[(size_t)k * nj + j] + gr;
+                if (d) d[(size_t)k * nj + j] = dL[(size_t)k * nj + j] + ab * 2.0f * nn;
+                phi += 0.5 * (double)x[(size_t)k * nj + j] * (double)gr;
+            }
+        }
+    }
+    const double tot = block_sum(phi, sh);
+    if (threadIdx.x == 0 && partials) partials[blockIdx.x] = tot;
+}
+
+// p^T R'' p: quadratic p^T (beta (x) Gamma) p; Huber beta sum_pairs omega(x_j - x_j') (p_j - p_j')^2.
+__global__ __launch_bounds__(kThreads) void k_penalty_quadform(PenaltyArgs a, const float* __restrict__ x,
+                                                               const float* __restrict__ p,
+                                                               double* __restrict__ partials) {
+    __shared__ double sh[kThreads / 64];
+    const int nj = a.nx * a.ny;
+    const int j = blockIdx.x * kThreads + threadIdx.x;
+    double acc = 0.0;
+    if (j < nj) {
+        const int iy = j / a.nx, ix = j - iy * a.nx;
+        const bool R = ix + 1 < a.nx, D = iy + 1 < a.ny;
+        if (a.kind == MBMD_PENALTY_HUBER) {
+            float s = 0.0f;
+            if (R) { const float dp = p[j] - p[j + 1]; s += huber_omega(x[j] - x[j + 1], a.delta) * dp * dp; }
+            if (D) { const float dp = p[j] - p[j + a.nx]; s += huber_omega(x[j] - x[j + a.nx], a.delta) * dp * dp; }
+            acc = (double)a.beta[0] * (double)s;
+        } else {
+            // sum over pairs of sum_kl beta_kl (p_k - p_k')(p_l - p_l') = p^T (beta (x) Gamma) p
+            for (int k = 0; k < a.K; ++k)
+                for (int l2 = 0; l2 < a.K; ++l2) {
+                    const float* pk = p + (size_t)k * nj;
+                    const float* pl = p + (size_t)l2 * nj;
+                    float s = 0.0f;
+                    if (R) s += (pk[j] - pk[j + 1]) * (pl[j] - pl[j + 1]);
+                    if (D) s += (pk[j] - pk[j + a.nx]) * (pl[j] - pl[j + a.nx]);
+                    acc += (double)a.beta[k * a.K + l2] * (double)s;
+                }
+        }
+    }
+    const double tot = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// out += (beta (x) Gamma) v (the quadratic Hessian; Huber builds use it too).
+__global__ __launch_bounds__(kThreads) void k_penalty_hess_add(PenaltyArgs a, const float* __restrict__ v,
+                                                               float* __restrict__ out) {
+    const int nj = a.nx * a.ny;
+    const int j = blockIdx.x * kThreads + threadIdx.x;
+    if (j >= nj) return;
+    const int iy = j / a.nx, ix = j - iy * a.nx;
+    const bool L = ix > 0, R = ix + 1 < a.nx, U = iy > 0, D = iy + 1 < a.ny;
+    const float nn = (float)(L + R + U + D);
+    float lap[kMaxMat];
+    for (int k = 0; k < a.K; ++k) {
+        const float* vk = v + (size_t)k * nj;
+        float s = nn * vk[j];
+        if (L) s -= vk[j - 1];
+        if (R) s -= vk[j + 1];
+        if (U) s -= vk[j - a.nx];
+        if (D) s -= vk[j + a.nx];
+        lap[k] = s;
+    }
+    for (int k = 0; k < a.K; ++k) {
+        float gr = 0.0f;
+        for (int l2 = 0; l2 < a.K; ++l2) gr = fmaf(a.beta[k * a.K + l2], lap[l2], gr);
+        out[(size_t)k * nj + j] += gr;
+    }
+}
+
+__global__ void k_plain_update(int n, float* __restrict__ x, const float* __restrict__ g,
+                               const float* __restrict__ d) {
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) x[i] -= g[i] / fmaxf(d[i], 1e-30f);
+}
+
+__global__ void k_axpy_alpha(int n, float* __restrict__ x, const float* __restrict__ p,
+                             const double* __restrict__ alpha) {
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) x[i] = fmaf((float)*alpha, p[i], x[i]);
+}
+
+__global__ void k_fill(int n, float* __restrict__ x, float value) {
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) x[i] = value;
+}
+
+__global__ void k_scale_copy(int n, const float* __restrict__ in, float* __restrict__ out, float scale) {
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) out[i] = scale * in[i];
+}
+
+__global__ __launch_bounds__(kThreads) void k_dot(int n, const float* __restrict__ a,
+                                                  const float* __restrict__ b,
+                                                  double* __restrict__ partials) {
+    __shared__ double sh[kThreads / 64];
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    const double v = i < n ? (double)a[i] * (double)b[i] : 0.0;
+    const double tot = block_sum(v, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// out_k = scale * sum_l M_kl in_l per pixel; M packed component-major.  in may alias out.
+__global__ void k_block_apply(int nj, int K, const float* __restrict__ M, const float* in, float* out,
+                              float scale) {
+    const int j = blockIdx.x * kThreads + threadIdx.x;
+    if (j >= nj) return;
+    float a[kMaxMat];
+    for (int k = 0; k < K; ++k) a[k] = in[(size_t)k * nj + j];
+    for (int k = 0; k < K; ++k) {
+        float s = 0.0f;
+        for (int l2 = 0; l2 < K; ++l2) s = fmaf(M[(size_t)packed_index(k, l2, K) * nj + j], a[l2], s);
+        out[(size_t)k * nj + j] = scale * s;
+    }
+}
+
+// Symmetric eigen-decomposition of a K x K matrix (K <= 4) by cyclic Jacobi.
+__device__ void jacobi_eig(int K, double A[kMaxMat][kMaxMat], double V[kMaxMat][kMaxMat], double* lam) {
+    for (int i = 0; i < K; ++i)
+        for (int j = 0; j < K; ++j) V[i][j] = (i == j) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 16; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < K; ++i)
+            for (int j = 0; j < K; ++j) {
+                tot += A[i][j] * A[i][j];
+                if (i != j) off += A[i][j] * A[i][j];
+            }
+        if (off <= 1e-30 * tot || off == 0.0) break;
+        for (int p = 0; p < K - 1; ++p)
+            for (int q = p + 1; q < K; ++q) {
+                if (A[p][q] == 0.0) continue;
+                const double theta = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < K; ++k) {
+                    const double akp = A[k][p], akq = A[k][q];
+                    A[k][p] = c * akp - s * akq;
+                    A[k][q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < K; ++k) {
+                    const double apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = c * apk - s * aqk;
+                    A[q][k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < K; ++k) {
+                    const double vkp = V[k][p], vkq = V[k][q];
+                    V[k][p] = c * vkp - s * vkq;
+                    V[k][q] = s * vkp + c * vkq;
+                }
+            }
+    }
+    for (int i = 0; i < K; ++i) lam[i] = A[i][i];
+}
+
+__device__ void load_block(int K, const float* __restrict__ in, int n, int j, double A[kMaxMat][kMaxMat]) {
+    for (int k = 0; k < K; ++k)
+        for (int l2 = 0; l2 < K; ++l2) A[k][l2] = (double)in[(size_t)packed_index(k, l2, K) * n + j];
+}
+
+// out = V diag(max(lam, floor)^power) V^T.  floor = floor_rel * lambda_max of
+// the block (blocks with lambda_max <= 0 map to 0) unless floor_abs is given,
+// in which case floor = eps * (*floor_abs) for every block.
+__global__ void k_block_invsqrt(int n, int K, const float* __restrict__ in, float* __restrict__ out,
+                                double power, double floor_rel, const double* __restrict__ floor_abs,
+                                double eps, int* __restrict__ n_floored) {
+    const int j = blockIdx.x * kThreads + threadIdx.x;
+    if (j >= n) return;
+    double A[kMaxMat][kMaxMat], V[kMaxMat][kMaxMat], lam[kMaxMat];
+    load_block(K, in, n, j, A);
+    jacobi_eig(K, A, V, lam);
+    double lmax = -DBL_MAX;
+    for (int k = 0; k < K; ++k) lmax = fmax(lmax, lam[k]);
+    double floor;
+    bool zero = false;
+    if (floor_abs) {
+        floor = eps * (*floor_abs);
+    } else {
+        floor = floor_rel * lmax;
+        zero = !(lmax > 0.0);
+    }
+    int nf = 0;
+    double f[kMaxMat];
+    for (int k = 0; k < K; ++k) {
+        double l2 = lam[k];
+        if (l2 < floor) { l2 = floor; ++nf; }
+        f[k] = (zero || !(l2 > 0.0)) ? 0.0 : pow(l2, power);
+    }
+    for (int k = 0; k < K; ++k)
+        for (int l2 = k; l2 < K; ++l2) {
+            double s = 0.0;
+            for (int m = 0; m < K; ++m) s += V[k][m] * f[m] * V[l2][m];
+            out[(size_t)packed_index(k, l2, K) * n + j] = (float)s;
+        }
+    if (nf && n_floored) atomicAdd(n_floored, nf);
+}
+
+__device__ void atomic_max_double(double* addr, double val) {
+    unsigned long long* a = reinterpret_cast<unsigned long long*>(addr);
+    unsigned long long old = *a;
+    while (__longlong_as_double(old) < val) {
+        const unsigned long long prev = atomicCAS(a, old, __double_as_longlong(val));
+        if (prev == old) break;
+        old = prev;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_block_lmax(int n, int K, const float* __restrict__ in,
+                                                         double* __restrict__ lmax_out) {
+    __shared__ double sh[kThreads];
+    const int j = blockIdx.x * kThreads + threadIdx.x;
+    double lm = -DBL_MAX;
+    if (j < n) {
+        double A[kMaxMat][kMaxMat], V[kMaxMat][kMaxMat], lam[kMaxMat];
+        load_block(K, in, n, j, A);
+        jacobi_eig(K, A, V, lam);
+        for (int k = 0; k < K; ++k) lm = fmax(lm, lam[k]);
+    }
+    sh[threadIdx.x] = lm;
+    __syncthreads();
+    for (int off = kThreads / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomic_max_double(lmax_out, sh[0]);
+}
+
+__global__ void k_inv_var(int n, const float* __restrict__ y, float* __restrict__ w) {
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) w[i] = 1.0f / fmaxf(y[i], 1.0f);
+}
+
+// out[c][i] = in[c][i] * vec[i] for c < nch
+__global__ void k_scale_by_vec(int n, int nch, const float* __restrict__ in, const float* __restrict__ vec,
+                               float* __restrict__ out) {
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const float s = vec ? vec[i] : 1.0f;
+    for (int c = 0; c < nch; ++c) out[(size_t)c * n + i] = in[(size_t)c * n + i] * s;
+}
+
+__global__ void k_fill_double(int n, double* __restrict__ x, double value) {
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) x[i] = value;
+}
+
+struct Counts {
+    int c[kRegions];
+};
+
+// Sums every region in a fixed order; mode bit 1: compute alpha.
+__global__ __launch_bounds__(kThreads) void k_reduce_final(const double* __restrict__ partials, Counts counts,
+                                                           double* __restrict__ scal,
+                                                           double* __restrict__ trace_slot, int mode,
+                                                           int* __restrict__ flags) {
+    __shared__ double sh[kThreads];
+    double sums[kRegions];
+    for (int r = 0; r < kRegions; ++r) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < counts.c[r]; i += kThreads) s += partials[(size_t)r * kMaxPartials + i];
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int off = kThreads / 2; off > 0; off >>= 1) {
+            if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+            __syncthreads();
+        }
+        sums[r] = sh[0];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double phi = sums[R_PHI_L] + sums[R_PHI_R];
+    scal[S_PHI] = phi;
+    if (trace_slot) *trace_slot = phi;
+    bool bad = !isfinite(phi);
+    if (mode & 1) {
+        const double gp = sums[R_GP];
+        const double den = sums[R_CQ2] + sums[R_PRP];
+        const double alpha = den > 0.0 ? -gp / den : 0.0;
+        scal[S_GP] = gp;
+        scal[S_DEN] = den;
+        scal[S_ALPHA] = isfinite(alpha) ? alpha : 0.0;
+        bad = bad || !isfinite(alpha);
+    }
+    if (bad && flags) flags[0] = 1;
+}
+
+int nblk(int n) { return (n + kThreads - 1) / kThreads; }
+
+}  // namespace
+
+void launch_inv_var(int n, const float* y, float* w, hipStream_t s) {
+    hipLaunchKernelGGL(k_inv_var, dim3(nblk(n)), dim3(kThreads), 0, s, n, y, w);
+    MBMD_LAUNCHED();
+}
+
+void launch_scale_by_vec(int n, int nch, const float* in, const float* vec, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_by_vec, dim3(nblk(n)), dim3(kThreads), 0, s, n, nch, in, vec, out);
+    MBMD_LAUNCHED();
+}
+
+void launch_fill_double(int n, double* x, double value, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_double, dim3(nblk(n)), dim3(kThreads), 0, s, n, x, value);
+    MBMD_LAUNCHED();
+}
+
+int launch_penalty_grad(const PenaltyArgs& a, const float* x, const float* gL, const float* dL, float* g,
+                        float* d, double* phi_partials, hipStream_t s) {
+    const int nb = nblk(a.nx * a.ny);
+    MBMD_REQUIRE(nb <= kMaxPartials, MBMD_ERR_SHAPE, "image too large for the partial-sum buffer");
+    hipLaunchKernelGGL(k_penalty_grad, dim3(nb), dim3(kThreads), 0, s, a, x, gL, dL, g, d, phi_partials);
+    MBMD_LAUNCHED();
+    return nb;
+}
+
+int launch_penalty_quadform(const PenaltyArgs& a, const float* x, const float* p, double* partials,
+                            hipStream_t s) {
+    const int nb = nblk(a.nx * a.ny);
+    hipLaunchKernelGGL(k_penalty_quadform, dim3(nb), dim3(kThreads), 0, s, a, x, p, partials);
+    MBMD_LAUNCHED();
+    return nb;
+}
+
+void launch_penalty_hess_add(const PenaltyArgs& a, const float* v, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_penalty_hess_add, dim3(nblk(a.nx * a.ny)), dim3(kThreads), 0, s, a, v, out);
+    MBMD_LAUNCHED();
+}
+
+void launch_plain_update(int n, float* x, const float* g, const float* d, hipStream_t s) {
+    hipLaunchKernelGGL(k_plain_update, dim3(nblk(n)), dim3(kThreads), 0, s, n, x, g, d);
+    MBMD_LAUNCHED();
+}
+
+void launch_axpy_alpha(int n, float* x, const float* p, const double* alpha, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy_alpha, dim3(nblk(n)), dim3(kThreads), 0, s, n, x, p, alpha);
+    MBMD_LAUNCHED();
+}
+
+void launch_fill(int n, float* x, float value, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill, dim3(nblk(n)), dim3(kThreads), 0, s, n, x, value);
+    MBMD_LAUNCHED();
+}
+
+void launch_scale_copy(int n, const float* in, float* out, float scale, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_copy, dim3(nblk(n)), dim3(kThreads), 0, s, n, in, out, scale);
+    MBMD_LAUNCHED();
+}
+
+int launch_dot(int n, const float* a, const float* b, double* partials, hipStream_t s) {
+    const int nb = nblk(n);
+    MBMD_REQUIRE(nb <= kMaxPartials, MBMD_ERR_SHAPE, "vector too long for the partial-sum buffer");
+    hipLaunchKernelGGL(k_dot, dim3(nb), dim3(kThreads), 0, s, n, a, b, partials);
+    MBMD_LAUNCHED();
+    return nb;
+}
+
+void launch_block_apply(int nj, int K, const float* M, const float* in, float* out, float scale, hipStream_t s) {
+    hipLaunchKernelGGL(k_block_apply, dim3(nblk(nj)), dim3(kThreads), 0, s, nj, K, M, in, out, scale);
+    MBMD_LAUNCHED();
+}
+
+void launch_block_invsqrt(int n, int K, const float* in_packed, float* out_packed, double power,
+                          double floor_rel, const double* floor_abs_scaled, double eps, int* n_floored,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_block_invsqrt, dim3(nblk(n)), dim3(kThreads), 0, s, n, K, in_packed, out_packed,
+                       power, floor_rel, floor_abs_scaled, eps, n_floored);
+    MBMD_LAUNCHED();
+}
+
+void launch_block_lmax(int n, int K, const float* in_packed, double* lmax, hipStream_t s) {
+    hipLaunchKernelGGL(k_block_lmax, dim3(nblk(n)), dim3(kThreads), 0, s, n, K, in_packed, lmax);
+    MBMD_LAUNCHED();
+}
+
+void launch_reduce_final(double* partials, const int* counts, double* scal, double* trace_slot, int mode,
+                         int* flags, hipStream_t s) {
+    Counts c;
+    for (int r = 0; r < kRegions; ++r) {
+        MBMD_REQUIRE(counts[r] >= 0 && counts[r] <= kMaxPartials, MBMD_ERR_SHAPE, "bad partial count");
+        c.c[r] = counts[r];
+    }
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kThreads), 0, s, partials, c, scal, trace_slot, mode,
+                       flags);
+    MBMD_LAUNCHED();
+}
+
+}  // namespace mbmd

@@ -1,0 +1,222 @@
+// Internal declarations of the MI355X (gfx950) library behind include/mbmd.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mbmd.h"
+
+namespace mbmd {
+
+constexpr int kMaxMat = 4;
+constexpr int kMaxChan = 8;
+constexpr int kMaxEnergy = 256;
+constexpr int kMaxPacked = kMaxMat * (kMaxMat + 1) / 2;   // symmetric N_k x N_k, packed
+constexpr int kMaxBackCh = 10;                              // channels of one backprojection
+constexpr int kRefreshEvery = 25;                           // recompute l = A x this often
+constexpr int kMaxPartials = 16384;                         // per reduction region
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+struct Error {
+    int status;
+    std::string msg;
+};
+#define MBMD_HIP(call)                                                                  \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            throw ::mbmd::Error{MBMD_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+#define MBMD_REQUIRE(cond, status, msg)                                                 \
+    do {                                                                                \
+        if (!(cond)) throw ::mbmd::Error{(status), (msg)};                              \
+    } while (0)
+#define MBMD_LAUNCHED() MBMD_HIP(hipGetLastError())
+
+// Index of packed symmetric entry (k, l) of an n x n matrix, row-major upper.
+__host__ __device__ inline int packed_index(int k, int l, int n) {
+    if (k > l) { int t = k; k = l; l = t; }
+    return k * n - k * (k - 1) / 2 + (l - k);
+}
+
+// ---------------------------------------------------------------- device memory arena
+struct Arena {
+    char* base = nullptr;
+    size_t size = 0, used = 0;
+    std::vector<std::pair<size_t, size_t>> plan;   // unused, kept for symmetry
+    void reserve(size_t bytes);
+    template <class T> T* take(size_t n) {
+        size_t off = (used + 255) & ~size_t(255);
+        used = off + n * sizeof(T);
+        if (base == nullptr) return nullptr;     // sizing pass
+        if (used > size) throw Error{MBMD_ERR_HIP, "arena overflow"};
+        return reinterpret_cast<T*>(base + off);
+    }
+    void release();
+};
+
+// ---------------------------------------------------------------- geometry tables
+// Per-view data of the distance-driven projector.  A view sweeps either the
+// image rows (frame 0: line index q = iy, along index p = ix) or the columns
+// (frame 1: q = ix, p = iy).  Along-line positions K are in pixel units with
+// the origin at the image centre, so pixel p spans [p - Np/2, p + 1 - Np/2].
+struct ViewParams {
+    // fractional bin index of the point (K, q): beta = num / den with
+    // num = n0 + nK K + nq qq, den = d0 + dK K + dq qq, qq = q - (Nq-1)/2
+    float n0, nK, nq, d0, dK, dq;
+    int frame;
+    int pad;
+};
+
+struct GeomTables {
+    mbmd_geometry g{};
+    int V = 0, B = 0, nx = 0, ny = 0;
+    int n_frame_views[2] = {0, 0};
+    ViewParams* view = nullptr;      // [V]
+    float2* bound = nullptr;         // [V][B+1]: boundary b' at line q is C0 + C1 qq
+    float* path = nullptr;           // [V][B]: path length per sweep line of the bin-centre ray
+    int* frame_views = nullptr;      // [V]: views of frame 0, then views of frame 1
+    float2* prefix = nullptr;        // scratch: [n_mat][ny][nx] + [n_mat][nx][ny] exclusive prefix sums
+    int prefix_mat = 0;
+    void* mem = nullptr;
+    int device = -1;
+};
+
+// Builds the tables in FP64 on the host and uploads them (synchronous copy).
+void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat);
+void free_geometry(GeomTables& t);
+void validate_geometry(const mbmd_geometry& g);
+GeomTables& cached_geometry(const mbmd_geometry& g, int prefix_mat);
+
+// ---------------------------------------------------------------- projector launches
+void launch_project(const GeomTables& t, const float* x, float* sino, int n_mat, hipStream_t s);
+void launch_backproject(const GeomTables& t, const float* sino, float* x, int n_ch, hipStream_t s);
+
+// ---------------------------------------------------------------- problem
+struct Problem {
+    mbmd_geometry g{};
+    GeomTables* geom = nullptr;      // owned (projector geometries only)
+    int identity = 0;
+    int K = 1, E = 1, C = 1, npk = 1;
+    int nx = 0, ny = 0, V = 0, B = 0;
+    int nj = 0, ni = 0;              // pixels, rays
+    int pen_kind = 0;
+    double beta[kMaxMat * kMaxMat] = {0};
+    double delta = 0.0;
+    int has_penalty = 0;
+    std::vector<double> Qh, Sh;
+
+    Arena arena;
+    // spectral model (device)
+    float *Q = nullptr, *S = nullptr, *rowS = nullptr, *Qsum = nullptr, *beta_d = nullptr;
+    // data
+    float *y = nullptr, *w = nullptr, *gammaA = nullptr;
+    // sinogram state
+    float *l = nullptr, *q = nullptr, *u = nullptr, *v = nullptr, *r = nullptr, *sino_tmp = nullptr;
+    // image state
+    float *g_img = nullptr, *d_img = nullptr, *p_img = nullptr, *t_img = nullptr, *t2_img = nullptr;
+    float *dL_const = nullptr;       // single-energy data curvature A^T(gamma c), built once
+    int dL_valid = 0;
+    // preconditioners
+    float* M0 = nullptr;             // [nj][npk]
+    float* Linv = nullptr;           // [ny][nx][npk]  (L^-1 blocks)
+    float* Kinv = nullptr;           // [ny][nx][npk]  (K^-1 blocks)
+    float* W = nullptr;              // [npk][ni] Fisher weights (build)
+    float2* spec = nullptr;          // [K][ny][nx] complex scratch
+    float2* tw_x = nullptr;          // twiddles for nx
+    float2* tw_y = nullptr;          // twiddles for ny
+    float* coef = nullptr;           // [K][ny][nx] Haar coefficients
+    float* coarse = nullptr;         // [K][ny/T][nx/T]
+    int built[4] = {0, 0, 0, 0};
+    int m0_built = 0;
+    int n_floored[4] = {0, 0, 0, 0};
+    // reductions
+    double* partials = nullptr;      // [kRegions][kMaxPartials]
+    double* scal = nullptr;          // device scalars (alpha, phi, flags...)
+    double* trace = nullptr;         // device objective trace (grows)
+    int trace_cap = 0;
+    double* trace_mem_owner = nullptr;
+    int* flags = nullptr;
+    int l_valid_for_x = 0;
+    hipStream_t last_stream = nullptr;
+};
+
+// Reduction regions and scalar slots.
+enum { R_PHI_L = 0, R_PHI_R, R_GP, R_CQ2, R_PRP, R_AUX, kRegions };
+enum { S_ALPHA = 0, S_PHI, S_GP, S_DEN, S_LMAX, S_AUX, S_COUNT, kScalars = 16 };
+
+// ---------------------------------------------------------------- ray (per detector element) passes
+struct RayArgs {
+    int ni, K, E, C;
+    const float *Q, *S, *rowS, *Qsum;    // device spectral model
+    const float *y, *w, *gammaA;         // [C][ni], [C][ni], [ni] (NULL gammaA = 1)
+};
+int launch_ray_grad(const RayArgs& a, const float* l, float* u, float* v, float* r,
+                    double* phi_partials, hipStream_t s);
+int launch_ray_curv(const RayArgs& a, const float* l, const float* r, const float* q,
+                    double* partials, hipStream_t s);
+void launch_forward_model(const RayArgs& a, const float* l, float* ybar, hipStream_t s);
+void launch_forward_vjp(const RayArgs& a, const float* l, const float* gbar, float* sk, hipStream_t s);
+void launch_fisher(const RayArgs& a, float* W, hipStream_t s);
+void launch_fisher_mix(int ni, int K, const float* W, const float* in, float* out, hipStream_t s);
+int launch_identity_iterate(const RayArgs& a, float* x, const float* M0, int precond, int n_iter,
+                            double* partials_per_iter, int stride, hipStream_t s);
+
+// ---------------------------------------------------------------- image passes
+struct PenaltyArgs {
+    int K, nx, ny, kind;
+    const float* beta;     // device [K][K]
+    float delta;
+};
+int launch_penalty_grad(const PenaltyArgs& a, const float* x, const float* gL, const float* dL,
+                        float* g, float* d, double* phi_partials, hipStream_t s);
+int launch_penalty_quadform(const PenaltyArgs& a, const float* x, const float* p, double* partials,
+                            hipStream_t s);
+void launch_penalty_hess_add(const PenaltyArgs& a, const float* v, float* out, hipStream_t s);
+void launch_plain_update(int n, float* x, const float* g, const float* d, hipStream_t s);
+void launch_inv_var(int n, const float* y, float* w, hipStream_t s);
+void launch_scale_by_vec(int n, int nch, const float* in, const float* vec, float* out, hipStream_t s);
+void launch_fill_double(int n, double* x, double value, hipStream_t s);
+void launch_axpy_alpha(int n, float* x, const float* p, const double* alpha, hipStream_t s);
+void launch_fill(int n, float* x, float value, hipStream_t s);
+void launch_scale_copy(int n, const float* in, float* out, float scale, hipStream_t s);
+int launch_dot(int n, const float* a, const float* b, double* partials, hipStream_t s);
+void launch_block_apply(int nj, int K, const float* M, const float* in, float* out, float scale,
+                        hipStream_t s);
+void launch_block_pack_from_images(int nj, int K, const float* cols, float* packed, hipStream_t s);
+void launch_block_invsqrt(int n, int K, const float* in_packed, float* out_packed, double power,
+                          double floor_rel, const double* floor_abs_scaled, double eps,
+                          int* n_floored, hipStream_t s);
+void launch_block_lmax(int n, int K, const float* in_packed, double* lmax, hipStream_t s);
+void launch_reduce_final(double* partials, const int* counts, double* scal, double* trace_slot,
+                         int mode, int* flags, hipStream_t s);
+
+// ---------------------------------------------------------------- transforms
+void fill_twiddles(float2* tw, int n, hipStream_t s);
+// Forward 2D FFT of K real images (optionally pre-multiplied by packed blocks
+// M and circularly shifted by (-sy, -sx)); complex output [K][ny][nx].
+void launch_fft2_forward(int K, int nx, int ny, const float* in, const float* M, int sy, int sx,
+                         float2* spec, const float2* twx, const float2* twy, hipStream_t s);
+// out = -scale * M * Re(IFFT2(Filt * FFT2(M * in)))  and partial sums of g.out.
+int launch_fourier_apply(int K, int nx, int ny, const float* in, const float* M, const float* Filt,
+                         float2* spec, const float2* twx, const float2* twy, float* out,
+                         float out_sign, const float* g, double* partials, hipStream_t s);
+void launch_spectrum_real_to_blocks(int K, int nj, int k_col, const float2* spec, float* blocks,
+                                    hipStream_t s);
+
+int haar_tile(int n);
+void launch_haar_forward(int K, int n, const float* in, const float* M, float* coef, float* coarse,
+                         hipStream_t s);
+void launch_haar_inverse(int K, int n, const float* coef, float* coarse, const float* M, float* out,
+                         float out_sign, hipStream_t s);
+int launch_haar_apply(int K, int n, const float* in, const float* M, const float* Kinv, float* coef,
+                      float* coarse, float* out, float out_sign, const float* g, double* partials,
+                      hipStream_t s);
+void launch_coef_blocks(int K, int n, int k_col, const float* coef, float* blocks, hipStream_t s);
+
+}  // namespace mbmd

@@ -1,0 +1,419 @@
+// Per-ray (per detector element) passes of the polyenergetic model.
+//
+// One thread per ray.  The energy loop recomputes t_E = exp(-sum_k Q_Ek l_k)
+// instead of storing a ray x energy tensor: the first pass forms the channel
+// means ybar_c and the weighted residuals r_c = w_c (ybar_c - y_c); the second
+// pass forms, per energy (SPS section, with rho read as S^T W (ybar - y) -
+// eta t):
+//   s_E    = sum_c S_cE r_c
+//   eta_E  = sum_c S_cE w_c sum_E' S_cE'
+//   hdot_E = -t_E s_E                      (dL/dl_E)
+//   c_E    = max(2 eta_E + s_E - eta_E t_E, 0)   (maximum curvature on l >= 0)
+// and accumulates u_k = sum_E Q_Ek hdot_E and v_k = sum_E Q_Ek gamma_E c_E
+// with gamma_E = (A 1)_i sum_k Q_Ek.  The spectral model Q, S is read with
+// wave-uniform indices (scalar loads).  Objective partial sums are FP64 and
+// reduced per block in a fixed order.
+#include <cmath>
+
+#include "internal.h"
+
+namespace mbmd {
+
+namespace {
+
+constexpr int kRayThreads = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int i = 0; i < nw; ++i) t += sh[i];
+    }
+    return t;
+}
+
+struct RayModel {
+    int K, E, C;
+    const float *Q, *S, *rowS, *Qsum;
+};
+
+// Pass 1: ybar_c for the ray with line integrals lk.
+__device__ __forceinline__ void channel_means(const RayModel& m, const float* lk, float* ybar) {
+    for (int c = 0; c < m.C; ++c) ybar[c] = 0.0f;
+    for (int e = 0; e < m.E; ++e) {
+        float le = 0.0f;
+        for (int k = 0; k < m.K; ++k) le = fmaf(m.Q[e * m.K + k], lk[k], le);
+        const float t = expf(-le);
+        for (int c = 0; c < m.C; ++c) ybar[c] = fmaf(m.S[c * m.E + e], t, ybar[c]);
+    }
+}
+
+__global__ __launch_bounds__(kRayThreads) void k_ray_grad(RayModel m, int ni, const float* __restrict__ l,
+                                                          const float* __restrict__ y,
+                                                          const float* __restrict__ w,
+                                                          const float* __restrict__ gammaA,
+                                                          float* __restrict__ u, float* __restrict__ v,
+                                                          float* __restrict__ r_out,
+                                                          double* __restrict__ partials) {
+    __shared__ double sh[kRayThreads / 64];
+    const int i = blockIdx.x * kRayThreads + threadIdx.x;
+    double phi = 0.0;
+    if (i < ni) {
+        float lk[kMaxMat], ybar[kMaxChan], rc[kMaxChan], sig[kMaxChan];
+        for (int k = 0; k < m.K; ++k) lk[k] = l[(size_t)k * ni + i];
+        channel_means(m, lk, ybar);
+        for (int c = 0; c < m.C; ++c) {
+            const float yc = y[(size_t)c * ni + i], wc = w[(size_t)c * ni + i];
+            const float dv = ybar[c] - yc;
+            rc[c] = wc * dv;
+            sig[c] = wc * m.rowS[c];
+            phi += 0.5 * (double)wc * (double)dv * (double)dv;
+            if (r_out) r_out[(size_t)c * ni + i] = rc[c];
+        }
+        const float gA = gammaA ? gammaA[i] : 1.0f;
+        float uk[kMaxMat], vk[kMaxMat];
+        for (int k = 0; k < m.K; ++k) uk[k] = vk[k] = 0.0f;
+        for (int e = 0; e < m.E; ++e) {
+            float le = 0.0f;
+            for (int k = 0; k < m.K; ++k) le = fmaf(m.Q[e * m.K + k], lk[k], le);
+            const float t = expf(-le);
+            float s = 0.0f, eta = 0.0f;
+            for (int c = 0; c < m.C; ++c) {
+                const float sce = m.S[c * m.E + e];
+                s = fmaf(sce, rc[c], s);
+                eta = fmaf(sce, sig[c], eta);
+            }
+            const float hdot = -t * s;
+            const float ce = fmaxf(2.0f * eta + s - eta * t, 0.0f);
+            const float gc = gA * m.Qsum[e] * ce;
+            for (int k = 0; k < m.K; ++k) {
+                const float qek = m.Q[e * m.K + k];
+                uk[k] = fmaf(qek, hdot, uk[k]);
+                vk[k] = fmaf(qek, gc, vk[k]);
+            }
+        }
+        for (int k = 0; k < m.K; ++k) {
+            u[(size_t)k * ni + i] = uk[k];
+            if (v) v[(size_t)k * ni + i] = vk[k];
+        }
+    }
+    const double tot = block_sum(phi, sh);
+    if (threadIdx.x == 0 && partials) partials[blockIdx.x] = tot;
+}
+
+// sum_iE c_iE q_iE^2 with q_iE = sum_k Q_Ek q_ik, c recomputed from l and r.
+__global__ __launch_bounds__(kRayThreads) void k_ray_curv(RayModel m, int ni, const float* __restrict__ l,
+                                                          const float* __restrict__ r,
+                                                          const float* __restrict__ w,
+                                                          const float* __restrict__ q,
+                                                          double* __restrict__ partials) {
+    __shared__ double sh[kRayThreads / 64];
+    const int i = blockIdx.x * kRayThreads + threadIdx.x;
+    double acc = 0.0;
+    if (i < ni) {
+        float lk[kMaxMat], qk[kMaxMat], rc[kMaxChan], sig[kMaxChan];
+        for (int k = 0; k < m.K; ++k) {
+            lk[k] = l[(size_t)k * ni + i];
+            qk[k] = q[(size_t)k * ni + i];
+        }
+        for (int c = 0; c < m.C; ++c) {
+            rc[c] = r[(size_t)c * ni + i];
+            sig[c] = w[(size_t)c * ni + i] * m.rowS[c];
+        }
+        float a = 0.0f;
+        for (int e = 0; e < m.E; ++e) {
+            float le = 0.0f, qe = 0.0f;
+            for (int k = 0; k < m.K; ++k) {
+                le = fmaf(m.Q[e * m.K + k], lk[k], le);
+                qe = fmaf(m.Q[e * m.K + k], qk[k], qe);
+            }
+            const float t = expf(-le);
+            float s = 0.0f, eta = 0.0f;
+            for (int c = 0; c < m.C; ++c) {
+                const float sce = m.S[c * m.E + e];
+                s = fmaf(sce, rc[c], s);
+                eta = fmaf(sce, sig[c], eta);
+            }
+            const float ce = fmaxf(2.0f * eta + s - eta * t, 0.0f);
+            a = fmaf(ce * qe, qe, a);
+        }
+        acc = (double)a;
+    }
+    const double tot = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kRayThreads) void k_forward_model(RayModel m, int ni, const float* __restrict__ l,
+                                                               float* __restrict__ ybar_out) {
+    const int i = blockIdx.x * kRayThreads + threadIdx.x;
+    if (i >= ni) return;
+    float lk[kMaxMat], ybar[kMaxChan];
+    for (int k = 0; k < m.K; ++k) lk[k] = l[(size_t)k * ni + i];
+    channel_means(m, lk, ybar);
+    for (int c = 0; c < m.C; ++c) ybar_out[(size_t)c * ni + i] = ybar[c];
+}
+
+// s_k = sum_E Q_Ek (-t_E) sum_c S_cE gbar_c
+__global__ __launch_bounds__(kRayThreads) void k_forward_vjp(RayModel m, int ni, const float* __restrict__ l,
+                                                             const float* __restrict__ gbar,
+                                                             float* __restrict__ sk) {
+    const int i = blockIdx.x * kRayThreads + threadIdx.x;
+    if (i >= ni) return;
+    float lk[kMaxMat], gc[kMaxChan], acc[kMaxMat];
+    for (int k = 0; k < m.K; ++k) {
+        lk[k] = l[(size_t)k * ni + i];
+        acc[k] = 0.0f;
+    }
+    for (int c = 0; c < m.C; ++c) gc[c] = gbar[(size_t)c * ni + i];
+    for (int e = 0; e < m.E; ++e) {
+        float le = 0.0f;
+        for (int k = 0; k < m.K; ++k) le = fmaf(m.Q[e * m.K + k], lk[k], le);
+        const float t = expf(-le);
+        float s = 0.0f;
+        for (int c = 0; c < m.C; ++c) s = fmaf(m.S[c * m.E + e], gc[c], s);
+        const float f = -t * s;
+        for (int k = 0; k < m.K; ++k) acc[k] = fmaf(m.Q[e * m.K + k], f, acc[k]);
+    }
+    for (int k = 0; k < m.K; ++k) sk[(size_t)k * ni + i] = acc[k];
+}
+
+// Fisher weights W_i = J^T diag(w) J, J[c,k] = -sum_E S_cE D_E Q_Ek, with the
+// data-based D: y / I0 for one energy and channel, else exp(-mu_w(E) l_w)
+// from a 10-step Gauss-Newton water-only estimate (material 0 is water).
+__global__ __launch_bounds__(kRayThreads) void k_fisher(RayModel m, int ni, const float* __restrict__ y,
+                                                        const float* __restrict__ w,
+                                                        float* __restrict__ W) {
+    const int i = blockIdx.x * kRayThreads + threadIdx.x;
+    if (i >= ni) return;
+    const int npk = m.K * (m.K + 1) / 2;
+    double yc[kMaxChan], wc[kMaxChan];
+    for (int c = 0; c < m.C; ++c) {
+        yc[c] = y[(size_t)c * ni + i];
+        wc[c] = w[(size_t)c * ni + i];
+    }
+    double J[kMaxChan][kMaxMat];
+    if (m.E == 1 && m.C == 1) {
+        const double D = yc[0] / (double)m.S[0];
+        for (int k = 0; k < m.K; ++k) J[0][k] = -(double)m.S[0] * D * (double)m.Q[k];
+    } else {
+        double lw = 0.0;
+        for (int it = 0; it < 10; ++it) {
+            double res[kMaxChan], jac[kMaxChan];
+            for (int c = 0; c < m.C; ++c) res[c] = jac[c] = 0.0;
+            for (int e = 0; e < m.E; ++e) {
+                const double mu = m.Q[e * m.K];
+                const double ex = exp(-mu * lw);
+                for (int c = 0; c < m.C; ++c) {
+                    const double sce = m.S[c * m.E + e];
+                    res[c] += sce * ex;
+                    jac[c] -= sce * mu * ex;
+                }
+            }
+            double num = 0.0, den = 0.0;
+            for (int c = 0; c < m.C; ++c) {
+                num += wc[c] * jac[c] * (res[c] - yc[c]);
+                den += wc[c] * jac[c] * jac[c];
+            }
+            const double step = den > 0.0 ? num / den : 0.0;
+            lw = fmax(lw - step, 0.0);
+        }
+        for (int c = 0; c < m.C; ++c)
+            for (int k = 0; k < m.K; ++k) J[c][k] = 0.0;
+        for (int e = 0; e < m.E; ++e) {
+            const double D = exp(-(double)m.Q[e * m.K] * lw);
+            for (int c = 0; c < m.C; ++c) {
+                const double sd = (double)m.S[c * m.E + e] * D;
+                for (int k = 0; k < m.K; ++k) J[c][k] -= sd * (double)m.Q[e * m.K + k];
+            }
+        }
+    }
+    for (int k = 0; k < m.K; ++k)
+        for (int l2 = k; l2 < m.K; ++l2) {
+            double s = 0.0;
+            for (int c = 0; c < m.C; ++c) s += wc[c] * J[c][k] * J[c][l2];
+            W[(size_t)packed_index(k, l2, m.K) * ni + i] = (float)s;
+        }
+    (void)npk;
+}
+
+__global__ __launch_bounds__(kRayThreads) void k_fisher_mix(int ni, int K, const float* __restrict__ W,
+                                                            const float* __restrict__ in,
+                                                            float* __restrict__ out) {
+    const int i = blockIdx.x * kRayThreads + threadIdx.x;
+    if (i >= ni) return;
+    float a[kMaxMat];
+    for (int k = 0; k < K; ++k) a[k] = in[(size_t)k * ni + i];
+    for (int k = 0; k < K; ++k) {
+        float s = 0.0f;
+        for (int l2 = 0; l2 < K; ++l2) s = fmaf(W[(size_t)packed_index(k, l2, K) * ni + i], a[l2], s);
+        out[(size_t)k * ni + i] = s;
+    }
+}
+
+// Whole iteration of the identity geometry without a penalty: every ray is an
+// independent N_k-unknown problem, so all n_iter iterations run in registers.
+// precond 0: plain SPS, x -= g / d.  precond 3: p = -M0 M0 g, per-ray alpha
+// from the 1D majoriser.  Objective partials of iteration it go to
+// partials[it * stride + block], the final one to partials[n_iter * stride + block].
+__global__ __launch_bounds__(kRayThreads) void k_identity_iterate(RayModel m, int ni, float* __restrict__ x,
+                                                                  const float* __restrict__ y,
+                                                                  const float* __restrict__ w,
+                                                                  const float* __restrict__ M0,
+                                                                  int precond, int n_iter,
+                                                                  double* __restrict__ partials,
+                                                                  int stride) {
+    __shared__ double sh[kRayThreads / 64];
+    const int i = blockIdx.x * kRayThreads + threadIdx.x;
+    const bool act = i < ni;
+    float xk[kMaxMat], yc[kMaxChan], wc[kMaxChan], sig[kMaxChan], Mb[kMaxPacked];
+    const int npk = m.K * (m.K + 1) / 2;
+    if (act) {
+        for (int k = 0; k < m.K; ++k) xk[k] = x[(size_t)k * ni + i];
+        for (int c = 0; c < m.C; ++c) {
+            yc[c] = y[(size_t)c * ni + i];
+            wc[c] = w[(size_t)c * ni + i];
+            sig[c] = wc[c] * m.rowS[c];
+        }
+        if (precond == MBMD_PRECOND_BLOCKDIAG)
+            for (int t = 0; t < npk; ++t) Mb[t] = M0[(size_t)t * ni + i];
+    }
+    for (int it = 0; it <= n_iter; ++it) {
+        double phi = 0.0;
+        float rc[kMaxChan], ybar[kMaxChan];
+        if (act) {
+            channel_means(m, xk, ybar);
+            for (int c = 0; c < m.C; ++c) {
+                const float dv = ybar[c] - yc[c];
+                rc[c] = wc[c] * dv;
+                phi += 0.5 * (double)wc[c] * (double)dv * (double)dv;
+            }
+        }
+        const double tot = block_sum(phi, sh);
+        if (threadIdx.x == 0) partials[(size_t)it * stride + blockIdx.x] = tot;
+        if (it == n_iter || !act) continue;
+        float gk[kMaxMat], dk[kMaxMat];
+        for (int k = 0; k < m.K; ++k) gk[k] = dk[k] = 0.0f;
+        for (int e = 0; e < m.E; ++e) {
+            float le = 0.0f;
+            for (int k = 0; k < m.K; ++k) le = fmaf(m.Q[e * m.K + k], xk[k], le);
+            const float t = expf(-le);
+            float s = 0.0f, eta = 0.0f;
+            for (int c = 0; c < m.C; ++c) {
+                const float sce = m.S[c * m.E + e];
+                s = fmaf(sce, rc[c], s);
+                eta = fmaf(sce, sig[c], eta);
+            }
+            const float hdot = -t * s;
+            const float ce = fmaxf(2.0f * eta + s - eta * t, 0.0f);
+            const float gc = m.Qsum[e] * ce;
+            for (int k = 0; k < m.K; ++k) {
+                gk[k] = fmaf(m.Q[e * m.K + k], hdot, gk[k]);
+                dk[k] = fmaf(m.Q[e * m.K + k], gc, dk[k]);
+            }
+        }
+        if (precond != MBMD_PRECOND_BLOCKDIAG) {
+            for (int k = 0; k < m.K; ++k) xk[k] -= gk[k] / fmaxf(dk[k], 1e-30f);
+            continue;
+        }
+        float h[kMaxMat], p[kMaxMat];
+        for (int k = 0; k < m.K; ++k) {
+            float s = 0.0f;
+            for (int l2 = 0; l2 < m.K; ++l2) s = fmaf(Mb[packed_index(k, l2, m.K)], gk[l2], s);
+            h[k] = s;
+        }
+        float num = 0.0f;
+        for (int k = 0; k < m.K; ++k) {
+            float s = 0.0f;
+            for (int l2 = 0; l2 < m.K; ++l2) s = fmaf(Mb[packed_index(k, l2, m.K)], h[l2], s);
+            p[k] = -s;
+            num = fmaf(-gk[k], p[k], num);
+        }
+        float den = 0.0f;
+        for (int e = 0; e < m.E; ++e) {
+            float le = 0.0f, qe = 0.0f;
+            for (int k = 0; k < m.K; ++k) {
+                le = fmaf(m.Q[e * m.K + k], xk[k], le);
+                qe = fmaf(m.Q[e * m.K + k], p[k], qe);
+            }
+            const float t = expf(-le);
+            float s = 0.0f, eta = 0.0f;
+            for (int c = 0; c < m.C; ++c) {
+                const float sce = m.S[c * m.E + e];
+                s = fmaf(sce, rc[c], s);
+                eta = fmaf(sce, sig[c], eta);
+            }
+            const float ce = fmaxf(2.0f * eta + s - eta * t, 0.0f);
+            den = fmaf(ce * qe, qe, den);
+        }
+        const float alpha = den > 0.0f ? num / den : 0.0f;
+        for (int k = 0; k < m.K; ++k) xk[k] = fmaf(alpha, p[k], xk[k]);
+    }
+    if (act)
+        for (int k = 0; k < m.K; ++k) x[(size_t)k * ni + i] = xk[k];
+}
+
+RayModel model_of(const RayArgs& a) { return RayModel{a.K, a.E, a.C, a.Q, a.S, a.rowS, a.Qsum}; }
+
+int blocks_for(int n) { return (n + kRayThreads - 1) / kRayThreads; }
+
+}  // namespace
+
+int launch_ray_grad(const RayArgs& a, const float* l, float* u, float* v, float* r, double* phi_partials,
+                    hipStream_t s) {
+    const int nb = blocks_for(a.ni);
+    MBMD_REQUIRE(nb <= kMaxPartials, MBMD_ERR_SHAPE, "too many rays for the partial-sum buffer");
+    hipLaunchKernelGGL(k_ray_grad, dim3(nb), dim3(kRayThreads), 0, s, model_of(a), a.ni, l, a.y, a.w,
+                       a.gammaA, u, v, r, phi_partials);
+    MBMD_LAUNCHED();
+    return nb;
+}
+
+int launch_ray_curv(const RayArgs& a, const float* l, const float* r, const float* q, double* partials,
+                    hipStream_t s) {
+    const int nb = blocks_for(a.ni);
+    MBMD_REQUIRE(nb <= kMaxPartials, MBMD_ERR_SHAPE, "too many rays for the partial-sum buffer");
+    hipLaunchKernelGGL(k_ray_curv, dim3(nb), dim3(kRayThreads), 0, s, model_of(a), a.ni, l, r, a.w, q,
+                       partials);
+    MBMD_LAUNCHED();
+    return nb;
+}
+
+void launch_forward_model(const RayArgs& a, const float* l, float* ybar, hipStream_t s) {
+    hipLaunchKernelGGL(k_forward_model, dim3(blocks_for(a.ni)), dim3(kRayThreads), 0, s, model_of(a), a.ni,
+                       l, ybar);
+    MBMD_LAUNCHED();
+}
+
+void launch_forward_vjp(const RayArgs& a, const float* l, const float* gbar, float* sk, hipStream_t s) {
+    hipLaunchKernelGGL(k_forward_vjp, dim3(blocks_for(a.ni)), dim3(kRayThreads), 0, s, model_of(a), a.ni,
+                       l, gbar, sk);
+    MBMD_LAUNCHED();
+}
+
+void launch_fisher(const RayArgs& a, float* W, hipStream_t s) {
+    hipLaunchKernelGGL(k_fisher, dim3(blocks_for(a.ni)), dim3(kRayThreads), 0, s, model_of(a), a.ni, a.y,
+                       a.w, W);
+    MBMD_LAUNCHED();
+}
+
+void launch_fisher_mix(int ni, int K, const float* W, const float* in, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_fisher_mix, dim3(blocks_for(ni)), dim3(kRayThreads), 0, s, ni, K, W, in, out);
+    MBMD_LAUNCHED();
+}
+
+int launch_identity_iterate(const RayArgs& a, float* x, const float* M0, int precond, int n_iter,
+                            double* partials_per_iter, int stride, hipStream_t s) {
+    const int nb = blocks_for(a.ni);
+    MBMD_REQUIRE(nb <= stride, MBMD_ERR_SHAPE, "too many rays for the partial-sum buffer");
+    hipLaunchKernelGGL(k_identity_iterate, dim3(nb), dim3(kRayThreads), 0, s, model_of(a), a.ni, x, a.y,
+                       a.w, M0, precond, n_iter, partials_per_iter, stride);
+    MBMD_LAUNCHED();
+    return nb;
+}
+
+}  // namespace mbmd

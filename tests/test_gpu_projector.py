@@ -1,0 +1,126 @@
+"""GPU parity of the distance-driven projector pair (mbmd_project /
+mbmd_backproject) against the FP64 oracle."""
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import announce, dev, host, l2rel, maxrel
+from oracle import projector as OP
+from workloads import configs as C
+
+import paper_2010_01371_amd as mb
+
+pytestmark = pytest.mark.gpu
+
+# Projection tolerance: max |A x_gpu - A x_oracle| / max |A x_oracle| <= 1e-5.
+TOL_PROJ = 1e-5
+
+GEOMS = {
+    "c1_parallel": C.make_c1().geom,
+    "fan64": C.geometry("fan", 64, 64, 2.0, 2.0, 90, 2 * np.pi, 128, 1.6, dso=300.0, dsd=550.0),
+    # ragged: non-square, bins not a multiple of the block, 45-degree views present
+    "fan_ragged": C.geometry("fan", 70, 50, 1.3, 1.7, 36, 2 * np.pi, 301, 0.9, dso=250.0, dsd=480.0,
+                             u_offset=0.37),
+    "parallel_offset": C.geometry("parallel", 40, 40, 1.0, 1.0, 8, np.pi, 67, 0.85, theta0=0.1, u_offset=-0.4),
+    "fan_c4": C.geometry("fan", 256, 256, 0.75, 0.75, 360, 2 * np.pi, 512, 1.0, dso=600.0, dsd=1100.0),
+}
+
+
+def _image(g, nmat, seed):
+    rng = np.random.default_rng(seed)
+    ny, nx = g["ny"], g["nx"]
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    smooth = np.exp(-(((xx - nx / 2) / (0.3 * nx)) ** 2 + ((yy - ny / 2) / (0.35 * ny)) ** 2))
+    return np.stack([smooth * (1 + m) + 0.3 * rng.uniform(size=(ny, nx)) for m in range(nmat)])
+
+
+@pytest.mark.parametrize("name", sorted(GEOMS))
+@pytest.mark.parametrize("nmat", [1, 3])
+def test_project_matches_oracle(name, nmat):
+    g = GEOMS[name]
+    x = _image(g, nmat, 1)
+    announce("project", name, nmat)
+    got = host(mb.project(g, dev(x)))
+    want = OP.project(g, x)
+    assert maxrel(got, want) <= TOL_PROJ, maxrel(got, want)
+
+
+@pytest.mark.parametrize("name", sorted(GEOMS))
+@pytest.mark.parametrize("nch", [1, 2, 6])
+def test_backproject_matches_oracle(name, nch):
+    g = GEOMS[name]
+    rng = np.random.default_rng(2)
+    s = rng.uniform(0.0, 1.0, size=(nch, g["n_views"], g["n_bins"]))
+    announce("backproject", name, nch)
+    got = host(mb.backproject(g, dev(s)))
+    want = OP.backproject(g, s)
+    assert maxrel(got, want) <= TOL_PROJ, maxrel(got, want)
+
+
+def test_backproject_signed_data():
+    """Mixed-sign sinograms (residual-like) keep the same normwise bound."""
+    g = GEOMS["fan64"]
+    s = np.random.default_rng(3).normal(size=(1, g["n_views"], g["n_bins"]))
+    announce("backproject signed")
+    got = host(mb.backproject(g, dev(s)))
+    want = OP.backproject(g, s)
+    assert l2rel(got, want) <= TOL_PROJ
+
+
+@pytest.mark.parametrize("name", ["fan64", "fan_ragged", "c1_parallel"])
+def test_adjoint_identity_fp32(name):
+    """<A x, y> = <x, A^T y> for the GPU pair; FP32 sums of ~1e5 terms:
+    relative mismatch bounded by 1e-5."""
+    g = GEOMS[name]
+    rng = np.random.default_rng(4)
+    x = rng.uniform(size=(1, g["ny"], g["nx"]))
+    y = rng.uniform(size=(1, g["n_views"], g["n_bins"]))
+    announce("adjoint", name)
+    Ax = host(mb.project(g, dev(x)))
+    Aty = host(mb.backproject(g, dev(y)))
+    a, b = np.sum(Ax * y), np.sum(x * Aty)
+    assert abs(a - b) / abs(a) <= 1e-5
+
+
+def test_backproject_is_deterministic():
+    g = GEOMS["fan_c4"]
+    s = dev(np.random.default_rng(5).normal(size=(2, g["n_views"], g["n_bins"])))
+    announce("determinism")
+    a = mb.backproject(g, s)
+    b = mb.backproject(g, s)
+    c = mb.backproject(g, s)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(b, c)
+
+
+def test_identity_geometry_is_a_copy():
+    g = C.identity_geometry(5, 7)
+    x = np.random.default_rng(6).normal(size=(2, 5, 7))
+    announce("identity projector")
+    np.testing.assert_array_equal(host(mb.project(g, dev(x))), x.astype(np.float32))
+    np.testing.assert_array_equal(host(mb.backproject(g, dev(x))), x.astype(np.float32))
+
+
+def test_c2_full_size_projection_pair():
+    """512^2 fan beam, 720 views x 888 bins (the benchmarked geometry): the whole
+    forward and back projection against the oracle."""
+    wl = C.make_c2(noise=True)
+    g = wl.geom
+    x = wl.x_true
+    announce("c2 project")
+    got = host(mb.project(g, dev(x)))
+    want = OP.project(g, x)
+    assert maxrel(got, want) <= TOL_PROJ, maxrel(got, want)
+    s = np.log(5e4 / np.maximum(wl.y, 1.0))
+    announce("c2 backproject")
+    gotb = host(mb.backproject(g, dev(s)))
+    wantb = OP.backproject(g, s)
+    assert maxrel(gotb, wantb) <= TOL_PROJ, maxrel(gotb, wantb)
+
+
+def test_errors_are_reported_not_raised_in_c():
+    g = dict(GEOMS["fan64"])
+    g["dso"] = 10.0            # source inside the image circle
+    with pytest.raises(RuntimeError, match="source"):
+        mb.project(g, dev(np.zeros((1, 64, 64))))
