@@ -144,10 +144,17 @@ int mbmd_project(const mbmd_geometry* geom, const float* x_dev, float* sino_dev,
  * x_dev[m] = A^T sino_dev[m] for m < n_ch (matched back projection with the
  * same weights; pixel-driven, deterministic, compensated sums over views).
  * sino_dev: [n_ch][n_views][n_bins]; x_dev: [n_ch][ny][nx] (overwritten);
- * 1 <= n_ch <= 8.  Same caching and errors as mbmd_project.
+ * 1 <= n_ch <= 10.  Same caching and errors as mbmd_project.
  */
 int mbmd_backproject(const mbmd_geometry* geom, const float* sino_dev, float* x_dev,
                      int n_ch, void* stream);
+
+/*
+ * Number of nonzeros of A (pairs of a ray and a pixel with a positive
+ * footprint overlap), counted on the device from the projector's own tables;
+ * the unit of work of one projection.  Synchronizes `stream`.
+ */
+int mbmd_projector_nnz(const mbmd_geometry* geom, long long* nnz_host, void* stream);
 
 /* ---------------------------------------------------------------- problems */
 
@@ -260,6 +267,28 @@ void mbmd_batch_destroy(mbmd_batch* batch);
  */
 int mbmd_batch_sps_step(mbmd_batch* batch, float* const* x_dev, int precond, int n_iter,
                         int use_graph, void* stream);
+
+/* ---------------------------------------------------------------- timing */
+
+/*
+ * Per-kernel timing for callers that measure the library (benchmarks,
+ * roofline reports).  While enabled, every kernel launch of the library is
+ * bracketed by two hipEvents recorded on the stream it is launched on
+ * (launches enqueued during graph capture are not instrumented).
+ * mbmd_profile_query waits for the recorded events and returns, for the
+ * kernel named `kernel` (e.g. "k_dd_back"), the number of instrumented
+ * launches and their summed duration in ms since the last reset.
+ * mbmd_profile_kernels writes the comma-separated names seen so far into
+ * `names` (capacity bytes, NUL-terminated).  mbmd_profile_select restricts
+ * the instrumentation to a comma-separated list of kernel names (NULL or ""
+ * = every kernel), so that a timed region carries only the events it needs.
+ * Errors: MBMD_ERR_ARG, MBMD_ERR_HIP.
+ */
+int mbmd_profile_enable(int on);
+int mbmd_profile_select(const char* names);
+int mbmd_profile_reset(void);
+int mbmd_profile_query(const char* kernel, long long* launches, double* total_ms);
+int mbmd_profile_kernels(char* names, size_t capacity);
 
 /* ---------------------------------------------------------------- misc */
 

@@ -48,6 +48,12 @@ _SIGNATURES = {
     "mbmd_batch_create": (c_int, [P(c_void_p), c_int, P(c_void_p)]),
     "mbmd_batch_destroy": (None, [c_void_p]),
     "mbmd_batch_sps_step": (c_int, [c_void_p, P(c_void_p), c_int, c_int, c_int, c_void_p]),
+    "mbmd_projector_nnz": (c_int, [P(Geometry), P(ctypes.c_longlong), c_void_p]),
+    "mbmd_profile_enable": (c_int, [c_int]),
+    "mbmd_profile_reset": (c_int, []),
+    "mbmd_profile_select": (c_int, [ctypes.c_char_p]),
+    "mbmd_profile_query": (c_int, [ctypes.c_char_p, P(ctypes.c_longlong), P(c_double)]),
+    "mbmd_profile_kernels": (c_int, [ctypes.c_char_p, c_size_t]),
 }
 
 _lib = None

@@ -72,6 +72,15 @@ def backproject(geom, sino):
     return out
 
 
+def projector_nnz(geom):
+    """Nonzeros of A for a geometry (counted on the GPU from the projector tables)."""
+    lib = _lib.load()
+    g = geometry_struct(geom)
+    n = ctypes.c_longlong(0)
+    check(lib.mbmd_projector_nnz(ctypes.byref(g), ctypes.byref(n), _stream()), "mbmd_projector_nnz")
+    return int(n.value)
+
+
 class Problem:
     """A PWLS / MBMD estimation problem living on the GPU."""
 
@@ -199,3 +208,36 @@ class Batch:
         arr = (ctypes.c_void_p * len(xs))(*[x.data_ptr() for x in xs])
         check(self._lib.mbmd_batch_sps_step(self._h, arr, PRECONDS[precond], int(n_iter), int(bool(use_graph)),
                                             _stream()), "mbmd_batch_sps_step")
+
+
+class KernelProfile:
+    """Per-kernel HIP-event timing of the library's launches (see mbmd_profile_*)."""
+
+    def __init__(self, only=None):
+        self._lib = _lib.load()
+        self._only = ",".join(only) if only else ""
+
+    def __enter__(self):
+        check(self._lib.mbmd_profile_reset(), "mbmd_profile_reset")
+        check(self._lib.mbmd_profile_select(self._only.encode()), "mbmd_profile_select")
+        check(self._lib.mbmd_profile_enable(1), "mbmd_profile_enable")
+        return self
+
+    def __exit__(self, *exc):
+        self._lib.mbmd_profile_enable(0)
+        self._lib.mbmd_profile_select(b"")
+        return False
+
+    def kernels(self):
+        buf = ctypes.create_string_buffer(1 << 16)
+        check(self._lib.mbmd_profile_kernels(buf, len(buf)), "mbmd_profile_kernels")
+        return [k for k in buf.value.decode().split(",") if k]
+
+    def query(self, name):
+        n = ctypes.c_longlong(0)
+        ms = ctypes.c_double(0.0)
+        check(self._lib.mbmd_profile_query(name.encode(), ctypes.byref(n), ctypes.byref(ms)), "mbmd_profile_query")
+        return int(n.value), float(ms.value)
+
+    def table(self):
+        return {k: self.query(k) for k in self.kernels()}

@@ -423,6 +423,18 @@ int mbmd_backproject(const mbmd_geometry* geom, const float* sino_dev, float* x_
     });
 }
 
+int mbmd_projector_nnz(const mbmd_geometry* geom, long long* nnz_host, void* stream) {
+    return guarded([&] {
+        MBMD_REQUIRE(geom && nnz_host, MBMD_ERR_ARG, "NULL argument");
+        validate_geometry(*geom);
+        if (geom->kind == MBMD_GEOM_IDENTITY) {
+            *nnz_host = (long long)geom->nx * geom->ny;
+            return;
+        }
+        *nnz_host = count_nonzeros(cached_geometry(*geom, kMaxMat), static_cast<hipStream_t>(stream));
+    });
+}
+
 int mbmd_problem_create(const mbmd_geometry* geom, const mbmd_spectral* sp, const mbmd_penalty* pen,
                         const float* y_dev, const float* w_dev, void* stream, mbmd_problem** out) {
     return guarded([&] {

@@ -260,12 +260,20 @@ void fill_twiddles(float2* tw, int n, hipStream_t s) {
 void launch_fft2_forward(int K, int nx, int ny, const float* in, const float* M, int sy, int sx, float2* spec,
                          const float2* twx, const float2* twy, hipStream_t s) {
     check_sizes(K, nx, ny);
-    hipLaunchKernelGGL(k_fft_rows_fwd, dim3(ny), dim3(kThreads), sizeof(float2) * K * nx, s, K, nx, ny,
+    {
+        KernelTimer kt_("k_fft_rows_fwd", s);
+        hipLaunchKernelGGL(k_fft_rows_fwd, dim3(ny), dim3(kThreads), sizeof(float2) * K * nx, s, K, nx, ny,
                        ilog2(nx), in, M, sy, sx, spec, twx);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
     const int C = col_group(K, nx, ny);
-    hipLaunchKernelGGL(k_fft_cols, dim3(nx / C), dim3(kThreads), sizeof(float2) * K * C * ny, s, K, nx, ny,
+    {
+        KernelTimer kt_("k_fft_cols", s);
+        hipLaunchKernelGGL(k_fft_cols, dim3(nx / C), dim3(kThreads), sizeof(float2) * K * C * ny, s, K, nx, ny,
                        ilog2(ny), C, spec, (const float*)nullptr, twy);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
 }
 
@@ -274,22 +282,38 @@ int launch_fourier_apply(int K, int nx, int ny, const float* in, const float* M,
                          double* partials, hipStream_t s) {
     check_sizes(K, nx, ny);
     MBMD_REQUIRE(ny <= kMaxPartials, MBMD_ERR_SHAPE, "too many rows for the partial-sum buffer");
-    hipLaunchKernelGGL(k_fft_rows_fwd, dim3(ny), dim3(kThreads), sizeof(float2) * K * nx, s, K, nx, ny,
+    {
+        KernelTimer kt_("k_fft_rows_fwd", s);
+        hipLaunchKernelGGL(k_fft_rows_fwd, dim3(ny), dim3(kThreads), sizeof(float2) * K * nx, s, K, nx, ny,
                        ilog2(nx), in, M, 0, 0, spec, twx);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
     const int C = col_group(K, nx, ny);
-    hipLaunchKernelGGL(k_fft_cols, dim3(nx / C), dim3(kThreads), sizeof(float2) * K * C * ny, s, K, nx, ny,
+    {
+        KernelTimer kt_("k_fft_cols", s);
+        hipLaunchKernelGGL(k_fft_cols, dim3(nx / C), dim3(kThreads), sizeof(float2) * K * C * ny, s, K, nx, ny,
                        ilog2(ny), C, spec, Filt, twy);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
-    hipLaunchKernelGGL(k_fft_rows_inv, dim3(ny), dim3(kThreads), sizeof(float2) * K * nx, s, K, nx, ny,
+    {
+        KernelTimer kt_("k_fft_rows_inv", s);
+        hipLaunchKernelGGL(k_fft_rows_inv, dim3(ny), dim3(kThreads), sizeof(float2) * K * nx, s, K, nx, ny,
                        ilog2(nx), spec, M, out_sign / (float)((double)nx * ny), out, g, partials, twx);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
     return ny;
 }
 
 void launch_spectrum_real_to_blocks(int K, int nj, int k_col, const float2* spec, float* blocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_spectrum_real_to_blocks, dim3((nj + kThreads - 1) / kThreads), dim3(kThreads), 0, s, K,
+    {
+        KernelTimer kt_("k_spectrum_real_to_blocks", s);
+        hipLaunchKernelGGL(k_spectrum_real_to_blocks, dim3((nj + kThreads - 1) / kThreads), dim3(kThreads), 0, s, K,
                        nj, k_col, spec, blocks);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
 }
 

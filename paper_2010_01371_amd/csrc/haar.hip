@@ -218,11 +218,19 @@ int haar_tile(int n) { return n < kTile ? n : kTile; }
 void launch_haar_forward(int K, int n, const float* in, const float* M, float* coef, float* coarse, hipStream_t s) {
     check(K, n);
     const int T = haar_tile(n), nt = n / T;
-    hipLaunchKernelGGL(k_haar_fwd_tile, dim3(nt, nt), dim3(kThreads), sizeof(float) * 2 * K * T * T, s, K, n, T,
+    {
+        KernelTimer kt_("k_haar_fwd_tile", s);
+        hipLaunchKernelGGL(k_haar_fwd_tile, dim3(nt, nt), dim3(kThreads), sizeof(float) * 2 * K * T * T, s, K, n, T,
                        in, M, coef, coarse);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
-    hipLaunchKernelGGL(k_haar_coarse_fwd, dim3(1), dim3(kThreads), sizeof(float) * 2 * K * nt * nt, s, K, n, nt,
+    {
+        KernelTimer kt_("k_haar_coarse_fwd", s);
+        hipLaunchKernelGGL(k_haar_coarse_fwd, dim3(1), dim3(kThreads), sizeof(float) * 2 * K * nt * nt, s, K, n, nt,
                        coarse, coef);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
 }
 
@@ -230,11 +238,19 @@ void launch_haar_inverse(int K, int n, const float* coef, float* coarse, const f
                          hipStream_t s) {
     check(K, n);
     const int T = haar_tile(n), nt = n / T;
-    hipLaunchKernelGGL(k_haar_coarse_inv, dim3(1), dim3(kThreads), sizeof(float) * 2 * K * nt * nt, s, K, n, nt,
+    {
+        KernelTimer kt_("k_haar_coarse_inv", s);
+        hipLaunchKernelGGL(k_haar_coarse_inv, dim3(1), dim3(kThreads), sizeof(float) * 2 * K * nt * nt, s, K, n, nt,
                        coef, coarse);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
-    hipLaunchKernelGGL(k_haar_inv_tile, dim3(nt, nt), dim3(kThreads), sizeof(float) * 2 * K * T * T, s, K, n, T,
+    {
+        KernelTimer kt_("k_haar_inv_tile", s);
+        hipLaunchKernelGGL(k_haar_inv_tile, dim3(nt, nt), dim3(kThreads), sizeof(float) * 2 * K * T * T, s, K, n, T,
                        coef, (const float*)coarse, M, out_sign, out, (const float*)nullptr, (double*)nullptr);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
 }
 
@@ -245,19 +261,31 @@ int launch_haar_apply(int K, int n, const float* in, const float* M, const float
     MBMD_REQUIRE(nt * nt <= kMaxPartials, MBMD_ERR_SHAPE, "too many Haar tiles for the partial-sum buffer");
     launch_haar_forward(K, n, in, M, coef, coarse, s);
     launch_block_apply(n * n, K, Kinv, coef, coef, 1.0f, s);
-    hipLaunchKernelGGL(k_haar_coarse_inv, dim3(1), dim3(kThreads), sizeof(float) * 2 * K * nt * nt, s, K, n, nt,
+    {
+        KernelTimer kt_("k_haar_coarse_inv", s);
+        hipLaunchKernelGGL(k_haar_coarse_inv, dim3(1), dim3(kThreads), sizeof(float) * 2 * K * nt * nt, s, K, n, nt,
                        coef, coarse);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
-    hipLaunchKernelGGL(k_haar_inv_tile, dim3(nt, nt), dim3(kThreads), sizeof(float) * 2 * K * T * T, s, K, n, T,
+    {
+        KernelTimer kt_("k_haar_inv_tile", s);
+        hipLaunchKernelGGL(k_haar_inv_tile, dim3(nt, nt), dim3(kThreads), sizeof(float) * 2 * K * T * T, s, K, n, T,
                        coef, (const float*)coarse, M, out_sign, out, g, partials);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
     return nt * nt;
 }
 
 void launch_coef_blocks(int K, int n, int k_col, const float* coef, float* blocks, hipStream_t s) {
     const int nj = n * n;
-    hipLaunchKernelGGL(k_coef_blocks, dim3((nj + kThreads - 1) / kThreads), dim3(kThreads), 0, s, K, nj, k_col, coef,
+    {
+        KernelTimer kt_("k_coef_blocks", s);
+        hipLaunchKernelGGL(k_coef_blocks, dim3((nj + kThreads - 1) / kThreads), dim3(kThreads), 0, s, K, nj, k_col, coef,
                        blocks);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
 }
 

@@ -380,17 +380,29 @@ int nblk(int n) { return (n + kThreads - 1) / kThreads; }
 }  // namespace
 
 void launch_inv_var(int n, const float* y, float* w, hipStream_t s) {
-    hipLaunchKernelGGL(k_inv_var, dim3(nblk(n)), dim3(kThreads), 0, s, n, y, w);
+    {
+        KernelTimer kt_("k_inv_var", s);
+        hipLaunchKernelGGL(k_inv_var, dim3(nblk(n)), dim3(kThreads), 0, s, n, y, w);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
 }
 
 void launch_scale_by_vec(int n, int nch, const float* in, const float* vec, float* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_scale_by_vec, dim3(nblk(n)), dim3(kThreads), 0, s, n, nch, in, vec, out);
+    {
+        KernelTimer kt_("k_scale_by_vec", s);
+        hipLaunchKernelGGL(k_scale_by_vec, dim3(nblk(n)), dim3(kThreads), 0, s, n, nch, in, vec, out);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
 }
 
 void launch_fill_double(int n, double* x, double value, hipStream_t s) {
-    hipLaunchKernelGGL(k_fill_double, dim3(nblk(n)), dim3(kThreads), 0, s, n, x, value);
+    {
+        KernelTimer kt_("k_fill_double", s);
+        hipLaunchKernelGGL(k_fill_double, dim3(nblk(n)), dim3(kThreads), 0, s, n, x, value);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
 }
 
@@ -398,7 +410,11 @@ int launch_penalty_grad(const PenaltyArgs& a, const float* x, const float* gL, c
                         float* d, double* phi_partials, hipStream_t s) {
     const int nb = nblk(a.nx * a.ny);
     MBMD_REQUIRE(nb <= kMaxPartials, MBMD_ERR_SHAPE, "image too large for the partial-sum buffer");
-    hipLaunchKernelGGL(k_penalty_grad, dim3(nb), dim3(kThreads), 0, s, a, x, gL, dL, g, d, phi_partials);
+    {
+        KernelTimer kt_("k_penalty_grad", s);
+        hipLaunchKernelGGL(k_penalty_grad, dim3(nb), dim3(kThreads), 0, s, a, x, gL, dL, g, d, phi_partials);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
     return nb;
 }
@@ -406,59 +422,99 @@ int launch_penalty_grad(const PenaltyArgs& a, const float* x, const float* gL, c
 int launch_penalty_quadform(const PenaltyArgs& a, const float* x, const float* p, double* partials,
                             hipStream_t s) {
     const int nb = nblk(a.nx * a.ny);
-    hipLaunchKernelGGL(k_penalty_quadform, dim3(nb), dim3(kThreads), 0, s, a, x, p, partials);
+    {
+        KernelTimer kt_("k_penalty_quadform", s);
+        hipLaunchKernelGGL(k_penalty_quadform, dim3(nb), dim3(kThreads), 0, s, a, x, p, partials);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
     return nb;
 }
 
 void launch_penalty_hess_add(const PenaltyArgs& a, const float* v, float* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_penalty_hess_add, dim3(nblk(a.nx * a.ny)), dim3(kThreads), 0, s, a, v, out);
+    {
+        KernelTimer kt_("k_penalty_hess_add", s);
+        hipLaunchKernelGGL(k_penalty_hess_add, dim3(nblk(a.nx * a.ny)), dim3(kThreads), 0, s, a, v, out);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
 }
 
 void launch_plain_update(int n, float* x, const float* g, const float* d, hipStream_t s) {
-    hipLaunchKernelGGL(k_plain_update, dim3(nblk(n)), dim3(kThreads), 0, s, n, x, g, d);
+    {
+        KernelTimer kt_("k_plain_update", s);
+        hipLaunchKernelGGL(k_plain_update, dim3(nblk(n)), dim3(kThreads), 0, s, n, x, g, d);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
 }
 
 void launch_axpy_alpha(int n, float* x, const float* p, const double* alpha, hipStream_t s) {
-    hipLaunchKernelGGL(k_axpy_alpha, dim3(nblk(n)), dim3(kThreads), 0, s, n, x, p, alpha);
+    {
+        KernelTimer kt_("k_axpy_alpha", s);
+        hipLaunchKernelGGL(k_axpy_alpha, dim3(nblk(n)), dim3(kThreads), 0, s, n, x, p, alpha);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
 }
 
 void launch_fill(int n, float* x, float value, hipStream_t s) {
-    hipLaunchKernelGGL(k_fill, dim3(nblk(n)), dim3(kThreads), 0, s, n, x, value);
+    {
+        KernelTimer kt_("k_fill", s);
+        hipLaunchKernelGGL(k_fill, dim3(nblk(n)), dim3(kThreads), 0, s, n, x, value);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
 }
 
 void launch_scale_copy(int n, const float* in, float* out, float scale, hipStream_t s) {
-    hipLaunchKernelGGL(k_scale_copy, dim3(nblk(n)), dim3(kThreads), 0, s, n, in, out, scale);
+    {
+        KernelTimer kt_("k_scale_copy", s);
+        hipLaunchKernelGGL(k_scale_copy, dim3(nblk(n)), dim3(kThreads), 0, s, n, in, out, scale);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
 }
 
 int launch_dot(int n, const float* a, const float* b, double* partials, hipStream_t s) {
     const int nb = nblk(n);
     MBMD_REQUIRE(nb <= kMaxPartials, MBMD_ERR_SHAPE, "vector too long for the partial-sum buffer");
-    hipLaunchKernelGGL(k_dot, dim3(nb), dim3(kThreads), 0, s, n, a, b, partials);
+    {
+        KernelTimer kt_("k_dot", s);
+        hipLaunchKernelGGL(k_dot, dim3(nb), dim3(kThreads), 0, s, n, a, b, partials);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
     return nb;
 }
 
 void launch_block_apply(int nj, int K, const float* M, const float* in, float* out, float scale, hipStream_t s) {
-    hipLaunchKernelGGL(k_block_apply, dim3(nblk(nj)), dim3(kThreads), 0, s, nj, K, M, in, out, scale);
+    {
+        KernelTimer kt_("k_block_apply", s);
+        hipLaunchKernelGGL(k_block_apply, dim3(nblk(nj)), dim3(kThreads), 0, s, nj, K, M, in, out, scale);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
 }
 
 void launch_block_invsqrt(int n, int K, const float* in_packed, float* out_packed, double power,
                           double floor_rel, const double* floor_abs_scaled, double eps, int* n_floored,
                           hipStream_t s) {
-    hipLaunchKernelGGL(k_block_invsqrt, dim3(nblk(n)), dim3(kThreads), 0, s, n, K, in_packed, out_packed,
+    {
+        KernelTimer kt_("k_block_invsqrt", s);
+        hipLaunchKernelGGL(k_block_invsqrt, dim3(nblk(n)), dim3(kThreads), 0, s, n, K, in_packed, out_packed,
                        power, floor_rel, floor_abs_scaled, eps, n_floored);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
 }
 
 void launch_block_lmax(int n, int K, const float* in_packed, double* lmax, hipStream_t s) {
-    hipLaunchKernelGGL(k_block_lmax, dim3(nblk(n)), dim3(kThreads), 0, s, n, K, in_packed, lmax);
+    {
+        KernelTimer kt_("k_block_lmax", s);
+        hipLaunchKernelGGL(k_block_lmax, dim3(nblk(n)), dim3(kThreads), 0, s, n, K, in_packed, lmax);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
 }
 
@@ -469,8 +525,12 @@ void launch_reduce_final(double* partials, const int* counts, double* scal, doub
         MBMD_REQUIRE(counts[r] >= 0 && counts[r] <= kMaxPartials, MBMD_ERR_SHAPE, "bad partial count");
         c.c[r] = counts[r];
     }
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kThreads), 0, s, partials, c, scal, trace_slot, mode,
+    {
+        KernelTimer kt_("k_reduce_final", s);
+        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kThreads), 0, s, partials, c, scal, trace_slot, mode,
                        flags);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
 }
 

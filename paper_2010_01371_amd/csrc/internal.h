@@ -44,6 +44,26 @@ __host__ __device__ inline int packed_index(int k, int l, int n) {
     return k * n - k * (k - 1) / 2 + (l - k);
 }
 
+// ---------------------------------------------------------------- optional kernel timing
+// Brackets one launch with hipEvents on its stream when profiling is enabled.
+class KernelTimer {
+  public:
+    KernelTimer(const char* name, hipStream_t s);
+    ~KernelTimer() {
+        try {
+            stop();
+        } catch (...) {
+        }
+    }
+    void stop();
+
+  private:
+    const char* name_;
+    hipStream_t s_;
+    hipEvent_t a_{}, b_{};
+    bool active_ = false;
+};
+
 // ---------------------------------------------------------------- device memory arena
 struct Arena {
     char* base = nullptr;
@@ -96,6 +116,7 @@ GeomTables& cached_geometry(const mbmd_geometry& g, int prefix_mat);
 // ---------------------------------------------------------------- projector launches
 void launch_project(const GeomTables& t, const float* x, float* sino, int n_mat, hipStream_t s);
 void launch_backproject(const GeomTables& t, const float* sino, float* x, int n_ch, hipStream_t s);
+long long count_nonzeros(const GeomTables& t, hipStream_t s);
 
 // ---------------------------------------------------------------- problem
 struct Problem {

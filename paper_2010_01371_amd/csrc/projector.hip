@@ -196,14 +196,54 @@ __global__ __launch_bounds__(kBackX* kBackY) void k_dd_back(
     }
 }
 
+// Number of (ray, pixel) pairs with a positive footprint overlap, i.e. the
+// nonzeros of A, from the same boundary table the projector uses.
+__global__ __launch_bounds__(kFwdThreads) void k_dd_count(const ViewParams* __restrict__ view,
+                                                          const float2* __restrict__ bound, int nx, int ny,
+                                                          int V, int B, unsigned long long* __restrict__ nnz) {
+    __shared__ unsigned long long sh[kFwdThreads];
+    const int v = blockIdx.y;
+    const int b = blockIdx.x * kFwdThreads + threadIdx.x;
+    unsigned long long cnt = 0;
+    if (b < B) {
+        const int frame = view[v].frame;
+        const int Nq = frame ? nx : ny;
+        const int Np = frame ? ny : nx;
+        const float2 b0 = bound[(size_t)v * (B + 1) + b];
+        const float2 b1 = bound[(size_t)v * (B + 1) + b + 1];
+        const float half = 0.5f * (float)Np;
+        const float qc = 0.5f * (float)(Nq - 1);
+        for (int q = 0; q < Nq; ++q) {
+            const float qq = (float)q - qc;
+            const float ka = fmaf(b0.y, qq, b0.x), kb = fmaf(b1.y, qq, b1.x);
+            const float lo = fmaxf(fminf(ka, kb), -half), hi = fminf(fmaxf(ka, kb), half);
+            if (hi <= lo) continue;
+            const int k0 = (int)floorf(lo + half);
+            const int k1 = (int)ceilf(hi + half) - 1;
+            cnt += (unsigned long long)max(0, min(k1, Np - 1) - max(k0, 0) + 1);
+        }
+    }
+    sh[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int off = kFwdThreads / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(nnz, sh[0]);
+}
+
 template <int NK>
 void fwd_launch(const GeomTables& t, float* sino, hipStream_t s) {
     dim3 grid((t.B + kFwdThreads - 1) / kFwdThreads, t.V);
     const size_t nj = (size_t)t.nx * t.ny;
     const float2* rows = t.prefix;
     const float2* cols = t.prefix + nj * t.prefix_mat;
-    hipLaunchKernelGGL(k_dd_forward<NK>, grid, dim3(kFwdThreads), 0, s, t.view, t.bound, t.path, rows,
+    {
+        KernelTimer kt_("k_dd_forward", s);
+        hipLaunchKernelGGL(k_dd_forward<NK>, grid, dim3(kFwdThreads), 0, s, t.view, t.bound, t.path, rows,
                        cols, t.nx, t.ny, t.V, t.B, sino);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
 }
 
@@ -214,9 +254,13 @@ void back_launch(const GeomTables& t, const float* sino, float* x, hipStream_t s
         const int Np = frame ? t.ny : t.nx;
         dim3 grid((Np + kBackX - 1) / kBackX, (Nq + kBackY - 1) / kBackY);
         const int* fv = t.frame_views + (frame ? t.n_frame_views[0] : 0);
-        hipLaunchKernelGGL(k_dd_back<NCH>, grid, dim3(kBackX, kBackY), 0, s, t.view, t.bound, t.path,
+        {
+            KernelTimer kt_("k_dd_back", s);
+            hipLaunchKernelGGL(k_dd_back<NCH>, grid, dim3(kBackX, kBackY), 0, s, t.view, t.bound, t.path,
                            fv, t.n_frame_views[frame], frame, t.nx, t.ny, t.V, t.B, sino, x,
                            frame);
+            kt_.stop();
+        }
         MBMD_LAUNCHED();
     }
 }
@@ -232,8 +276,12 @@ void launch_project(const GeomTables& t, const float* x, float* sino, int n_mat,
         if (t.n_frame_views[frame] == 0) continue;
         const int Nq = frame ? t.nx : t.ny;
         float2* out = t.prefix + (frame ? nj * t.prefix_mat : 0);
-        hipLaunchKernelGGL(k_line_prefix, dim3(Nq, n_mat), dim3(kScanThreads), 0, s, x, out, t.nx,
+        {
+            KernelTimer kt_("k_line_prefix", s);
+            hipLaunchKernelGGL(k_line_prefix, dim3(Nq, n_mat), dim3(kScanThreads), 0, s, x, out, t.nx,
                            t.ny, frame);
+            kt_.stop();
+        }
         MBMD_LAUNCHED();
     }
     switch (n_mat) {
@@ -242,6 +290,25 @@ void launch_project(const GeomTables& t, const float* x, float* sino, int n_mat,
         case 3: fwd_launch<3>(t, sino, s); break;
         default: fwd_launch<4>(t, sino, s); break;
     }
+}
+
+long long count_nonzeros(const GeomTables& t, hipStream_t s) {
+    unsigned long long* d = nullptr;
+    MBMD_HIP(hipMalloc(&d, sizeof(unsigned long long)));
+    unsigned long long h = 0;
+    try {
+        MBMD_HIP(hipMemcpyAsync(d, &h, sizeof(h), hipMemcpyHostToDevice, s));
+        dim3 grid((t.B + kFwdThreads - 1) / kFwdThreads, t.V);
+        hipLaunchKernelGGL(k_dd_count, grid, dim3(kFwdThreads), 0, s, t.view, t.bound, t.nx, t.ny, t.V, t.B, d);
+        MBMD_LAUNCHED();
+        MBMD_HIP(hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s));
+        MBMD_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+        (void)hipFree(d);
+        throw;
+    }
+    MBMD_HIP(hipFree(d));
+    return (long long)h;
 }
 
 void launch_backproject(const GeomTables& t, const float* sino, float* x, int n_ch, hipStream_t s) {

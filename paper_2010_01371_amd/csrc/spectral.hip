@@ -367,8 +367,12 @@ int launch_ray_grad(const RayArgs& a, const float* l, float* u, float* v, float*
                     hipStream_t s) {
     const int nb = blocks_for(a.ni);
     MBMD_REQUIRE(nb <= kMaxPartials, MBMD_ERR_SHAPE, "too many rays for the partial-sum buffer");
-    hipLaunchKernelGGL(k_ray_grad, dim3(nb), dim3(kRayThreads), 0, s, model_of(a), a.ni, l, a.y, a.w,
+    {
+        KernelTimer kt_("k_ray_grad", s);
+        hipLaunchKernelGGL(k_ray_grad, dim3(nb), dim3(kRayThreads), 0, s, model_of(a), a.ni, l, a.y, a.w,
                        a.gammaA, u, v, r, phi_partials);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
     return nb;
 }
@@ -377,32 +381,52 @@ int launch_ray_curv(const RayArgs& a, const float* l, const float* r, const floa
                     hipStream_t s) {
     const int nb = blocks_for(a.ni);
     MBMD_REQUIRE(nb <= kMaxPartials, MBMD_ERR_SHAPE, "too many rays for the partial-sum buffer");
-    hipLaunchKernelGGL(k_ray_curv, dim3(nb), dim3(kRayThreads), 0, s, model_of(a), a.ni, l, r, a.w, q,
+    {
+        KernelTimer kt_("k_ray_curv", s);
+        hipLaunchKernelGGL(k_ray_curv, dim3(nb), dim3(kRayThreads), 0, s, model_of(a), a.ni, l, r, a.w, q,
                        partials);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
     return nb;
 }
 
 void launch_forward_model(const RayArgs& a, const float* l, float* ybar, hipStream_t s) {
-    hipLaunchKernelGGL(k_forward_model, dim3(blocks_for(a.ni)), dim3(kRayThreads), 0, s, model_of(a), a.ni,
+    {
+        KernelTimer kt_("k_forward_model", s);
+        hipLaunchKernelGGL(k_forward_model, dim3(blocks_for(a.ni)), dim3(kRayThreads), 0, s, model_of(a), a.ni,
                        l, ybar);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
 }
 
 void launch_forward_vjp(const RayArgs& a, const float* l, const float* gbar, float* sk, hipStream_t s) {
-    hipLaunchKernelGGL(k_forward_vjp, dim3(blocks_for(a.ni)), dim3(kRayThreads), 0, s, model_of(a), a.ni,
+    {
+        KernelTimer kt_("k_forward_vjp", s);
+        hipLaunchKernelGGL(k_forward_vjp, dim3(blocks_for(a.ni)), dim3(kRayThreads), 0, s, model_of(a), a.ni,
                        l, gbar, sk);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
 }
 
 void launch_fisher(const RayArgs& a, float* W, hipStream_t s) {
-    hipLaunchKernelGGL(k_fisher, dim3(blocks_for(a.ni)), dim3(kRayThreads), 0, s, model_of(a), a.ni, a.y,
+    {
+        KernelTimer kt_("k_fisher", s);
+        hipLaunchKernelGGL(k_fisher, dim3(blocks_for(a.ni)), dim3(kRayThreads), 0, s, model_of(a), a.ni, a.y,
                        a.w, W);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
 }
 
 void launch_fisher_mix(int ni, int K, const float* W, const float* in, float* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_fisher_mix, dim3(blocks_for(ni)), dim3(kRayThreads), 0, s, ni, K, W, in, out);
+    {
+        KernelTimer kt_("k_fisher_mix", s);
+        hipLaunchKernelGGL(k_fisher_mix, dim3(blocks_for(ni)), dim3(kRayThreads), 0, s, ni, K, W, in, out);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
 }
 
@@ -410,8 +434,12 @@ int launch_identity_iterate(const RayArgs& a, float* x, const float* M0, int pre
                             double* partials_per_iter, int stride, hipStream_t s) {
     const int nb = blocks_for(a.ni);
     MBMD_REQUIRE(nb <= stride, MBMD_ERR_SHAPE, "too many rays for the partial-sum buffer");
-    hipLaunchKernelGGL(k_identity_iterate, dim3(nb), dim3(kRayThreads), 0, s, model_of(a), a.ni, x, a.y,
+    {
+        KernelTimer kt_("k_identity_iterate", s);
+        hipLaunchKernelGGL(k_identity_iterate, dim3(nb), dim3(kRayThreads), 0, s, model_of(a), a.ni, x, a.y,
                        a.w, M0, precond, n_iter, partials_per_iter, stride);
+        kt_.stop();
+    }
     MBMD_LAUNCHED();
     return nb;
 }
