@@ -6,6 +6,7 @@
 // sums are reduced by one final kernel that also forms the step size alpha on
 // the device, so an iteration has no host synchronisation and can be captured
 // in a hipGraph (batched form).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <exception>
@@ -404,7 +405,7 @@ int mbmd_project(const mbmd_geometry* geom, const float* x_dev, float* sino_dev,
                                     hipMemcpyDeviceToDevice, s));
             return;
         }
-        launch_project(cached_geometry(*geom, kMaxMat), x_dev, sino_dev, n_mat, s);
+        launch_project(cached_geometry(*geom, kMaxMat, kMaxBackCh), x_dev, sino_dev, n_mat, s);
     });
 }
 
@@ -419,7 +420,7 @@ int mbmd_backproject(const mbmd_geometry* geom, const float* sino_dev, float* x_
                                     hipMemcpyDeviceToDevice, s));
             return;
         }
-        launch_backproject(cached_geometry(*geom, kMaxMat), sino_dev, x_dev, n_ch, s);
+        launch_backproject(cached_geometry(*geom, kMaxMat, kMaxBackCh), sino_dev, x_dev, n_ch, s);
     });
 }
 
@@ -431,7 +432,7 @@ int mbmd_projector_nnz(const mbmd_geometry* geom, long long* nnz_host, void* str
             *nnz_host = (long long)geom->nx * geom->ny;
             return;
         }
-        *nnz_host = count_nonzeros(cached_geometry(*geom, kMaxMat), static_cast<hipStream_t>(stream));
+        *nnz_host = count_nonzeros(cached_geometry(*geom, kMaxMat, kMaxBackCh), static_cast<hipStream_t>(stream));
     });
 }
 
@@ -474,7 +475,7 @@ int mbmd_problem_create(const mbmd_geometry* geom, const mbmd_spectral* sp, cons
                      "problem too large for the partial-sum buffer");
         if (!P->identity) {
             P->geom = new GeomTables();
-            build_geometry(*geom, *P->geom, P->K);
+            build_geometry(*geom, *P->geom, P->K, std::max(P->npk, 2 * P->K));
         }
         carve(*P);                                // sizing pass
         P->arena.reserve(P->arena.used + 4096);

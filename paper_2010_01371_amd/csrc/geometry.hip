@@ -56,7 +56,7 @@ Ray boundary_ray(const mbmd_geometry& g, double c, double s, double u) {
 
 }  // namespace
 
-void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat) {
+void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int back_ch) {
     validate_geometry(g);
     MBMD_REQUIRE(g.kind != MBMD_GEOM_IDENTITY, MBMD_ERR_ARG, "identity geometry has no projector tables");
     t.g = g;
@@ -70,18 +70,26 @@ void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat) {
     std::vector<float> path((size_t)V * B);
     std::vector<int> views[2];
 
+    // Per-view tables are stored in "slot" order: the views sweeping rows first,
+    // then the views sweeping columns; frame_views maps a slot to its view.
+    std::vector<int> frame_of(V);
     for (int v = 0; v < V; ++v) {
         const double th = g.theta0 + v * g.dtheta;
-        const double c = std::cos(th), s = std::sin(th);
-        const int frame = std::fabs(c) >= std::fabs(s) ? 0 : 1;
+        const int frame = std::fabs(std::cos(th)) >= std::fabs(std::sin(th)) ? 0 : 1;
+        frame_of[v] = frame;
         views[frame].push_back(v);
+    }
+    std::vector<int> fv(views[0]);
+    fv.insert(fv.end(), views[1].begin(), views[1].end());
+    for (int slot = 0; slot < V; ++slot) {
+        const int v = fv[slot];
+        const double th = g.theta0 + v * g.dtheta;
+        const double c = std::cos(th), s = std::sin(th);
+        const int frame = frame_of[v];
         const int ia = frame == 0 ? 1 : 0;        // line-normal axis (y for row sweeps)
         const int it = frame == 0 ? 0 : 1;        // along-line axis
-        const int Nq = frame == 0 ? g.ny : g.nx;
         const double dq = frame == 0 ? g.dy : g.dx;
         const double dp = frame == 0 ? g.dx : g.dy;
-        const double qc = 0.5 * (Nq - 1);
-        (void)qc;
         for (int bb = 0; bb <= B; ++bb) {
             const double u = (bb - 0.5 * B) * g.du + g.u_offset;
             const Ray r = boundary_ray(g, c, s, u);
@@ -94,13 +102,13 @@ void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat) {
             //   t = P_t + (a - P_a) * slope
             const double C0 = (P[it] - P[ia] * slope) / dp;
             const double C1 = dq * slope / dp;
-            bound[(size_t)v * (B + 1) + bb] = make_float2((float)C0, (float)C1);
+            bound[(size_t)slot * (B + 1) + bb] = make_float2((float)C0, (float)C1);
         }
         for (int b = 0; b < B; ++b) {
             const double u = (b - 0.5 * (B - 1)) * g.du + g.u_offset;
             const Ray r = boundary_ray(g, c, s, u);
             const double R[2] = {r.rx, r.ry};
-            path[(size_t)v * B + b] = (float)(dq * std::hypot(R[0], R[1]) / std::fabs(R[ia]));
+            path[(size_t)slot * B + b] = (float)(dq * std::hypot(R[0], R[1]) / std::fabs(R[ia]));
         }
         // fractional bin index of the point at along position K (pixels, centred)
         // on line qq: world point with along coordinate K dp and normal qq dq.
@@ -124,28 +132,33 @@ void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat) {
             p.dq = (float)(g.du * d[ia] * dq);
         }
         p.frame = frame;
-        vp[v] = p;
+        p.view = v;
+        vp[slot] = p;
     }
     t.n_frame_views[0] = (int)views[0].size();
     t.n_frame_views[1] = (int)views[1].size();
-    std::vector<int> fv(views[0]);
-    fv.insert(fv.end(), views[1].begin(), views[1].end());
 
     const size_t nj = (size_t)g.nx * g.ny;
     t.prefix_mat = prefix_mat;
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
     const size_t b_view = al(sizeof(ViewParams) * V), b_bound = al(sizeof(float2) * bound.size()),
                  b_path = al(sizeof(float) * path.size()), b_fv = al(sizeof(int) * V),
-                 b_pre = al(sizeof(float2) * nj * 2 * prefix_mat);
+                 b_pre = al(sizeof(float2) * prefix_elems(g.nx, g.ny) * prefix_mat),
+                 b_det = al(sizeof(double) * (size_t)back_ch * V * (B + 1)),
+                 b_tmp = al(sizeof(float) * (size_t)back_ch * nj);
+    t.back_ch = back_ch;
     char* base = nullptr;
     MBMD_HIP(hipGetDevice(&t.device));
-    MBMD_HIP(hipMalloc(&base, b_view + b_bound + b_path + b_fv + b_pre));
+    MBMD_HIP(hipMalloc(&base, b_view + b_bound + b_path + b_fv + b_pre + b_det + b_tmp));
     t.mem = base;
     t.view = reinterpret_cast<ViewParams*>(base);
     t.bound = reinterpret_cast<float2*>(base + b_view);
     t.path = reinterpret_cast<float*>(base + b_view + b_bound);
     t.frame_views = reinterpret_cast<int*>(base + b_view + b_bound + b_path);
     t.prefix = prefix_mat ? reinterpret_cast<float2*>(base + b_view + b_bound + b_path + b_fv) : nullptr;
+    char* after_pre = base + b_view + b_bound + b_path + b_fv + b_pre;
+    t.det_prefix = back_ch ? reinterpret_cast<double*>(after_pre) : nullptr;
+    t.back_tmp = back_ch ? reinterpret_cast<float*>(after_pre + b_det) : nullptr;
     MBMD_HIP(hipMemcpy(t.view, vp.data(), sizeof(ViewParams) * V, hipMemcpyHostToDevice));
     MBMD_HIP(hipMemcpy(t.bound, bound.data(), sizeof(float2) * bound.size(), hipMemcpyHostToDevice));
     MBMD_HIP(hipMemcpy(t.path, path.data(), sizeof(float) * path.size(), hipMemcpyHostToDevice));
@@ -162,7 +175,7 @@ std::mutex g_cache_mu;
 std::map<std::string, GeomTables*> g_cache;
 }
 
-GeomTables& cached_geometry(const mbmd_geometry& g, int prefix_mat) {
+GeomTables& cached_geometry(const mbmd_geometry& g, int prefix_mat, int back_ch) {
     int dev = 0;
     MBMD_HIP(hipGetDevice(&dev));
     // key from the fields (the struct has padding bytes)
@@ -172,7 +185,8 @@ GeomTables& cached_geometry(const mbmd_geometry& g, int prefix_mat) {
     std::string key(reinterpret_cast<const char*>(f), sizeof(f));
     std::lock_guard<std::mutex> lock(g_cache_mu);
     auto it = g_cache.find(key);
-    if (it != g_cache.end() && it->second->prefix_mat >= prefix_mat) return *it->second;
+    if (it != g_cache.end() && it->second->prefix_mat >= prefix_mat && it->second->back_ch >= back_ch)
+        return *it->second;
     if (it != g_cache.end()) {
         // a larger prefix scratch is needed: rebuild (hipFree waits for the device)
         free_geometry(*it->second);
@@ -181,7 +195,7 @@ GeomTables& cached_geometry(const mbmd_geometry& g, int prefix_mat) {
     }
     GeomTables* t = new GeomTables();
     try {
-        build_geometry(g, *t, prefix_mat < 1 ? 1 : prefix_mat);
+        build_geometry(g, *t, prefix_mat < 1 ? 1 : prefix_mat, back_ch < 1 ? 1 : back_ch);
     } catch (...) {
         delete t;
         throw;

@@ -90,28 +90,36 @@ struct ViewParams {
     // num = n0 + nK K + nq qq, den = d0 + dK K + dq qq, qq = q - (Nq-1)/2
     float n0, nK, nq, d0, dK, dq;
     int frame;
-    int pad;
+    int view;          // original view index of this slot
 };
 
+// Per-view tables are in slot order (views of frame 0, then of frame 1).
 struct GeomTables {
     mbmd_geometry g{};
     int V = 0, B = 0, nx = 0, ny = 0;
     int n_frame_views[2] = {0, 0};
-    ViewParams* view = nullptr;      // [V]
-    float2* bound = nullptr;         // [V][B+1]: boundary b' at line q is C0 + C1 qq
-    float* path = nullptr;           // [V][B]: path length per sweep line of the bin-centre ray
-    int* frame_views = nullptr;      // [V]: views of frame 0, then views of frame 1
-    float2* prefix = nullptr;        // scratch: [n_mat][ny][nx] + [n_mat][nx][ny] exclusive prefix sums
+    ViewParams* view = nullptr;      // [slot]
+    float2* bound = nullptr;         // [slot][B+1]: boundary b' at line q is C0 + C1 qq
+    float* path = nullptr;           // [slot][B]: path length per sweep line of the bin-centre ray
+    int* frame_views = nullptr;      // [slot] -> view index
+    // scratch: line prefix sums, frame 0 lines [n_mat][ny][nx+1] then frame 1 lines
+    // [n_mat][nx][ny+1]; entry Np of a line holds (line total, 0)
+    float2* prefix = nullptr;
     int prefix_mat = 0;
+    double* det_prefix = nullptr;    // scratch: [back_ch][V][B+1] detector prefix sums (FP64)
+    float* back_tmp = nullptr;       // scratch: [back_ch][nx][ny] column-sweep part of a back projection
+    int back_ch = 0;
     void* mem = nullptr;
     int device = -1;
 };
 
+inline size_t prefix_elems(int nx, int ny) { return (size_t)ny * (nx + 1) + (size_t)nx * (ny + 1); }
+
 // Builds the tables in FP64 on the host and uploads them (synchronous copy).
-void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat);
+void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int back_ch);
 void free_geometry(GeomTables& t);
 void validate_geometry(const mbmd_geometry& g);
-GeomTables& cached_geometry(const mbmd_geometry& g, int prefix_mat);
+GeomTables& cached_geometry(const mbmd_geometry& g, int prefix_mat, int back_ch);
 
 // ---------------------------------------------------------------- projector launches
 void launch_project(const GeomTables& t, const float* x, float* sino, int n_mat, hipStream_t s);
