@@ -135,14 +135,15 @@ typedef struct mbmd_batch mbmd_batch;
  * cached per device; concurrent calls with the same geometry on different
  * streams race on the cached scratch buffer.
  * Errors: MBMD_ERR_ARG (NULL pointer, bad sizes), MBMD_ERR_SHAPE (fan source
- * inside the image circle, n_mat out of range), MBMD_ERR_HIP.
+ * inside the image circle or between the sweep lines of a view, a bin
+ * boundary parallel to the sweep lines, n_mat out of range), MBMD_ERR_HIP.
  */
 int mbmd_project(const mbmd_geometry* geom, const float* x_dev, float* sino_dev,
                  int n_mat, void* stream);
 
 /*
  * x_dev[m] = A^T sino_dev[m] for m < n_ch (matched back projection with the
- * same weights; pixel-driven, deterministic, compensated sums over views).
+ * same weights; pixel-driven, deterministic, FP64 sums over views).
  * sino_dev: [n_ch][n_views][n_bins]; x_dev: [n_ch][ny][nx] (overwritten);
  * 1 <= n_ch <= 10.  Same caching and errors as mbmd_project.
  */

@@ -30,7 +30,7 @@ void validate_geometry(const mbmd_geometry& g) {
                      "identity geometry needs nx == n_bins and ny == n_views");
         return;
     }
-    MBMD_REQUIRE(g.nx <= 8192 && g.ny <= 8192 && g.n_bins <= 65536 && g.n_views <= 65536,
+    MBMD_REQUIRE(g.nx <= 8192 && g.ny <= 8192 && g.n_bins <= 65535 && g.n_views <= 65535,
                  MBMD_ERR_SHAPE, "geometry too large");
     MBMD_REQUIRE(g.dx > 0 && g.dy > 0 && g.du > 0, MBMD_ERR_ARG, "pixel and bin sizes must be positive");
     if (g.kind == MBMD_GEOM_FAN_FLAT) {
@@ -90,6 +90,7 @@ void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int b
         const int it = frame == 0 ? 0 : 1;        // along-line axis
         const double dq = frame == 0 ? g.dy : g.dx;
         const double dp = frame == 0 ? g.dx : g.dy;
+        std::vector<double> C0s(B + 1), C1s(B + 1);
         for (int bb = 0; bb <= B; ++bb) {
             const double u = (bb - 0.5 * B) * g.du + g.u_offset;
             const Ray r = boundary_ray(g, c, s, u);
@@ -103,7 +104,22 @@ void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int b
             const double C0 = (P[it] - P[ia] * slope) / dp;
             const double C1 = dq * slope / dp;
             bound[(size_t)slot * (B + 1) + bb] = make_float2((float)C0, (float)C1);
+            C0s[bb] = C0;
+            C1s[bb] = C1;
         }
+        // Orientation: the sign of the bin widths K(b+1) - K(b).  They are affine in
+        // the line coordinate, so checking the first and last sweep line covers every
+        // line; a sign change would need the source inside the slab of sweep lines.
+        const double qmax = 0.5 * ((frame == 0 ? g.ny : g.nx) - 1);
+        int n_pos = 0, n_neg = 0;
+        for (int b = 0; b < B; ++b)
+            for (double qq : {-qmax, qmax}) {
+                const double w = (C0s[b + 1] - C0s[b]) + (C1s[b + 1] - C1s[b]) * qq;
+                n_pos += w > 0.0;
+                n_neg += w < 0.0;
+            }
+        MBMD_REQUIRE(n_pos == 0 || n_neg == 0, MBMD_ERR_SHAPE,
+                     "fan beam: the source lies between the sweep lines of a view (source too close)");
         for (int b = 0; b < B; ++b) {
             const double u = (b - 0.5 * (B - 1)) * g.du + g.u_offset;
             const Ray r = boundary_ray(g, c, s, u);
@@ -131,8 +147,8 @@ void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int b
             p.dK = (float)(g.du * d[it] * dp);
             p.dq = (float)(g.du * d[ia] * dq);
         }
-        p.frame = frame;
-        p.view = v;
+        p.orient = n_neg == 0 ? 1.0f : -1.0f;
+        p.view_frame = v | (frame << 16);
         vp[slot] = p;
     }
     t.n_frame_views[0] = (int)views[0].size();

@@ -89,9 +89,11 @@ struct ViewParams {
     // fractional bin index of the point (K, q): beta = num / den with
     // num = n0 + nK K + nq qq, den = d0 + dK K + dq qq, qq = q - (Nq-1)/2
     float n0, nK, nq, d0, dK, dq;
-    int frame;
-    int view;          // original view index of this slot
+    float orient;      // +1 when bin boundaries run along +K on every sweep line, else -1
+    int view_frame;    // original view index | frame << 16
 };
+__host__ __device__ inline int vp_view(const ViewParams& p) { return p.view_frame & 0xffff; }
+__host__ __device__ inline int vp_frame(const ViewParams& p) { return p.view_frame >> 16; }
 
 // Per-view tables are in slot order (views of frame 0, then of frame 1).
 struct GeomTables {

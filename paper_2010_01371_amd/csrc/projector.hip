@@ -18,8 +18,8 @@
 // C_v[b] = sum_{b'<b} sino * path.  The back projected detector signal on a
 // sweep line is piecewise constant in the along-line position K, with
 // cumulative integral H(K) = C[b] + (C[b+1] - C[b]) (K - K_b)/(K_b+1 - K_b)
-// for K in bin b, so a pixel [K, K+1] receives H(K+1) - H(K) (times the
-// orientation sign).  One lane per pixel EDGE: 63 pixels per wavefront, the
+// for K in bin b, so a pixel [K, K+1] receives H(K+1) - H(K); the view's
+// orientation sign is folded into C.  One lane per pixel EDGE: 63 pixels per wavefront, the
 // right edge taken from the neighbour lane.  The bin holding an edge comes
 // from the rational map K -> fractional bin index; the fraction inside the
 // bin is clamped to [0, 1], which keeps H continuous when that map is off by
@@ -53,16 +53,16 @@ constexpr int kBufferWord3 = 0x00020000;     // raw buffer resource, gfx9 family
 
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// Value held by lane + 1 (DPP wave shift left by one lane; lane 63 keeps its own).
+// Value held by lane + 1 (DPP wave shift left by one lane; lane 63 reads 0 and
+// its result is never stored).
 __device__ __forceinline__ float next_lane(float v) {
     const int i = __builtin_bit_cast(int, v);
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(i, i, 0x130, 0xf, 0xf, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(i, 0x130, 0xf, 0xf, true));
 }
 __device__ __forceinline__ double next_lane(double v) {
     const long long i = __builtin_bit_cast(long long, v);
-    const int lo = (int)(i & 0xffffffffll), hi = (int)(i >> 32);
-    const int nlo = __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false);
-    const int nhi = __builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false);
+    const int nlo = __builtin_amdgcn_mov_dpp((int)(i & 0xffffffffll), 0x130, 0xf, 0xf, true);
+    const int nhi = __builtin_amdgcn_mov_dpp((int)(i >> 32), 0x130, 0xf, 0xf, true);
     return __builtin_bit_cast(double, ((long long)nhi << 32) | (unsigned int)nlo);
 }
 
@@ -123,13 +123,15 @@ __global__ __launch_bounds__(kScanThreads) void k_line_prefix(const float* __res
     if (threadIdx.x == kScanThreads - 1) dst[Np] = make_float2((float)part[kScanThreads - 1], 0.0f);
 }
 
-// Per slot and channel: C[b] = sum_{b'<b} sino[b'] path[b'] (FP64), b = 0..B.
+// Per slot and channel: C[b] = orient * sum_{b'<b} sino[b'] path[b'] (FP64),
+// b = 0..B; the view's orientation sign makes H(K+1) - H(K) the pixel value.
 __global__ __launch_bounds__(kScanThreads) void k_detector_prefix(const float* __restrict__ sino,
                                                                    const float* __restrict__ path,
-                                                                   const int* __restrict__ slot_view, int V,
+                                                                   const ViewParams* __restrict__ view, int V,
                                                                    int B, double* __restrict__ C) {
     const int slot = blockIdx.x, ch = blockIdx.y;
-    const float* s = sino + ((size_t)ch * V + slot_view[slot]) * B;
+    const double orient = (double)view[slot].orient;
+    const float* s = sino + ((size_t)ch * V + vp_view(view[slot])) * B;
     const float* pa = path + (size_t)slot * B;
     double* dst = C + ((size_t)ch * V + slot) * (B + 1);
     __shared__ double part[kScanThreads];
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(kScanThreads) void k_detector_prefix(const float* _
     double acc = 0.0;
     for (int i = 0; i < per; ++i) {
         const int b = b0 + i;
-        if (b < B) acc += (double)s[b] * (double)pa[b];
+        if (b < B) acc += orient * ((double)s[b] * (double)pa[b]);
     }
     part[threadIdx.x] = acc;
     __syncthreads();
@@ -153,7 +155,7 @@ __global__ __launch_bounds__(kScanThreads) void k_detector_prefix(const float* _
         const int b = b0 + i;
         if (b < B) {
             dst[b] = run;
-            run += (double)s[b] * (double)pa[b];
+            run += orient * ((double)s[b] * (double)pa[b]);
         }
     }
     if (threadIdx.x == kScanThreads - 1) dst[B] = part[kScanThreads - 1];
@@ -223,7 +225,7 @@ __global__ __launch_bounds__(kThreads) void k_dd_forward(const ViewParams* __res
     }
     for (; q < Nq; ++q) line_step(q);
     if (lane < kPerWave && edge < B) {
-        const int v = view[slot].view;
+        const int v = vp_view(view[slot]);
         const float L = path[(size_t)slot * B + edge];
 #pragma unroll
         for (int m = 0; m < NK; ++m) sino[((size_t)m * V + v) * B + edge] = acc[m] * L;
@@ -263,19 +265,16 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const ViewParams* __restri
         const ViewParams vp = view[slot];
         const float num = fmaf(vp.nK, K, fmaf(vp.nq, qq, vp.n0));
         const float den = fmaf(vp.dK, K, fmaf(vp.dq, qq, vp.d0));
-        int b = (int)floorf(num * fast_rcp(den));
-        b = min(max(b, 0), B - 1);
-        const float4 cb = load_f4(tb, b * (int)sizeof(float2), slot * row);   // boundaries b, b+1
+        const int b = min((int)fmaxf(num * fast_rcp(den), 0.0f), B - 1);   // >= 0: truncation is floor
+        const float4 cb = load_f4(tb, b * (int)sizeof(float2), slot * row);    // boundaries b, b+1
         const float kb = fmaf(cb.y, qq, cb.x);
         const float kb1 = fmaf(cb.w, qq, cb.z);
-        const float w = kb1 - kb;
-        const float fr = fminf(fmaxf((K - kb) * fast_rcp(w), 0.0f), 1.0f);
-        const double sgn = w > 0.0f ? 1.0 : -1.0;
+        const float fr = fminf(fmaxf((K - kb) * fast_rcp(kb1 - kb), 0.0f), 1.0f);
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             const double2 h = load_d2(tc, b * (int)sizeof(double), (c * V + slot) * crow);
             const double H = fma(h.y - h.x, (double)fr, h.x);
-            acc[c] = fma(sgn, next_lane(H) - H, acc[c]);
+            acc[c] += next_lane(H) - H;
         }
     };
     int is = 0;
@@ -344,7 +343,7 @@ void back_launch(const GeomTables& t, const float* sino, float* x, hipStream_t s
     {
         KernelTimer kt_("k_detector_prefix", s);
         hipLaunchKernelGGL(k_detector_prefix, dim3(t.V, NCH), dim3(kScanThreads), 0, s, sino, t.path,
-                           t.frame_views, t.V, t.B, t.det_prefix);
+                           t.view, t.V, t.B, t.det_prefix);
         kt_.stop();
     }
     MBMD_LAUNCHED();
@@ -379,7 +378,7 @@ __global__ __launch_bounds__(kThreads) void k_dd_count(const ViewParams* __restr
     const int b = blockIdx.x * kThreads + threadIdx.x;
     unsigned long long cnt = 0;
     if (b < B) {
-        const int frame = view[slot].frame;
+        const int frame = vp_frame(view[slot]);
         const int Nq = frame ? nx : ny;
         const int Np = frame ? ny : nx;
         const float2 b0 = bound[(size_t)slot * (B + 1) + b];
