@@ -4,13 +4,16 @@
 //   * the sweep frame (rows when |cos theta| >= |sin theta|, else columns),
 //     decided here in FP64;
 //   * for every bin boundary b' = 0..B, the along-line position of the
-//     boundary ray on sweep line q as C0 + C1 (q - (Nq-1)/2), in pixel units
-//     centred on the image (intersections of a straight line with a family of
-//     parallel lines are affine in the line index);
+//     boundary ray on sweep line q as X0 + X1 q, in pixel units from the
+//     line's first pixel edge (intersections of a straight line with a family
+//     of parallel lines are affine in the line index);
 //   * for every bin, the path length per sweep line of the bin-centre ray,
 //     line spacing / |cos(angle to the line normal)|;
-//   * the rational map from a point (K, q) back to its fractional bin index,
-//     used by the pixel-driven back projector to find the bins a pixel sees.
+//   * the rational map from a point (K, q), K centred on the image, back to
+//     its fractional bin index,
+//     used by the pixel-driven back projector to find the bins a pixel sees,
+//     and per sweep line its restriction to that line with the factor that
+//     turns a residual of the map into the fraction of the bin.
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -67,6 +70,8 @@ void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int b
     const int V = t.V, B = t.B;
     std::vector<ViewParams> vp(V);
     std::vector<float2> bound((size_t)V * (B + 1));
+    const int QL = g.nx > g.ny ? g.nx : g.ny;
+    std::vector<float4> line((size_t)QL * V * 2, make_float4(0.f, 0.f, 0.f, 0.f));
     std::vector<float> path((size_t)V * B);
     std::vector<int> views[2];
 
@@ -103,7 +108,8 @@ void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int b
             //   t = P_t + (a - P_a) * slope
             const double C0 = (P[it] - P[ia] * slope) / dp;
             const double C1 = dq * slope / dp;
-            bound[(size_t)slot * (B + 1) + bb] = make_float2((float)C0, (float)C1);
+            const double X0 = C0 + 0.5 * (frame == 0 ? g.nx : g.ny) - C1 * 0.5 * ((frame == 0 ? g.ny : g.nx) - 1);
+            bound[(size_t)slot * (B + 1) + bb] = make_float2((float)X0, (float)C1);
             C0s[bb] = C0;
             C1s[bb] = C1;
         }
@@ -130,22 +136,50 @@ void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int b
         // on line qq: world point with along coordinate K dp and normal qq dq.
         const double e[2] = {c, s}, d[2] = {-s, c};
         const double u0 = -0.5 * B * g.du + g.u_offset;     // left edge of bin 0
-        ViewParams p{};
+        double n0, nK, nq, d0, dK, dqq;
         if (g.kind == MBMD_GEOM_PARALLEL) {
-            p.n0 = (float)(-u0 / g.du);
-            p.nK = (float)(e[it] * dp / g.du);
-            p.nq = (float)(e[ia] * dq / g.du);
-            p.d0 = 1.0f;
-            p.dK = 0.0f;
-            p.dq = 0.0f;
+            n0 = -u0 / g.du;
+            nK = e[it] * dp / g.du;
+            nq = e[ia] * dq / g.du;
+            d0 = 1.0;
+            dK = 0.0;
+            dqq = 0.0;
         } else {
             // u = dsd (e.X) / (d.X + dso);  beta = (u - u0) / du
-            p.n0 = (float)(-u0 * g.dso);
-            p.nK = (float)((g.dsd * e[it] - u0 * d[it]) * dp);
-            p.nq = (float)((g.dsd * e[ia] - u0 * d[ia]) * dq);
-            p.d0 = (float)(g.du * g.dso);
-            p.dK = (float)(g.du * d[it] * dp);
-            p.dq = (float)(g.du * d[ia] * dq);
+            n0 = -u0 * g.dso;
+            nK = (g.dsd * e[it] - u0 * d[it]) * dp;
+            nq = (g.dsd * e[ia] - u0 * d[ia]) * dq;
+            d0 = g.du * g.dso;
+            dK = g.du * d[it] * dp;
+            dqq = g.du * d[ia] * dq;
+        }
+        ViewParams p{};
+        p.n0 = (float)n0;
+        p.nK = (float)nK;
+        p.nq = (float)nq;
+        p.d0 = (float)d0;
+        p.dK = (float)dK;
+        p.dq = (float)dqq;
+        // Per sweep line: with N = n0 + nq qq and D = d0 + dqq qq the bin index is
+        // beta(K) = (N + nK K) / (D + dK K).  Boundary b sits at K_b with
+        // beta(K_b) = b; the map is projective, so
+        //   (K - K_b) / (K_{b+1} - K_b) = (num - b den) (nK - (b+1) dK) / Delta,
+        // Delta = D nK - N dK (nonzero: boundaries are distinct and not parallel to
+        // the line).  The bin origin is shifted by s_q = beta(0) rounded, which
+        // keeps the FP32 operands of the residual small.
+        const int Nq = frame == 0 ? g.ny : g.nx;
+        for (int q = 0; q < Nq; ++q) {
+            const double qq = q - 0.5 * (Nq - 1);
+            const double N = n0 + nq * qq, D = d0 + dqq * qq;
+            const double delta = D * nK - N * dK;
+            MBMD_REQUIRE(std::fabs(delta) > 0.0 && D > 0.0, MBMD_ERR_SHAPE,
+                         "degenerate bin map on a sweep line (source too close)");
+            double sq = std::nearbyint(N / D);
+            sq = sq < 0.0 ? 0.0 : (sq > B - 1 ? B - 1 : sq);
+            float4* L = &line[((size_t)q * V + slot) * 2];
+            L[0] = make_float4((float)(N - sq * D), (float)(nK - sq * dK), (float)D, (float)dK);
+            L[1] = make_float4((float)((nK - (sq + 1.0) * dK) / delta), (float)(dK / delta), (float)(-sq),
+                               (float)(B - 1 - sq));
         }
         p.orient = n_neg == 0 ? 1.0f : -1.0f;
         p.view_frame = v | (frame << 16);
@@ -160,25 +194,31 @@ void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int b
     const size_t b_view = al(sizeof(ViewParams) * V), b_bound = al(sizeof(float2) * bound.size()),
                  b_path = al(sizeof(float) * path.size()), b_fv = al(sizeof(int) * V),
                  b_pre = al(sizeof(float2) * prefix_elems(g.nx, g.ny) * prefix_mat),
-                 b_det = al(sizeof(double) * (size_t)back_ch * V * (B + 1)),
+                 b_line = al(sizeof(float4) * line.size()),
+                 b_det = al(sizeof(double) * 2 * (size_t)back_ch * V * B),
                  b_tmp = al(sizeof(float) * (size_t)back_ch * nj);
     t.back_ch = back_ch;
     char* base = nullptr;
     MBMD_HIP(hipGetDevice(&t.device));
-    MBMD_HIP(hipMalloc(&base, b_view + b_bound + b_path + b_fv + b_pre + b_det + b_tmp));
+    // the back projector addresses the detector prefix with 32-bit buffer offsets
+    MBMD_REQUIRE(b_det < (size_t(1) << 31), MBMD_ERR_SHAPE, "too many views x bins x channels for a back projection");
+    MBMD_HIP(hipMalloc(&base, b_view + b_bound + b_path + b_fv + b_pre + b_line + b_det + b_tmp));
     t.mem = base;
     t.view = reinterpret_cast<ViewParams*>(base);
     t.bound = reinterpret_cast<float2*>(base + b_view);
     t.path = reinterpret_cast<float*>(base + b_view + b_bound);
     t.frame_views = reinterpret_cast<int*>(base + b_view + b_bound + b_path);
     t.prefix = prefix_mat ? reinterpret_cast<float2*>(base + b_view + b_bound + b_path + b_fv) : nullptr;
-    char* after_pre = base + b_view + b_bound + b_path + b_fv + b_pre;
+    t.back_line = reinterpret_cast<float4*>(base + b_view + b_bound + b_path + b_fv + b_pre);
+    t.back_line_q = QL;
+    char* after_pre = base + b_view + b_bound + b_path + b_fv + b_pre + b_line;
     t.det_prefix = back_ch ? reinterpret_cast<double*>(after_pre) : nullptr;
-    t.back_tmp = back_ch ? reinterpret_cast<float*>(after_pre + b_det) : nullptr;
+    t.back_part = back_ch ? reinterpret_cast<float*>(after_pre + b_det) : nullptr;
     MBMD_HIP(hipMemcpy(t.view, vp.data(), sizeof(ViewParams) * V, hipMemcpyHostToDevice));
     MBMD_HIP(hipMemcpy(t.bound, bound.data(), sizeof(float2) * bound.size(), hipMemcpyHostToDevice));
     MBMD_HIP(hipMemcpy(t.path, path.data(), sizeof(float) * path.size(), hipMemcpyHostToDevice));
     MBMD_HIP(hipMemcpy(t.frame_views, fv.data(), sizeof(int) * V, hipMemcpyHostToDevice));
+    MBMD_HIP(hipMemcpy(t.back_line, line.data(), sizeof(float4) * line.size(), hipMemcpyHostToDevice));
 }
 
 void free_geometry(GeomTables& t) {

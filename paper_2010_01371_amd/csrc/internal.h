@@ -17,6 +17,7 @@ constexpr int kMaxChan = 8;
 constexpr int kMaxEnergy = 256;
 constexpr int kMaxPacked = kMaxMat * (kMaxMat + 1) / 2;   // symmetric N_k x N_k, packed
 constexpr int kMaxBackCh = 10;                              // channels of one backprojection
+constexpr int kMaxGpus = 64;                                // devices with cached per-device launch data
 constexpr int kRefreshEvery = 25;                           // recompute l = A x this often
 constexpr int kMaxPartials = 16384;                         // per reduction region
 
@@ -101,15 +102,24 @@ struct GeomTables {
     int V = 0, B = 0, nx = 0, ny = 0;
     int n_frame_views[2] = {0, 0};
     ViewParams* view = nullptr;      // [slot]
-    float2* bound = nullptr;         // [slot][B+1]: boundary b' at line q is C0 + C1 qq
+    // [slot][B+1]: boundary b' crosses sweep line q (0..Nq-1) at along-line
+    // position X0 + X1 q, in pixels from the line's first pixel edge
+    float2* bound = nullptr;
     float* path = nullptr;           // [slot][B]: path length per sweep line of the bin-centre ray
     int* frame_views = nullptr;      // [slot] -> view index
     // scratch: line prefix sums, frame 0 lines [n_mat][ny][nx+1] then frame 1 lines
     // [n_mat][nx][ny+1]; entry Np of a line holds (line total, 0)
     float2* prefix = nullptr;
     int prefix_mat = 0;
-    double* det_prefix = nullptr;    // scratch: [back_ch][V][B+1] detector prefix sums (FP64)
-    float* back_tmp = nullptr;       // scratch: [back_ch][nx][ny] column-sweep part of a back projection
+    // [max(nx,ny)][slot][2]: per sweep line q of the slot's frame, the fractional
+    // bin index shifted by an integer s_q: beta - s_q = (N + nK K) / (D + dK K), as
+    // {N, nK, D, dK} and {a, c, -s_q, B-1-s_q}, where (a - c (beta' floor)) scales
+    // (N + nK K) - floor(beta') (D + dK K) to the fraction of the bin
+    float4* back_line = nullptr;
+    int back_line_q = 0;             // max(nx, ny)
+    double* det_prefix = nullptr;    // scratch: [back_ch][V][B] pairs (C[b], C[b+1]-C[b]) (FP64)
+    // scratch: [back_ch][nx][ny] column-sweep part of a back projection
+    float* back_part = nullptr;
     int back_ch = 0;
     void* mem = nullptr;
     int device = -1;

@@ -10,8 +10,10 @@
 // the integral of the line over a footprint [K_b, K_b+1] is F(K_b+1) - F(K_b).
 // One lane per bin BOUNDARY: a wavefront evaluates F at 64 consecutive
 // boundaries and takes its right-hand neighbour's value with a wave shuffle,
-// giving 63 bins per wavefront.  The sign of (F(K_b+1) - F(K_b)) / (K_b+1 -
-// K_b) does not depend on the orientation of the view.
+// giving 63 bins per wavefront.  The footprint width is the difference of the
+// same two FP32 boundary positions that F is evaluated at, so position
+// rounding cancels to first order in the ratio (the exact width would not);
+// signs cancel too, whatever the orientation of the view.
 //
 // Back projection (pixel-driven gather): per call and view the sinogram times
 // the per-line path length is integrated over the detector in FP64,
@@ -19,12 +21,16 @@
 // sweep line is piecewise constant in the along-line position K, with
 // cumulative integral H(K) = C[b] + (C[b+1] - C[b]) (K - K_b)/(K_b+1 - K_b)
 // for K in bin b, so a pixel [K, K+1] receives H(K+1) - H(K); the view's
-// orientation sign is folded into C.  One lane per pixel EDGE: 63 pixels per wavefront, the
-// right edge taken from the neighbour lane.  The bin holding an edge comes
-// from the rational map K -> fractional bin index; the fraction inside the
-// bin is clamped to [0, 1], which keeps H continuous when that map is off by
-// rounding near a boundary.  H and the sums over views are FP64 (full rate on
-// CDNA); no atomics, so results are bitwise reproducible.
+// orientation sign is folded into C.  One lane per pixel EDGE: each lane sums
+// H over the views and the pixel value is the difference of the right
+// neighbour lane's sum and its own (63 pixels per wavefront).  The bin holding
+// an edge and the fraction (K - K_b)/(K_b+1 - K_b) both come from the
+// projective map K -> fractional bin index restricted to the sweep line, whose
+// per-line coefficients are read with scalar loads; the only per-lane table
+// read is the pair (C[b], C[b+1] - C[b]).  The fraction is clamped to [0, 1],
+// which keeps H continuous when the bin index is off by rounding near a
+// boundary.  H and the sums over views are FP64 (full rate on CDNA); no
+// atomics, so results are bitwise reproducible.
 //
 // Table reads go through buffer loads (32-bit offsets from a base held in
 // scalar registers; out-of-range offsets read zero), neighbour exchanges are
@@ -123,17 +129,18 @@ __global__ __launch_bounds__(kScanThreads) void k_line_prefix(const float* __res
     if (threadIdx.x == kScanThreads - 1) dst[Np] = make_float2((float)part[kScanThreads - 1], 0.0f);
 }
 
-// Per slot and channel: C[b] = orient * sum_{b'<b} sino[b'] path[b'] (FP64),
-// b = 0..B; the view's orientation sign makes H(K+1) - H(K) the pixel value.
+// Per slot and channel, for b = 0..B-1: the pair (C[b], C[b+1] - C[b]) with
+// C[b] = orient * sum_{b'<b} sino[b'] path[b'] (FP64); the view's orientation
+// sign makes H(K+1) - H(K) the pixel value.
 __global__ __launch_bounds__(kScanThreads) void k_detector_prefix(const float* __restrict__ sino,
                                                                    const float* __restrict__ path,
                                                                    const ViewParams* __restrict__ view, int V,
-                                                                   int B, double* __restrict__ C) {
+                                                                   int B, double2* __restrict__ C) {
     const int slot = blockIdx.x, ch = blockIdx.y;
     const double orient = (double)view[slot].orient;
     const float* s = sino + ((size_t)ch * V + vp_view(view[slot])) * B;
     const float* pa = path + (size_t)slot * B;
-    double* dst = C + ((size_t)ch * V + slot) * (B + 1);
+    double2* dst = C + ((size_t)ch * V + slot) * B;
     __shared__ double part[kScanThreads];
     const int per = (B + kScanThreads - 1) / kScanThreads;
     const int b0 = threadIdx.x * per;
@@ -154,11 +161,11 @@ __global__ __launch_bounds__(kScanThreads) void k_detector_prefix(const float* _
     for (int i = 0; i < per; ++i) {
         const int b = b0 + i;
         if (b < B) {
-            dst[b] = run;
-            run += orient * ((double)s[b] * (double)pa[b]);
+            const double d = orient * ((double)s[b] * (double)pa[b]);
+            dst[b] = make_double2(run, d);
+            run += d;
         }
     }
-    if (threadIdx.x == kScanThreads - 1) dst[B] = part[kScanThreads - 1];
 }
 
 // Work of the two sweep frames of one launch.
@@ -187,7 +194,8 @@ __global__ __launch_bounds__(kThreads) void k_dd_forward(const ViewParams* __res
     if (!decode_block(fs, frame, item)) return;
     const int slot = (frame ? nv0 : 0) + item / chunks;
     const int chunk = item % chunks;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int edge = (chunk * kWaves + wave) * kPerWave + lane;   // boundary index; valid ones are 0..B
     const int Nq = frame ? nx : ny;
     const int Np = frame ? ny : nx;
@@ -195,25 +203,23 @@ __global__ __launch_bounds__(kThreads) void k_dd_forward(const ViewParams* __res
     const __amdgpu_buffer_rsrc_t pre =
         rsrc(frame ? pre_cols : pre_rows, sizeof(float2) * (size_t)NK * Nq * Lp);
     const float2 bd = bound[(size_t)slot * (B + 1) + min(edge, B)];
-    const float half = 0.5f * (float)Np;
-    float qq = -0.5f * (float)(Nq - 1);
+    const float Npf = (float)Np;
     float acc[NK];
 #pragma unroll
     for (int m = 0; m < NK; ++m) acc[m] = 0.0f;
     // one sweep line: F at this lane's boundary, the neighbour's from lane + 1
     auto line_step = [&](int q) {
-        const float K = fmaf(bd.y, qq, bd.x);
-        qq += 1.0f;
-        const float Kc = fminf(fmaxf(K, -half), half);
-        const int k = (int)(Kc + half);                          // >= 0, so truncation is floor
-        const float f = Kc - ((float)k - half);
-        const float inv_w = fast_rcp(next_lane(K) - K);
+        const float X = fmaf(bd.y, (float)q, bd.x);
+        const float Xc = __builtin_amdgcn_fmed3f(X, 0.0f, Npf);
+        const int k = (int)Xc;                                   // >= 0, so truncation is floor
+        const float f = __builtin_amdgcn_fractf(Xc);
+        const float s = fast_rcp(next_lane(X) - X);
         const int voff = k * (int)sizeof(float2);
 #pragma unroll
         for (int m = 0; m < NK; ++m) {
             const float2 e = load_f2(pre, voff, (m * Nq + q) * Lp * (int)sizeof(float2));
             const float F = fmaf(f, e.y, e.x);
-            acc[m] = fmaf(next_lane(F) - F, inv_w, acc[m]);
+            acc[m] = fmaf(next_lane(F) - F, s, acc[m]);
         }
     };
     int q = 0;
@@ -232,81 +238,151 @@ __global__ __launch_bounds__(kThreads) void k_dd_forward(const ViewParams* __res
     }
 }
 
-template <int NCH>
-__global__ __launch_bounds__(kThreads) void k_dd_back(const ViewParams* __restrict__ view,
-                                                      const float2* __restrict__ bound, int nv0, int nv1,
+// One block: kWaves wavefronts x LPW adjacent sweep lines each, one segment of
+// 63 pixel edges; every wavefront walks all views of its frame.  Several lines
+// per wavefront give each wave LPW independent load chains per view, which is
+// what hides the memory latency, and let the whole launch fit in one round of
+// resident waves.  Row sweeps write x; column sweeps write their partial image
+// (layout [ix][iy]) to part, added by k_back_reduce.
+template <int NCH, int LPW>
+__global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__ line_tab, int nv0, int nv1,
                                                       FrameSplit fs, int nx, int ny, int V, int B,
-                                                      const double* __restrict__ C, float* __restrict__ x,
-                                                      float* __restrict__ xt) {
+                                                      const double2* __restrict__ C, float* __restrict__ x,
+                                                      float* __restrict__ part) {
     int frame, item;
     if (!decode_block(fs, frame, item)) return;
     const int Nq = frame ? nx : ny;
     const int Np = frame ? ny : nx;
     const int segs = (Np + kPerWave - 1) / kPerWave;
     const int seg = item % segs;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int q = (item / segs) * kWaves + wave;
-    if (q >= Nq) return;                           // whole wavefront (one line) outside the image
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int q0 = ((item / segs) * kWaves + wave) * LPW;
+    if (q0 >= Nq) return;                          // whole wavefront outside the image
     const int pe = seg * kPerWave + lane;          // edge index; lanes past Np repeat edge Np
-    const float half = 0.5f * (float)Np;
-    const float qq = (float)q - 0.5f * (float)(Nq - 1);
-    const float K = (float)min(pe, Np) - half;
+    const float K = (float)min(pe, Np) - 0.5f * (float)Np;
     const int nv = frame ? nv1 : nv0;
     const int slot0 = frame ? nv0 : 0;
-    const int row = (B + 1) * (int)sizeof(float2);
-    const __amdgpu_buffer_rsrc_t tb = rsrc(bound, sizeof(float2) * (size_t)V * (B + 1));
-    const __amdgpu_buffer_rsrc_t tc = rsrc(C, sizeof(double) * (size_t)NCH * V * (B + 1));
-    const int crow = (B + 1) * (int)sizeof(double);
-    double acc[NCH];
+    const float4* lt[LPW];
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) acc[c] = 0.0;
-    auto view_step = [&](int is) {
-        const int slot = slot0 + is;
-        const ViewParams vp = view[slot];
-        const float num = fmaf(vp.nK, K, fmaf(vp.nq, qq, vp.n0));
-        const float den = fmaf(vp.dK, K, fmaf(vp.dq, qq, vp.d0));
-        const int b = min((int)fmaxf(num * fast_rcp(den), 0.0f), B - 1);   // >= 0: truncation is floor
-        const float4 cb = load_f4(tb, b * (int)sizeof(float2), slot * row);    // boundaries b, b+1
-        const float kb = fmaf(cb.y, qq, cb.x);
-        const float kb1 = fmaf(cb.w, qq, cb.z);
-        const float fr = fminf(fmaxf((K - kb) * fast_rcp(kb1 - kb), 0.0f), 1.0f);
+    for (int j = 0; j < LPW; ++j) lt[j] = line_tab + (size_t)min(q0 + j, Nq - 1) * V * 2;
+    const __amdgpu_buffer_rsrc_t tc = rsrc(C, sizeof(double2) * (size_t)NCH * V * B);
+    const int crow = B * (int)sizeof(double2);
+    double acc[LPW][NCH];                           // sum over views of H(K)
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            const double2 h = load_d2(tc, b * (int)sizeof(double), (c * V + slot) * crow);
-            const double H = fma(h.y - h.x, (double)fr, h.x);
-            acc[c] += next_lane(H) - H;
+    for (int j = 0; j < LPW; ++j)
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) acc[j][c] = 0.0;
+    // Software pipeline over pairs of views: the per-line tables of the next
+    // pair are requested (scalar loads) only after this pair's values are in
+    // registers -- scalar loads complete out of order, so a wait for one waits
+    // for all -- and land while this pair's detector gathers are in flight.
+    constexpr int U = 2;
+    float4 tm[U][LPW], tf[U][LPW];
+    auto fetch = [&](int is) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int slot = slot0 + min(is + u, nv - 1);
+#pragma unroll
+            for (int j = 0; j < LPW; ++j) {
+                tm[u][j] = lt[j][2 * slot];         // {N, nK, D, dK}, shifted by s_q
+                tf[u][j] = lt[j][2 * slot + 1];     // {a, c, -s_q, B-1-s_q}
+            }
         }
     };
+    fetch(0);
+    const int nfull = nv - nv % U;
     int is = 0;
-    for (; is + 2 <= nv; is += 2) {   // trip counts are uniform over the wavefront
-        view_step(is);
-        view_step(is + 1);
-    }
-    for (; is < nv; ++is) view_step(is);
-    if (lane < kPerWave && pe < Np) {
-        const size_t img_stride = (size_t)nx * ny;
-        const size_t pix = (size_t)q * Np + pe;    // frame layout [q][p]
-        float* dst = frame ? xt : x;
+    for (; is < nfull; is += U) {          // trip counts are uniform over the wavefront
+        int off[U][LPW];
+        float frs[U][LPW];
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) dst[c * img_stride + pix] = (float)acc[c];
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < LPW; ++j) {
+                const float4 m = tm[u][j], f = tf[u][j];
+                const float num = fmaf(m.y, K, m.x);
+                const float den = fmaf(m.w, K, m.z);
+                const float bf = __builtin_amdgcn_fmed3f(floorf(num * fast_rcp(den)), f.z, f.w);
+                off[u][j] = (int)(bf - f.z) * (int)sizeof(double2);   // bin in [0, B-1]
+                frs[u][j] = __builtin_amdgcn_fmed3f(fmaf(-bf, den, num) * fmaf(-f.y, bf, f.x), 0.0f, 1.0f);
+            }
+        double2 h[U][LPW][NCH];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < LPW; ++j)
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) h[u][j][c] = load_d2(tc, off[u][j], (c * V + slot0 + is + u) * crow);
+        __builtin_amdgcn_sched_barrier(0);
+        fetch(is + U);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < LPW; ++j)
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) acc[j][c] += fma(h[u][j][c].y, (double)frs[u][j], h[u][j][c].x);
+    }
+    static_assert(U == 2, "the tail below handles one remaining view");
+    if (is < nv) {                         // one remaining view; its tables were fetched into slot 0
+#pragma unroll
+        for (int j = 0; j < LPW; ++j) {
+            const float4 m = tm[0][j], f = tf[0][j];
+            const float num = fmaf(m.y, K, m.x);
+            const float den = fmaf(m.w, K, m.z);
+            const float bf = __builtin_amdgcn_fmed3f(floorf(num * fast_rcp(den)), f.z, f.w);
+            const int o = (int)(bf - f.z) * (int)sizeof(double2);
+            const float fr = __builtin_amdgcn_fmed3f(fmaf(-bf, den, num) * fmaf(-f.y, bf, f.x), 0.0f, 1.0f);
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const double2 h = load_d2(tc, o, (c * V + slot0 + is) * crow);
+                acc[j][c] += fma(h.y, (double)fr, h.x);
+            }
+        }
+    }
+    const size_t img_stride = (size_t)nx * ny;
+    float* dst = frame ? part : x;
+#pragma unroll
+    for (int j = 0; j < LPW; ++j) {
+        float val[NCH];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) val[c] = (float)(next_lane(acc[j][c]) - acc[j][c]);
+        if (lane < kPerWave && pe < Np && q0 + j < Nq) {
+            const size_t pix = (size_t)(q0 + j) * Np + pe;    // frame layout [q][p]
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) dst[c * img_stride + pix] = val[c];
+        }
     }
 }
 
-// x[c][iy][ix] += xt[c][ix][iy]  (32 x 32 tiles through LDS)
-__global__ __launch_bounds__(kThreads) void k_add_transposed(const float* __restrict__ xt, float* __restrict__ x,
-                                                             int nx, int ny) {
+// x[c] = (accumulate ? x[c] : 0) + sum_{p < n0p} part[p][c] + sum_{n0p <= p < n0p+n1p} part[p][c]^T,
+// the transposed (column-sweep) partials through a 32 x 32 LDS tile; the sum
+// order is fixed, so results are reproducible.
+__global__ __launch_bounds__(kThreads) void k_back_reduce(const float* __restrict__ part, int n0p, int n1p,
+                                                          int nch, int nx, int ny, int accumulate,
+                                                          float* __restrict__ x) {
     __shared__ float tile[32][33];
-    const size_t off = (size_t)blockIdx.z * nx * ny;
+    const size_t nj = (size_t)nx * ny;
+    const int c = blockIdx.z;
     const int bx = blockIdx.x * 32, by = blockIdx.y * 32;    // image tile origin (ix, iy)
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8 threads
     for (int r = ty; r < 32; r += 8) {
-        const int ix = bx + r, iy = by + tx;                  // xt[ix][iy], coalesced along iy
-        if (ix < nx && iy < ny) tile[r][tx] = xt[off + (size_t)ix * ny + iy];
+        const int ix = bx + r, iy = by + tx;                  // column layout [ix][iy], coalesced along iy
+        float v = 0.0f;
+        if (ix < nx && iy < ny)
+            for (int p = n0p; p < n0p + n1p; ++p) v += part[((size_t)p * nch + c) * nj + (size_t)ix * ny + iy];
+        tile[r][tx] = v;
     }
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
         const int iy = by + r, ix = bx + tx;
-        if (ix < nx && iy < ny) x[off + (size_t)iy * nx + ix] += tile[tx][r];
+        if (ix < nx && iy < ny) {
+            const size_t j = (size_t)iy * nx + ix;
+            float v = accumulate ? x[c * nj + j] : 0.0f;
+            for (int p = 0; p < n0p; ++p) v += part[((size_t)p * nch + c) * nj + j];
+            x[c * nj + j] = v + tile[tx][r];
+        }
     }
 }
 
@@ -331,11 +407,56 @@ void fwd_launch(const GeomTables& t, float* sino, hipStream_t s) {
     const float2* cols = t.prefix + (size_t)t.prefix_mat * t.ny * (t.nx + 1);
     {
         KernelTimer kt_("k_dd_forward", s);
-        hipLaunchKernelGGL(k_dd_forward<NK>, dim3(grid_blocks(fs)), dim3(kThreads), 0, s, t.view, t.bound, t.path,
-                           rows, cols, t.n_frame_views[0], fs, chunks, t.nx, t.ny, t.V, t.B, sino);
+        hipLaunchKernelGGL(k_dd_forward<NK>, dim3(grid_blocks(fs)), dim3(kThreads), 0, s, t.view, t.bound,
+                           t.path, rows, cols, t.n_frame_views[0], fs, chunks, t.nx, t.ny, t.V, t.B, sino);
         kt_.stop();
     }
     MBMD_LAUNCHED();
+}
+
+// Wavefronts of k_dd_back<NCH, LPW> resident on the whole device at once.
+template <int NCH, int LPW>
+int back_waves_per_round() {
+    static int cached[kMaxGpus] = {};
+    int dev = 0;
+    MBMD_HIP(hipGetDevice(&dev));
+    MBMD_REQUIRE(dev >= 0 && dev < kMaxGpus, MBMD_ERR_ARG, "device index out of range");
+    if (!cached[dev]) {
+        int cus = 0, occ = 0;
+        MBMD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        MBMD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_dd_back<NCH, LPW>, kThreads, 0));
+        cached[dev] = (cus > 0 ? cus : 1) * (occ > 0 ? occ : 1) * kWaves;
+    }
+    return cached[dev];
+}
+
+// Relative time of a back projection launch with LPW lines per wavefront:
+// rounds of resident waves, each lasting the longer of the per-view latency
+// of one wavefront (~900 cycles with two views in flight) and the VALU time of
+// the waves sharing a SIMD (~76 cycles per line and view), both measured on
+// gfx950 at the fan-beam workloads.
+double back_cost(long long waves, int per_round, int lpw, int simds) {
+    double t = 0.0;
+    for (long long left = waves; left > 0; left -= per_round) {
+        const long long w = left < per_round ? left : per_round;
+        const double per_simd = (double)w / simds;
+        const double valu = per_simd * lpw * 76.0;
+        t += valu > 900.0 ? valu : 900.0;
+    }
+    return t;
+}
+
+template <int NCH, int LPW>
+void back_kernel_launch(const GeomTables& t, float* x, hipStream_t s) {
+    const int nv0 = t.n_frame_views[0], nv1 = t.n_frame_views[1];
+    const int lines = kWaves * LPW;
+    const int u0 = nv0 ? ((t.nx + kPerWave - 1) / kPerWave) * ((t.ny + lines - 1) / lines) : 0;
+    const int u1 = nv1 ? ((t.ny + kPerWave - 1) / kPerWave) * ((t.nx + lines - 1) / lines) : 0;
+    const FrameSplit fs = split(u0, u1);
+    KernelTimer kt_("k_dd_back", s);
+    hipLaunchKernelGGL((k_dd_back<NCH, LPW>), dim3(grid_blocks(fs)), dim3(kThreads), 0, s, t.back_line, nv0, nv1, fs,
+                       t.nx, t.ny, t.V, t.B, reinterpret_cast<const double2*>(t.det_prefix), x, t.back_part);
+    kt_.stop();
 }
 
 template <int NCH>
@@ -343,26 +464,38 @@ void back_launch(const GeomTables& t, const float* sino, float* x, hipStream_t s
     {
         KernelTimer kt_("k_detector_prefix", s);
         hipLaunchKernelGGL(k_detector_prefix, dim3(t.V, NCH), dim3(kScanThreads), 0, s, sino, t.path,
-                           t.view, t.V, t.B, t.det_prefix);
+                           t.view, t.V, t.B, reinterpret_cast<double2*>(t.det_prefix));
         kt_.stop();
     }
     MBMD_LAUNCHED();
-    const int segs0 = (t.nx + kPerWave - 1) / kPerWave, segs1 = (t.ny + kPerWave - 1) / kPerWave;
-    const int groups0 = (t.ny + kWaves - 1) / kWaves, groups1 = (t.nx + kWaves - 1) / kWaves;
-    const FrameSplit fs = split(t.n_frame_views[0] ? segs0 * groups0 : 0, t.n_frame_views[1] ? segs1 * groups1 : 0);
-    if (!t.n_frame_views[0]) launch_fill(NCH * t.nx * t.ny, x, 0.0f, s);
-    {
-        KernelTimer kt_("k_dd_back", s);
-        hipLaunchKernelGGL(k_dd_back<NCH>, dim3(grid_blocks(fs)), dim3(kThreads), 0, s, t.view, t.bound,
-                           t.n_frame_views[0], t.n_frame_views[1], fs, t.nx, t.ny, t.V, t.B, t.det_prefix, x,
-                           t.back_tmp);
-        kt_.stop();
+    const int nv0 = t.n_frame_views[0], nv1 = t.n_frame_views[1];
+    // two lines per wavefront when that is expected to be faster (NCH <= 2 keeps
+    // the registers of two lines' loads within full occupancy)
+    bool two = false;
+    if (NCH <= 2) {
+        int cus = 0, dev = 0;
+        MBMD_HIP(hipGetDevice(&dev));
+        MBMD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        const int simds = 4 * (cus > 0 ? cus : 1);
+        auto waves = [&](int lpw) {
+            const int lines = kWaves * lpw;
+            const long long u0 = nv0 ? (long long)((t.nx + kPerWave - 1) / kPerWave) * ((t.ny + lines - 1) / lines) : 0;
+            const long long u1 = nv1 ? (long long)((t.ny + kPerWave - 1) / kPerWave) * ((t.nx + lines - 1) / lines) : 0;
+            return (u0 + u1) * kWaves;
+        };
+        const double c1 = back_cost(waves(1), back_waves_per_round<NCH, 1>(), 1, simds);
+        const double c2 = back_cost(waves(2), back_waves_per_round<NCH <= 2 ? NCH : 1, 2>(), 2, simds);
+        two = c2 < c1;
     }
+    if (two)
+        back_kernel_launch<NCH <= 2 ? NCH : 1, 2>(t, x, s);
+    else
+        back_kernel_launch<NCH, 1>(t, x, s);
     MBMD_LAUNCHED();
-    if (t.n_frame_views[1]) {
-        KernelTimer kt_("k_add_transposed", s);
-        hipLaunchKernelGGL(k_add_transposed, dim3((t.nx + 31) / 32, (t.ny + 31) / 32, NCH), dim3(kThreads), 0, s,
-                           t.back_tmp, x, t.nx, t.ny);
+    if (nv1) {
+        KernelTimer kt_("k_back_reduce", s);
+        hipLaunchKernelGGL(k_back_reduce, dim3((t.nx + 31) / 32, (t.ny + 31) / 32, NCH), dim3(kThreads), 0, s,
+                           t.back_part, 0, 1, NCH, t.nx, t.ny, nv0 ? 1 : 0, x);
         kt_.stop();
         MBMD_LAUNCHED();
     }
@@ -383,15 +516,12 @@ __global__ __launch_bounds__(kThreads) void k_dd_count(const ViewParams* __restr
         const int Np = frame ? ny : nx;
         const float2 b0 = bound[(size_t)slot * (B + 1) + b];
         const float2 b1 = bound[(size_t)slot * (B + 1) + b + 1];
-        const float half = 0.5f * (float)Np;
-        const float qc = 0.5f * (float)(Nq - 1);
         for (int q = 0; q < Nq; ++q) {
-            const float qq = (float)q - qc;
-            const float ka = fmaf(b0.y, qq, b0.x), kb = fmaf(b1.y, qq, b1.x);
-            const float lo = fmaxf(fminf(ka, kb), -half), hi = fminf(fmaxf(ka, kb), half);
+            const float xa = fmaf(b0.y, (float)q, b0.x), xb = fmaf(b1.y, (float)q, b1.x);
+            const float lo = fmaxf(fminf(xa, xb), 0.0f), hi = fminf(fmaxf(xa, xb), (float)Np);
             if (hi <= lo) continue;
-            const int k0 = (int)floorf(lo + half);
-            const int k1 = (int)ceilf(hi + half) - 1;
+            const int k0 = (int)floorf(lo);
+            const int k1 = (int)ceilf(hi) - 1;
             cnt += (unsigned long long)max(0, min(k1, Np - 1) - max(k0, 0) + 1);
         }
     }
