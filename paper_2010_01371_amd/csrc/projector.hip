@@ -179,7 +179,7 @@ __device__ __forceinline__ bool decode_block(const FrameSplit& fs, int& frame, i
     const int xcd = id & 7;
     frame = xcd >> 2;
     item = (id >> 3) * 4 + (xcd & 3);
-    return item < fs.n_items[frame];
+    return item < (frame ? fs.n_items[1] : fs.n_items[0]);   // no dynamic index into the by-value array
 }
 
 template <int NK>
