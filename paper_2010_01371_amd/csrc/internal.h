@@ -107,8 +107,9 @@ struct GeomTables {
     float2* bound = nullptr;
     float* path = nullptr;           // [slot][B]: path length per sweep line of the bin-centre ray
     int* frame_views = nullptr;      // [slot] -> view index
-    // scratch: line prefix sums, frame 0 lines [n_mat][ny][nx+1] then frame 1 lines
-    // [n_mat][nx][ny+1]; entry Np of a line holds (line total, 0)
+    // scratch: line prefix sums, entries (F[k], img[k]) for k < Np and (line total, 0)
+    // at k = Np; frame 0 lines [n_mat][ny][prefix_row(nx)], then frame 1 lines
+    // [n_mat][nx][prefix_row(ny)]
     float2* prefix = nullptr;
     int prefix_mat = 0;
     // [max(nx,ny)][slot][2]: per sweep line q of the slot's frame, the fractional
@@ -125,7 +126,10 @@ struct GeomTables {
     int device = -1;
 };
 
-inline size_t prefix_elems(int nx, int ny) { return (size_t)ny * (nx + 1) + (size_t)nx * (ny + 1); }
+// Row stride (entries) of the line prefix table for lines of Np pixels: Np + 1
+// entries rounded up to even, so that rows start 16-byte aligned.
+__host__ __device__ inline int prefix_row(int Np) { return (Np + 2) & ~1; }
+inline size_t prefix_elems(int nx, int ny) { return (size_t)ny * prefix_row(nx) + (size_t)nx * prefix_row(ny); }
 
 // Builds the tables in FP64 on the host and uploads them (synchronous copy).
 void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int back_ch);

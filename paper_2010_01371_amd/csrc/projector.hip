@@ -85,21 +85,24 @@ __device__ __forceinline__ double2 load_d2(__amdgpu_buffer_rsrc_t r, int voff, i
     return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
 
-// Exclusive prefix sums of every sweep line of n_mat images for one frame, with
-// the line total appended (entry Np).  Line q of frame 0 is image row q; of
-// frame 1 image column q.
+// Exclusive prefix sums F[p] = sum_{p'<p} img[p'] (FP64 accumulation, stored
+// FP32 next to img[p]) of every sweep line of n_mat images, entry Np holding
+// (line total, 0).  One block per line: blocks [0, ny) take the rows (frame 0),
+// blocks [ny, ny+nx) the columns (frame 1); a frame without views is skipped by
+// the caller's grid.
 __global__ __launch_bounds__(kScanThreads) void k_line_prefix(const float* __restrict__ img,
-                                                               float2* __restrict__ out, int nx,
-                                                               int ny, int frame) {
-    const int q = blockIdx.x;
+                                                               float2* __restrict__ rows, float2* __restrict__ cols,
+                                                               int nx, int ny, int line0) {
+    const int line = line0 + blockIdx.x;
     const int m = blockIdx.y;
+    const int frame = line >= ny ? 1 : 0;
+    const int q = frame ? line - ny : line;
     const int Nq = frame ? nx : ny;
     const int Np = frame ? ny : nx;
-    if (q >= Nq) return;
     const float* src = img + (size_t)m * nx * ny;
     const size_t elem_stride = frame ? (size_t)nx : 1;
     const size_t line_off = frame ? (size_t)q : (size_t)q * nx;
-    float2* dst = out + ((size_t)m * Nq + q) * (Np + 1);
+    float2* dst = (frame ? cols : rows) + ((size_t)m * Nq + q) * prefix_row(Np);
 
     __shared__ double part[kScanThreads];
     const int per = (Np + kScanThreads - 1) / kScanThreads;
@@ -199,9 +202,8 @@ __global__ __launch_bounds__(kThreads) void k_dd_forward(const ViewParams* __res
     const int edge = (chunk * kWaves + wave) * kPerWave + lane;   // boundary index; valid ones are 0..B
     const int Nq = frame ? nx : ny;
     const int Np = frame ? ny : nx;
-    const int Lp = Np + 1;
-    const __amdgpu_buffer_rsrc_t pre =
-        rsrc(frame ? pre_cols : pre_rows, sizeof(float2) * (size_t)NK * Nq * Lp);
+    const int Lp = prefix_row(Np);
+    const __amdgpu_buffer_rsrc_t pre = rsrc(frame ? pre_cols : pre_rows, sizeof(float2) * (size_t)NK * Nq * Lp);
     const float2 bd = bound[(size_t)slot * (B + 1) + min(edge, B)];
     const float Npf = (float)Np;
     float acc[NK];
@@ -217,7 +219,7 @@ __global__ __launch_bounds__(kThreads) void k_dd_forward(const ViewParams* __res
         const int voff = k * (int)sizeof(float2);
 #pragma unroll
         for (int m = 0; m < NK; ++m) {
-            const float2 e = load_f2(pre, voff, (m * Nq + q) * Lp * (int)sizeof(float2));
+            const float2 e = load_f2(pre, voff, (m * Nq + q) * Lp * (int)sizeof(float2));   // F[k], img[k]
             const float F = fmaf(f, e.y, e.x);
             acc[m] = fmaf(next_lane(F) - F, s, acc[m]);
         }
@@ -336,7 +338,7 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
             const float fr = __builtin_amdgcn_fmed3f(fmaf(-bf, den, num) * fmaf(-f.y, bf, f.x), 0.0f, 1.0f);
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
-                const double2 h = load_d2(tc, o, (c * V + slot0 + is) * crow);
+                const double2 h = load_d2(tc, o, (c * V + slot0 + is) * crow);   // C[b], C[b+1] - C[b]
                 acc[j][c] += fma(h.y, (double)fr, h.x);
             }
         }
@@ -404,7 +406,7 @@ void fwd_launch(const GeomTables& t, float* sino, hipStream_t s) {
     const int chunks = (t.B + 1 + kWaves * kPerWave - 1) / (kWaves * kPerWave);
     const FrameSplit fs = split(t.n_frame_views[0] * chunks, t.n_frame_views[1] * chunks);
     const float2* rows = t.prefix;
-    const float2* cols = t.prefix + (size_t)t.prefix_mat * t.ny * (t.nx + 1);
+    const float2* cols = t.prefix + (size_t)t.prefix_mat * t.ny * prefix_row(t.nx);
     {
         KernelTimer kt_("k_dd_forward", s);
         hipLaunchKernelGGL(k_dd_forward<NK>, dim3(grid_blocks(fs)), dim3(kThreads), 0, s, t.view, t.bound,
@@ -539,17 +541,17 @@ __global__ __launch_bounds__(kThreads) void k_dd_count(const ViewParams* __restr
 void launch_project(const GeomTables& t, const float* x, float* sino, int n_mat, hipStream_t s) {
     MBMD_REQUIRE(n_mat >= 1 && n_mat <= kMaxMat, MBMD_ERR_SHAPE, "n_mat must be in 1..4");
     MBMD_REQUIRE(t.prefix != nullptr && t.prefix_mat >= n_mat, MBMD_ERR_ARG, "projector prefix scratch too small");
-    for (int frame = 0; frame < 2; ++frame) {
-        if (t.n_frame_views[frame] == 0) continue;
-        const int Nq = frame ? t.nx : t.ny;
-        float2* out = t.prefix + (frame ? (size_t)t.prefix_mat * t.ny * (t.nx + 1) : 0);
-        {
-            KernelTimer kt_("k_line_prefix", s);
-            hipLaunchKernelGGL(k_line_prefix, dim3(Nq, n_mat), dim3(kScanThreads), 0, s, x, out, t.nx, t.ny, frame);
-            kt_.stop();
-        }
-        MBMD_LAUNCHED();
+    {
+        // lines [line0, line1): rows then columns, only the frames that have views
+        const int line0 = t.n_frame_views[0] ? 0 : t.ny;
+        const int line1 = t.n_frame_views[1] ? t.ny + t.nx : t.ny;
+        float2* cols = t.prefix + (size_t)t.prefix_mat * t.ny * prefix_row(t.nx);
+        KernelTimer kt_("k_line_prefix", s);
+        hipLaunchKernelGGL(k_line_prefix, dim3(line1 - line0, n_mat), dim3(kScanThreads), 0, s, x, t.prefix, cols,
+                           t.nx, t.ny, line0);
+        kt_.stop();
     }
+    MBMD_LAUNCHED();
     switch (n_mat) {
         case 1: fwd_launch<1>(t, sino, s); break;
         case 2: fwd_launch<2>(t, sino, s); break;
