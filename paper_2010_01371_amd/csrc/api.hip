@@ -99,6 +99,15 @@ void backproject(Problem& P, const float* sino, float* img, int nch, hipStream_t
     launch_backproject(*P.geom, sino, img, nch, s);
 }
 
+// A^T sino with the column-sweep part left separate (see launch_backproject_parts).
+const float* backproject_parts(Problem& P, const float* sino, float* img, int nch, hipStream_t s) {
+    if (P.identity) {
+        MBMD_HIP(hipMemcpyAsync(img, sino, sizeof(float) * (size_t)nch * P.nj, hipMemcpyDeviceToDevice, s));
+        return nullptr;
+    }
+    return launch_backproject_parts(*P.geom, sino, img, nch, s);
+}
+
 double* region(Problem& P, int r) { return P.partials + (size_t)r * kMaxPartials; }
 
 // Sizes every buffer; called twice (sizing pass with a null arena base, then for real).
@@ -273,16 +282,15 @@ void plain_iteration(Problem& P, float* x, double* trace_slot, hipStream_t s) {
 void precond_iteration(Problem& P, float* x, int kind, double* trace_slot, hipStream_t s) {
     int counts[kRegions] = {0};
     counts[R_PHI_L] = launch_ray_grad(ray_args(P), P.l, P.u, nullptr, P.r, region(P, R_PHI_L), s);
-    backproject(P, P.u, P.g_img, P.K, s);
+    const float* part = backproject_parts(P, P.u, P.g_img, P.K, s);   // summed by the penalty pass
     counts[R_PHI_R] = launch_penalty_grad(pen_args(P), x, P.g_img, nullptr, P.g_img, nullptr,
-                                          region(P, R_PHI_R), s);
+                                          region(P, R_PHI_R), s, part);
     counts[R_GP] = apply_direction(P, kind, P.g_img, P.p_img, -1.0f, region(P, R_GP), s);
     project(P, P.p_img, P.q, P.K, s);
     counts[R_CQ2] = launch_ray_curv(ray_args(P), P.l, P.r, P.q, region(P, R_CQ2), s);
     if (P.has_penalty) counts[R_PRP] = launch_penalty_quadform(pen_args(P), x, P.p_img, region(P, R_PRP), s);
     launch_reduce_final(P.partials, counts, P.scal, trace_slot, 1, P.flags, s);
-    launch_axpy_alpha(P.K * P.nj, x, P.p_img, P.scal + S_ALPHA, s);
-    launch_axpy_alpha(P.K * P.ni, P.l, P.q, P.scal + S_ALPHA, s);
+    launch_axpy2_alpha(P.K * P.nj, x, P.p_img, P.K * P.ni, P.l, P.q, P.scal + S_ALPHA, s);
 }
 
 void check_precond_ready(Problem& P, int precond) {

@@ -48,11 +48,13 @@ __device__ __forceinline__ double huber_psi(double t, double d) {
     return a <= d ? 0.5 * t * t : d * a - 0.5 * d * d;
 }
 
-// g = gL + dR/dx, d = dL + d_R (d may be NULL), partials of R(x).
-// gL may alias g and dL may alias d (each element is read before it is written).
+// g = gL (+ gL2) + dR/dx, d = dL + d_R (d may be NULL), partials of R(x).
+// gL may alias g and dL may alias d (each element is read before it is written);
+// gL2, when given, is a second addend (the column-sweep part of a back projection).
 __global__ __launch_bounds__(kThreads) void k_penalty_grad(PenaltyArgs a, const float* __restrict__ x,
                                                            const float* gL, const float* dL, float* g, float* d,
-                                                           double* __restrict__ partials) {
+                                                           double* __restrict__ partials,
+                                                           const float* __restrict__ gL2) {
     __shared__ double sh[kThreads / 64];
     const int nj = a.nx * a.ny;
     const int j = blockIdx.x * kThreads + threadIdx.x;
@@ -70,7 +72,7 @@ __global__ __launch_bounds__(kThreads) void k_penalty_grad(PenaltyArgs a, const 
             if (D) { const float t = xc - x[j + a.nx]; gr += huber_dpsi(t, a.delta); om += huber_omega(t, a.delta);
                      phi += huber_psi((double)t, (double)a.delta); }
             const float b = a.beta[0];
-            g[j] = gL[j] + b * gr;
+            g[j] = (gL2 ? gL[j] + gL2[j] : gL[j]) + b * gr;
             if (d) d[j] = dL[j] + 2.0f * b * om;
             phi *= (double)b;
         } else {
@@ -91,7 +93,8 @@ __global__ __launch_bounds__(kThreads) void k_penalty_grad(PenaltyArgs a, const 
                     gr = fmaf(a.beta[k * a.K + l2], lap[l2], gr);
                     ab += fabsf(a.beta[k * a.K + l2]);
                 }
-                g[(size_t)k * nj + j] = gL[(size_t)k * nj + j] + gr;
+                const size_t jk = (size_t)k * nj + j;
+                g[jk] = (gL2 ? gL[jk] + gL2[jk] : gL[jk]) + gr;
                 if (d) d[(size_t)k * nj + j] = dL[(size_t)k * nj + j] + ab * 2.0f * nn;
                 phi += 0.5 * (double)x[(size_t)k * nj + j] * (double)gr;
             }
@@ -170,6 +173,15 @@ __global__ void k_axpy_alpha(int n, float* __restrict__ x, const float* __restri
                              const double* __restrict__ alpha) {
     const int i = blockIdx.x * kThreads + threadIdx.x;
     if (i < n) x[i] = fmaf((float)*alpha, p[i], x[i]);
+}
+
+__global__ void k_axpy2_alpha(int n1, float* __restrict__ x1, const float* __restrict__ p1, int n2,
+                              float* __restrict__ x2, const float* __restrict__ p2,
+                              const double* __restrict__ alpha) {
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    const float a = (float)*alpha;
+    if (i < n1) x1[i] = fmaf(a, p1[i], x1[i]);
+    else if (i - n1 < n2) x2[i - n1] = fmaf(a, p2[i - n1], x2[i - n1]);
 }
 
 __global__ void k_fill(int n, float* __restrict__ x, float value) {
@@ -340,25 +352,26 @@ struct Counts {
 };
 
 // Sums every region in a fixed order; mode bit 1: compute alpha.
-__global__ __launch_bounds__(kThreads) void k_reduce_final(const double* __restrict__ partials, Counts counts,
-                                                           double* __restrict__ scal,
-                                                           double* __restrict__ trace_slot, int mode,
-                                                           int* __restrict__ flags) {
-    __shared__ double sh[kThreads];
-    double sums[kRegions];
-    for (int r = 0; r < kRegions; ++r) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < counts.c[r]; i += kThreads) s += partials[(size_t)r * kMaxPartials + i];
-        sh[threadIdx.x] = s;
-        __syncthreads();
-        for (int off = kThreads / 2; off > 0; off >>= 1) {
-            if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
-            __syncthreads();
-        }
-        sums[r] = sh[0];
-        __syncthreads();
-    }
+// Sums of the partial-sum regions and the scalars formed from them.  Two
+// wavefronts per region, each adding a strided half in a fixed order, then a
+// fixed combination: the result does not depend on timing.
+constexpr int kReduceThreads = 128 * kRegions;
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_final(const double* __restrict__ partials,
+                                                                 Counts counts, double* __restrict__ scal,
+                                                                 double* __restrict__ trace_slot, int mode,
+                                                                 int* __restrict__ flags) {
+    __shared__ double sh[2 * kRegions];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = wave >> 1, half = wave & 1;
+    double v = 0.0;
+    const double* pr = partials + (size_t)r * kMaxPartials;
+    for (int i = half * 64 + lane; i < counts.c[r]; i += 128) v += pr[i];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
     if (threadIdx.x != 0) return;
+    double sums[kRegions];
+    for (int k = 0; k < kRegions; ++k) sums[k] = sh[2 * k] + sh[2 * k + 1];
     const double phi = sums[R_PHI_L] + sums[R_PHI_R];
     scal[S_PHI] = phi;
     if (trace_slot) *trace_slot = phi;
@@ -407,12 +420,12 @@ void launch_fill_double(int n, double* x, double value, hipStream_t s) {
 }
 
 int launch_penalty_grad(const PenaltyArgs& a, const float* x, const float* gL, const float* dL, float* g,
-                        float* d, double* phi_partials, hipStream_t s) {
+                        float* d, double* phi_partials, hipStream_t s, const float* gL2) {
     const int nb = nblk(a.nx * a.ny);
     MBMD_REQUIRE(nb <= kMaxPartials, MBMD_ERR_SHAPE, "image too large for the partial-sum buffer");
     {
         KernelTimer kt_("k_penalty_grad", s);
-        hipLaunchKernelGGL(k_penalty_grad, dim3(nb), dim3(kThreads), 0, s, a, x, gL, dL, g, d, phi_partials);
+        hipLaunchKernelGGL(k_penalty_grad, dim3(nb), dim3(kThreads), 0, s, a, x, gL, dL, g, d, phi_partials, gL2);
         kt_.stop();
     }
     MBMD_LAUNCHED();
@@ -453,6 +466,16 @@ void launch_axpy_alpha(int n, float* x, const float* p, const double* alpha, hip
     {
         KernelTimer kt_("k_axpy_alpha", s);
         hipLaunchKernelGGL(k_axpy_alpha, dim3(nblk(n)), dim3(kThreads), 0, s, n, x, p, alpha);
+        kt_.stop();
+    }
+    MBMD_LAUNCHED();
+}
+
+void launch_axpy2_alpha(int n1, float* x1, const float* p1, int n2, float* x2, const float* p2,
+                        const double* alpha, hipStream_t s) {
+    {
+        KernelTimer kt_("k_axpy2_alpha", s);
+        hipLaunchKernelGGL(k_axpy2_alpha, dim3(nblk(n1 + n2)), dim3(kThreads), 0, s, n1, x1, p1, n2, x2, p2, alpha);
         kt_.stop();
     }
     MBMD_LAUNCHED();
@@ -527,8 +550,8 @@ void launch_reduce_final(double* partials, const int* counts, double* scal, doub
     }
     {
         KernelTimer kt_("k_reduce_final", s);
-        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kThreads), 0, s, partials, c, scal, trace_slot, mode,
-                       flags);
+        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kReduceThreads), 0, s, partials, c, scal, trace_slot,
+                           mode, flags);
         kt_.stop();
     }
     MBMD_LAUNCHED();

@@ -140,6 +140,10 @@ GeomTables& cached_geometry(const mbmd_geometry& g, int prefix_mat, int back_ch)
 // ---------------------------------------------------------------- projector launches
 void launch_project(const GeomTables& t, const float* x, float* sino, int n_mat, hipStream_t s);
 void launch_backproject(const GeomTables& t, const float* sino, float* x, int n_ch, hipStream_t s);
+// A^T sino without the final sum: x receives the row-sweep part, the return value is
+// the column-sweep part in image layout (nullptr if none), valid until the next
+// back projection with the same geometry.
+const float* launch_backproject_parts(const GeomTables& t, const float* sino, float* x, int n_ch, hipStream_t s);
 long long count_nonzeros(const GeomTables& t, hipStream_t s);
 
 // ---------------------------------------------------------------- problem
@@ -219,7 +223,7 @@ struct PenaltyArgs {
     float delta;
 };
 int launch_penalty_grad(const PenaltyArgs& a, const float* x, const float* gL, const float* dL,
-                        float* g, float* d, double* phi_partials, hipStream_t s);
+                        float* g, float* d, double* phi_partials, hipStream_t s, const float* gL2 = nullptr);
 int launch_penalty_quadform(const PenaltyArgs& a, const float* x, const float* p, double* partials,
                             hipStream_t s);
 void launch_penalty_hess_add(const PenaltyArgs& a, const float* v, float* out, hipStream_t s);
@@ -228,6 +232,9 @@ void launch_inv_var(int n, const float* y, float* w, hipStream_t s);
 void launch_scale_by_vec(int n, int nch, const float* in, const float* vec, float* out, hipStream_t s);
 void launch_fill_double(int n, double* x, double value, hipStream_t s);
 void launch_axpy_alpha(int n, float* x, const float* p, const double* alpha, hipStream_t s);
+// x1 += alpha p1 (n1 floats) and x2 += alpha p2 (n2 floats) in one launch.
+void launch_axpy2_alpha(int n1, float* x1, const float* p1, int n2, float* x2, const float* p2,
+                        const double* alpha, hipStream_t s);
 void launch_fill(int n, float* x, float value, hipStream_t s);
 void launch_scale_copy(int n, const float* in, float* out, float scale, hipStream_t s);
 int launch_dot(int n, const float* a, const float* b, double* partials, hipStream_t s);

@@ -245,7 +245,8 @@ __global__ __launch_bounds__(kThreads) void k_dd_forward(const ViewParams* __res
 // per wavefront give each wave LPW independent load chains per view, which is
 // what hides the memory latency, and let the whole launch fit in one round of
 // resident waves.  Row sweeps write x; column sweeps write their partial image
-// (layout [ix][iy]) to part, added by k_back_reduce.
+// to part in the image's own layout (scattered 4-byte stores, once per pixel),
+// which the caller adds -- the iteration does it inside the penalty kernel.
 template <int NCH, int LPW>
 __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__ line_tab, int nv0, int nv1,
                                                       FrameSplit fs, int nx, int ny, int V, int B,
@@ -351,41 +352,19 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
 #pragma unroll
         for (int c = 0; c < NCH; ++c) val[c] = (float)(next_lane(acc[j][c]) - acc[j][c]);
         if (lane < kPerWave && pe < Np && q0 + j < Nq) {
-            const size_t pix = (size_t)(q0 + j) * Np + pe;    // frame layout [q][p]
+            // image layout: rows sweep (iy = q, ix = pe), columns sweep (iy = pe, ix = q)
+            const size_t pix = frame ? (size_t)pe * nx + (q0 + j) : (size_t)(q0 + j) * nx + pe;
 #pragma unroll
             for (int c = 0; c < NCH; ++c) dst[c * img_stride + pix] = val[c];
         }
     }
 }
 
-// x[c] = (accumulate ? x[c] : 0) + sum_{p < n0p} part[p][c] + sum_{n0p <= p < n0p+n1p} part[p][c]^T,
-// the transposed (column-sweep) partials through a 32 x 32 LDS tile; the sum
-// order is fixed, so results are reproducible.
-__global__ __launch_bounds__(kThreads) void k_back_reduce(const float* __restrict__ part, int n0p, int n1p,
-                                                          int nch, int nx, int ny, int accumulate,
-                                                          float* __restrict__ x) {
-    __shared__ float tile[32][33];
-    const size_t nj = (size_t)nx * ny;
-    const int c = blockIdx.z;
-    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;    // image tile origin (ix, iy)
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8 threads
-    for (int r = ty; r < 32; r += 8) {
-        const int ix = bx + r, iy = by + tx;                  // column layout [ix][iy], coalesced along iy
-        float v = 0.0f;
-        if (ix < nx && iy < ny)
-            for (int p = n0p; p < n0p + n1p; ++p) v += part[((size_t)p * nch + c) * nj + (size_t)ix * ny + iy];
-        tile[r][tx] = v;
-    }
-    __syncthreads();
-    for (int r = ty; r < 32; r += 8) {
-        const int iy = by + r, ix = bx + tx;
-        if (ix < nx && iy < ny) {
-            const size_t j = (size_t)iy * nx + ix;
-            float v = accumulate ? x[c * nj + j] : 0.0f;
-            for (int p = 0; p < n0p; ++p) v += part[((size_t)p * nch + c) * nj + j];
-            x[c * nj + j] = v + tile[tx][r];
-        }
-    }
+// x = (accumulate ? x : 0) + part, elementwise over n floats.
+__global__ __launch_bounds__(kThreads) void k_add_part(int n, const float* __restrict__ part, int accumulate,
+                                                       float* __restrict__ x) {
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) x[i] = accumulate ? x[i] + part[i] : part[i];
 }
 
 FrameSplit split(int items0, int items1) {
@@ -461,8 +440,10 @@ void back_kernel_launch(const GeomTables& t, float* x, hipStream_t s) {
     kt_.stop();
 }
 
+// Writes the row-sweep part of A^T sino to x (zero when no view sweeps rows) and
+// returns the column-sweep part, in image layout, or nullptr when there is none.
 template <int NCH>
-void back_launch(const GeomTables& t, const float* sino, float* x, hipStream_t s) {
+const float* back_launch(const GeomTables& t, const float* sino, float* x, hipStream_t s) {
     {
         KernelTimer kt_("k_detector_prefix", s);
         hipLaunchKernelGGL(k_detector_prefix, dim3(t.V, NCH), dim3(kScanThreads), 0, s, sino, t.path,
@@ -471,6 +452,7 @@ void back_launch(const GeomTables& t, const float* sino, float* x, hipStream_t s
     }
     MBMD_LAUNCHED();
     const int nv0 = t.n_frame_views[0], nv1 = t.n_frame_views[1];
+    if (!nv0) launch_fill(NCH * t.nx * t.ny, x, 0.0f, s);
     // two lines per wavefront when that is expected to be faster (NCH <= 2 keeps
     // the registers of two lines' loads within full occupancy)
     bool two = false;
@@ -494,13 +476,7 @@ void back_launch(const GeomTables& t, const float* sino, float* x, hipStream_t s
     else
         back_kernel_launch<NCH, 1>(t, x, s);
     MBMD_LAUNCHED();
-    if (nv1) {
-        KernelTimer kt_("k_back_reduce", s);
-        hipLaunchKernelGGL(k_back_reduce, dim3((t.nx + 31) / 32, (t.ny + 31) / 32, NCH), dim3(kThreads), 0, s,
-                           t.back_part, 0, 1, NCH, t.nx, t.ny, nv0 ? 1 : 0, x);
-        kt_.stop();
-        MBMD_LAUNCHED();
-    }
+    return nv1 ? t.back_part : nullptr;
 }
 
 // Number of (ray, pixel) pairs with a positive footprint overlap, i.e. the
@@ -560,20 +536,31 @@ void launch_project(const GeomTables& t, const float* x, float* sino, int n_mat,
     }
 }
 
-void launch_backproject(const GeomTables& t, const float* sino, float* x, int n_ch, hipStream_t s) {
+const float* launch_backproject_parts(const GeomTables& t, const float* sino, float* x, int n_ch, hipStream_t s) {
     MBMD_REQUIRE(n_ch >= 1 && n_ch <= kMaxBackCh, MBMD_ERR_SHAPE, "back projection channels must be in 1..10");
     MBMD_REQUIRE(t.det_prefix != nullptr && t.back_ch >= n_ch, MBMD_ERR_ARG, "back projection scratch too small");
     switch (n_ch) {
-        case 1: back_launch<1>(t, sino, x, s); break;
-        case 2: back_launch<2>(t, sino, x, s); break;
-        case 3: back_launch<3>(t, sino, x, s); break;
-        case 4: back_launch<4>(t, sino, x, s); break;
-        case 5: back_launch<5>(t, sino, x, s); break;
-        case 6: back_launch<6>(t, sino, x, s); break;
-        case 7: back_launch<7>(t, sino, x, s); break;
-        case 8: back_launch<8>(t, sino, x, s); break;
-        case 9: back_launch<9>(t, sino, x, s); break;
-        default: back_launch<10>(t, sino, x, s); break;
+        case 1: return back_launch<1>(t, sino, x, s);
+        case 2: return back_launch<2>(t, sino, x, s);
+        case 3: return back_launch<3>(t, sino, x, s);
+        case 4: return back_launch<4>(t, sino, x, s);
+        case 5: return back_launch<5>(t, sino, x, s);
+        case 6: return back_launch<6>(t, sino, x, s);
+        case 7: return back_launch<7>(t, sino, x, s);
+        case 8: return back_launch<8>(t, sino, x, s);
+        case 9: return back_launch<9>(t, sino, x, s);
+        default: return back_launch<10>(t, sino, x, s);
+    }
+}
+
+void launch_backproject(const GeomTables& t, const float* sino, float* x, int n_ch, hipStream_t s) {
+    const float* part = launch_backproject_parts(t, sino, x, n_ch, s);
+    if (part) {
+        const int n = n_ch * t.nx * t.ny;
+        KernelTimer kt_("k_add_part", s);
+        hipLaunchKernelGGL(k_add_part, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, n, part, 1, x);
+        kt_.stop();
+        MBMD_LAUNCHED();
     }
 }
 
