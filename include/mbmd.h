@@ -255,6 +255,11 @@ int mbmd_forward_vjp(mbmd_problem* prob, const float* l_dev, const float* gbar_d
 /*
  * Group problems (uneven sizes allowed, all on the current device) for a
  * batched iteration.  The problems are borrowed and must outlive the batch.
+ * Problems with the same geometry share projector tables and scratch, so
+ * they run in order; problems with different geometries run concurrently on
+ * up to 4 library-owned streams (default priority) forked from the caller's
+ * stream and joined back into it.  Errors: MBMD_ERR_ARG, MBMD_ERR_UNSUPPORTED
+ * (identity geometry), MBMD_ERR_HIP (stream or event creation).
  */
 int mbmd_batch_create(mbmd_problem* const* probs, int n, mbmd_batch** out);
 void mbmd_batch_destroy(mbmd_batch* batch);
@@ -262,9 +267,12 @@ void mbmd_batch_destroy(mbmd_batch* batch);
 /*
  * n_iter iterations of every problem of the batch (x_dev[i] belongs to
  * problem i).  use_graph != 0 captures one iteration over all problems in a
- * hipGraph on the first call and replays it; the same x pointers must be
- * passed on later calls (a change re-captures).  Preconditioners must have
- * been built.  No objective trace.
+ * hipGraph on the first call (the geometry groups as parallel branches) and
+ * replays it on `stream`; the same x pointers must be passed on later calls
+ * (a change re-captures).  use_graph == 0 enqueues every iteration of each
+ * geometry group on its stream.  Either way the work is ordered after what
+ * `stream` held before the call and before what it receives after it.
+ * Preconditioners must have been built.  No objective trace.
  */
 int mbmd_batch_sps_step(mbmd_batch* batch, float* const* x_dev, int precond, int n_iter,
                         int use_graph, void* stream);

@@ -18,8 +18,16 @@
 
 struct mbmd_problem : public mbmd::Problem {};
 
+// Problems that share projector tables (same geometry) share their scratch
+// buffers, so they run in order on one stream; different geometries run on
+// different library-owned streams (at most kBatchStreams) forked from and
+// joined back into the caller's stream -- or, captured, as parallel branches
+// of one graph per iteration.
+constexpr int kBatchStreams = 4;
 struct mbmd_batch {
     std::vector<mbmd_problem*> probs;
+    std::vector<int> lane;              // branch stream of each problem
+    int n_lanes = 0;
     std::vector<float*> xs;
     int precond = -1;
     hipGraph_t graph[2] = {nullptr, nullptr};
@@ -27,6 +35,9 @@ struct mbmd_batch {
     bool captured = false;
     hipStream_t stream = nullptr;       // caller stream the graphs were last launched on
     hipStream_t capture = nullptr;      // library-owned stream used only for capture
+    hipStream_t branch[kBatchStreams] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kBatchStreams] = {};
 };
 
 namespace mbmd {
@@ -631,11 +642,22 @@ int mbmd_batch_create(mbmd_problem* const* probs, int n, mbmd_batch** out) {
     return guarded([&] {
         MBMD_REQUIRE(probs && n > 0 && out, MBMD_ERR_ARG, "bad argument");
         std::unique_ptr<mbmd_batch> b(new mbmd_batch());
+        std::vector<const GeomTables*> geoms;
         for (int i = 0; i < n; ++i) {
             MBMD_REQUIRE(probs[i] != nullptr, MBMD_ERR_ARG, "NULL problem in batch");
             MBMD_REQUIRE(!probs[i]->identity, MBMD_ERR_UNSUPPORTED, "batches hold projector geometries");
             b->probs.push_back(probs[i]);
+            const GeomTables* g = probs[i]->geom;
+            int gi = (int)(std::find(geoms.begin(), geoms.end(), g) - geoms.begin());
+            if (gi == (int)geoms.size()) geoms.push_back(g);
+            b->lane.push_back(gi % kBatchStreams);
         }
+        b->n_lanes = (int)std::min<size_t>(geoms.size(), kBatchStreams);
+        for (int i = 0; i < b->n_lanes; ++i) {
+            MBMD_HIP(hipStreamCreateWithFlags(&b->branch[i], hipStreamNonBlocking));
+            MBMD_HIP(hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming));
+        }
+        MBMD_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
         *out = b.release();
     });
 }
@@ -648,6 +670,14 @@ void mbmd_batch_destroy(mbmd_batch* b) {
         if (b->graph[i]) (void)hipGraphDestroy(b->graph[i]);
     }
     if (b->capture) (void)hipStreamDestroy(b->capture);
+    for (int i = 0; i < b->n_lanes; ++i) {
+        if (b->branch[i]) {
+            (void)hipStreamSynchronize(b->branch[i]);
+            (void)hipStreamDestroy(b->branch[i]);
+        }
+        if (b->join[i]) (void)hipEventDestroy(b->join[i]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
     delete b;
 }
 
@@ -662,23 +692,38 @@ int mbmd_batch_sps_step(mbmd_batch* b, float* const* x_dev, int precond, int n_i
             b->probs[i]->last_stream = s;
             if (precond == MBMD_PRECOND_NONE) ensure_dL_const(*b->probs[i], s);
         }
-        auto enqueue = [&](bool refresh) {
-            for (size_t i = 0; i < n; ++i) {
-                Problem& P = *b->probs[i];
-                if (precond == MBMD_PRECOND_NONE) {
-                    plain_iteration(P, x_dev[i], nullptr, s);
-                } else {
-                    if (refresh) project(P, x_dev[i], P.l, P.K, s);
-                    precond_iteration(P, x_dev[i], precond, nullptr, s);
-                }
+        // one slice iteration on its branch stream
+        auto slice_iter = [&](size_t k, bool refresh) {
+            Problem& P = *b->probs[k];
+            hipStream_t bs = b->branch[b->lane[k]];
+            if (precond == MBMD_PRECOND_NONE) {
+                plain_iteration(P, x_dev[k], nullptr, bs);
+            } else {
+                if (refresh) project(P, x_dev[k], P.l, P.K, bs);
+                precond_iteration(P, x_dev[k], precond, nullptr, bs);
+            }
+        };
+        auto fork = [&](hipStream_t from) {
+            MBMD_HIP(hipEventRecord(b->fork, from));
+            for (int i = 0; i < b->n_lanes; ++i) MBMD_HIP(hipStreamWaitEvent(b->branch[i], b->fork, 0));
+        };
+        auto join = [&](hipStream_t into) {
+            for (int i = 0; i < b->n_lanes; ++i) {
+                MBMD_HIP(hipEventRecord(b->join[i], b->branch[i]));
+                MBMD_HIP(hipStreamWaitEvent(into, b->join[i], 0));
             }
         };
         if (!use_graph) {
-            for (int it = 0; it < n_iter; ++it) enqueue(it % kRefreshEvery == 0);
+            // the slices are independent: each branch runs all its iterations, then joins
+            fork(s);
+            for (int it = 0; it < n_iter; ++it)
+                for (size_t k = 0; k < n; ++k) slice_iter(k, it % kRefreshEvery == 0);
+            join(s);
             return;
         }
         // Capture on a library-owned stream (the legacy default stream cannot be
-        // captured); the instantiated graphs are then launched on the caller's stream.
+        // captured); the branches join the capture through the fork event, and the
+        // instantiated graphs are then launched on the caller's stream.
         bool same = b->captured && b->precond == precond && b->xs.size() == n;
         for (size_t i = 0; same && i < n; ++i) same = b->xs[i] == x_dev[i];
         if (!same) {
@@ -695,15 +740,9 @@ int mbmd_batch_sps_step(mbmd_batch* b, float* const* x_dev, int precond, int n_i
             for (int i = 0; i < 2; ++i) {
                 MBMD_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
                 try {
-                    for (size_t k = 0; k < n; ++k) {
-                        Problem& P = *b->probs[k];
-                        if (precond == MBMD_PRECOND_NONE) {
-                            plain_iteration(P, x_dev[k], nullptr, cs);
-                        } else {
-                            if (i == 1) project(P, x_dev[k], P.l, P.K, cs);
-                            precond_iteration(P, x_dev[k], precond, nullptr, cs);
-                        }
-                    }
+                    fork(cs);
+                    for (size_t k = 0; k < n; ++k) slice_iter(k, i == 1);
+                    join(cs);
                 } catch (...) {
                     hipGraph_t g = nullptr;
                     (void)hipStreamEndCapture(cs, &g);
