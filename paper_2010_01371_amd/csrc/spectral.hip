@@ -42,17 +42,45 @@ struct RayModel {
     const float *Q, *S, *rowS, *Qsum;
 };
 
+// Spectral tables staged in LDS once per block, per energy contiguous:
+// Q[e][k], S[e][c] (transposed from [c][e]) and Qsum[e]; every lane reads the
+// same entry, which LDS broadcasts.  KT / CT > 0 fix N_k / N_c at compile time
+// (the loops over materials and channels unroll into registers); 0 reads them
+// from the model.
+struct SharedModel {
+    float Q[kMaxEnergy * kMaxMat];
+    float S[kMaxEnergy * kMaxChan];
+    float Qsum[kMaxEnergy];
+};
+
+template <int KT, int CT>
+__device__ __forceinline__ void stage_model(const RayModel& m, SharedModel& sm) {
+    const int K = KT ? KT : m.K, C = CT ? CT : m.C;
+    for (int i = threadIdx.x; i < m.E * K; i += blockDim.x) sm.Q[i] = m.Q[i];
+    for (int i = threadIdx.x; i < m.E * C; i += blockDim.x) {
+        const int e = i / C, c = i - e * C;
+        sm.S[i] = m.S[c * m.E + e];
+    }
+    for (int i = threadIdx.x; i < m.E; i += blockDim.x) sm.Qsum[i] = m.Qsum ? m.Qsum[i] : 0.0f;
+    __syncthreads();
+}
+
 // Pass 1: ybar_c for the ray with line integrals lk.
-__device__ __forceinline__ void channel_means(const RayModel& m, const float* lk, float* ybar) {
-    for (int c = 0; c < m.C; ++c) ybar[c] = 0.0f;
+template <int KT, int CT>
+__device__ __forceinline__ void channel_means(const RayModel& m, const SharedModel& sm, const float* lk,
+                                              float* ybar) {
+    const int K = KT ? KT : m.K, C = CT ? CT : m.C;
+    for (int c = 0; c < C; ++c) ybar[c] = 0.0f;
+#pragma unroll 2
     for (int e = 0; e < m.E; ++e) {
         float le = 0.0f;
-        for (int k = 0; k < m.K; ++k) le = fmaf(m.Q[e * m.K + k], lk[k], le);
+        for (int k = 0; k < K; ++k) le = fmaf(sm.Q[e * K + k], lk[k], le);
         const float t = expf(-le);
-        for (int c = 0; c < m.C; ++c) ybar[c] = fmaf(m.S[c * m.E + e], t, ybar[c]);
+        for (int c = 0; c < C; ++c) ybar[c] = fmaf(sm.S[e * C + c], t, ybar[c]);
     }
 }
 
+template <int KT, int CT>
 __global__ __launch_bounds__(kRayThreads) void k_ray_grad(RayModel m, int ni, const float* __restrict__ l,
                                                           const float* __restrict__ y,
                                                           const float* __restrict__ w,
@@ -61,13 +89,16 @@ __global__ __launch_bounds__(kRayThreads) void k_ray_grad(RayModel m, int ni, co
                                                           float* __restrict__ r_out,
                                                           double* __restrict__ partials) {
     __shared__ double sh[kRayThreads / 64];
+    __shared__ SharedModel sm;
+    stage_model<KT, CT>(m, sm);
+    const int K = KT ? KT : m.K, C = CT ? CT : m.C;
     const int i = blockIdx.x * kRayThreads + threadIdx.x;
     double phi = 0.0;
     if (i < ni) {
         float lk[kMaxMat], ybar[kMaxChan], rc[kMaxChan], sig[kMaxChan];
-        for (int k = 0; k < m.K; ++k) lk[k] = l[(size_t)k * ni + i];
-        channel_means(m, lk, ybar);
-        for (int c = 0; c < m.C; ++c) {
+        for (int k = 0; k < K; ++k) lk[k] = l[(size_t)k * ni + i];
+        channel_means<KT, CT>(m, sm, lk, ybar);
+        for (int c = 0; c < C; ++c) {
             const float yc = y[(size_t)c * ni + i], wc = w[(size_t)c * ni + i];
             const float dv = ybar[c] - yc;
             rc[c] = wc * dv;
@@ -77,27 +108,28 @@ __global__ __launch_bounds__(kRayThreads) void k_ray_grad(RayModel m, int ni, co
         }
         const float gA = gammaA ? gammaA[i] : 1.0f;
         float uk[kMaxMat], vk[kMaxMat];
-        for (int k = 0; k < m.K; ++k) uk[k] = vk[k] = 0.0f;
+        for (int k = 0; k < K; ++k) uk[k] = vk[k] = 0.0f;
+#pragma unroll 2
         for (int e = 0; e < m.E; ++e) {
             float le = 0.0f;
-            for (int k = 0; k < m.K; ++k) le = fmaf(m.Q[e * m.K + k], lk[k], le);
+            for (int k = 0; k < K; ++k) le = fmaf(sm.Q[e * K + k], lk[k], le);
             const float t = expf(-le);
             float s = 0.0f, eta = 0.0f;
-            for (int c = 0; c < m.C; ++c) {
-                const float sce = m.S[c * m.E + e];
+            for (int c = 0; c < C; ++c) {
+                const float sce = sm.S[e * C + c];
                 s = fmaf(sce, rc[c], s);
                 eta = fmaf(sce, sig[c], eta);
             }
             const float hdot = -t * s;
             const float ce = fmaxf(2.0f * eta + s - eta * t, 0.0f);
-            const float gc = gA * m.Qsum[e] * ce;
-            for (int k = 0; k < m.K; ++k) {
-                const float qek = m.Q[e * m.K + k];
+            const float gc = gA * sm.Qsum[e] * ce;
+            for (int k = 0; k < K; ++k) {
+                const float qek = sm.Q[e * K + k];
                 uk[k] = fmaf(qek, hdot, uk[k]);
                 vk[k] = fmaf(qek, gc, vk[k]);
             }
         }
-        for (int k = 0; k < m.K; ++k) {
+        for (int k = 0; k < K; ++k) {
             u[(size_t)k * ni + i] = uk[k];
             if (v) v[(size_t)k * ni + i] = vk[k];
         }
@@ -107,35 +139,41 @@ __global__ __launch_bounds__(kRayThreads) void k_ray_grad(RayModel m, int ni, co
 }
 
 // sum_iE c_iE q_iE^2 with q_iE = sum_k Q_Ek q_ik, c recomputed from l and r.
+template <int KT, int CT>
 __global__ __launch_bounds__(kRayThreads) void k_ray_curv(RayModel m, int ni, const float* __restrict__ l,
                                                           const float* __restrict__ r,
                                                           const float* __restrict__ w,
                                                           const float* __restrict__ q,
                                                           double* __restrict__ partials) {
     __shared__ double sh[kRayThreads / 64];
+    __shared__ SharedModel sm;
+    stage_model<KT, CT>(m, sm);
+    const int K = KT ? KT : m.K, C = CT ? CT : m.C;
     const int i = blockIdx.x * kRayThreads + threadIdx.x;
     double acc = 0.0;
     if (i < ni) {
         float lk[kMaxMat], qk[kMaxMat], rc[kMaxChan], sig[kMaxChan];
-        for (int k = 0; k < m.K; ++k) {
+        for (int k = 0; k < K; ++k) {
             lk[k] = l[(size_t)k * ni + i];
             qk[k] = q[(size_t)k * ni + i];
         }
-        for (int c = 0; c < m.C; ++c) {
+        for (int c = 0; c < C; ++c) {
             rc[c] = r[(size_t)c * ni + i];
             sig[c] = w[(size_t)c * ni + i] * m.rowS[c];
         }
         float a = 0.0f;
+#pragma unroll 2
         for (int e = 0; e < m.E; ++e) {
             float le = 0.0f, qe = 0.0f;
-            for (int k = 0; k < m.K; ++k) {
-                le = fmaf(m.Q[e * m.K + k], lk[k], le);
-                qe = fmaf(m.Q[e * m.K + k], qk[k], qe);
+            for (int k = 0; k < K; ++k) {
+                const float qek = sm.Q[e * K + k];
+                le = fmaf(qek, lk[k], le);
+                qe = fmaf(qek, qk[k], qe);
             }
             const float t = expf(-le);
             float s = 0.0f, eta = 0.0f;
-            for (int c = 0; c < m.C; ++c) {
-                const float sce = m.S[c * m.E + e];
+            for (int c = 0; c < C; ++c) {
+                const float sce = sm.S[e * C + c];
                 s = fmaf(sce, rc[c], s);
                 eta = fmaf(sce, sig[c], eta);
             }
@@ -148,38 +186,47 @@ __global__ __launch_bounds__(kRayThreads) void k_ray_curv(RayModel m, int ni, co
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
+template <int KT, int CT>
 __global__ __launch_bounds__(kRayThreads) void k_forward_model(RayModel m, int ni, const float* __restrict__ l,
                                                                float* __restrict__ ybar_out) {
+    __shared__ SharedModel sm;
+    stage_model<KT, CT>(m, sm);
+    const int K = KT ? KT : m.K, C = CT ? CT : m.C;
     const int i = blockIdx.x * kRayThreads + threadIdx.x;
     if (i >= ni) return;
     float lk[kMaxMat], ybar[kMaxChan];
-    for (int k = 0; k < m.K; ++k) lk[k] = l[(size_t)k * ni + i];
-    channel_means(m, lk, ybar);
-    for (int c = 0; c < m.C; ++c) ybar_out[(size_t)c * ni + i] = ybar[c];
+    for (int k = 0; k < K; ++k) lk[k] = l[(size_t)k * ni + i];
+    channel_means<KT, CT>(m, sm, lk, ybar);
+    for (int c = 0; c < C; ++c) ybar_out[(size_t)c * ni + i] = ybar[c];
 }
 
 // s_k = sum_E Q_Ek (-t_E) sum_c S_cE gbar_c
+template <int KT, int CT>
 __global__ __launch_bounds__(kRayThreads) void k_forward_vjp(RayModel m, int ni, const float* __restrict__ l,
                                                              const float* __restrict__ gbar,
                                                              float* __restrict__ sk) {
+    __shared__ SharedModel sm;
+    stage_model<KT, CT>(m, sm);
+    const int K = KT ? KT : m.K, C = CT ? CT : m.C;
     const int i = blockIdx.x * kRayThreads + threadIdx.x;
     if (i >= ni) return;
     float lk[kMaxMat], gc[kMaxChan], acc[kMaxMat];
-    for (int k = 0; k < m.K; ++k) {
+    for (int k = 0; k < K; ++k) {
         lk[k] = l[(size_t)k * ni + i];
         acc[k] = 0.0f;
     }
-    for (int c = 0; c < m.C; ++c) gc[c] = gbar[(size_t)c * ni + i];
+    for (int c = 0; c < C; ++c) gc[c] = gbar[(size_t)c * ni + i];
+#pragma unroll 2
     for (int e = 0; e < m.E; ++e) {
         float le = 0.0f;
-        for (int k = 0; k < m.K; ++k) le = fmaf(m.Q[e * m.K + k], lk[k], le);
+        for (int k = 0; k < K; ++k) le = fmaf(sm.Q[e * K + k], lk[k], le);
         const float t = expf(-le);
         float s = 0.0f;
-        for (int c = 0; c < m.C; ++c) s = fmaf(m.S[c * m.E + e], gc[c], s);
+        for (int c = 0; c < C; ++c) s = fmaf(sm.S[e * C + c], gc[c], s);
         const float f = -t * s;
-        for (int k = 0; k < m.K; ++k) acc[k] = fmaf(m.Q[e * m.K + k], f, acc[k]);
+        for (int k = 0; k < K; ++k) acc[k] = fmaf(sm.Q[e * K + k], f, acc[k]);
     }
-    for (int k = 0; k < m.K; ++k) sk[(size_t)k * ni + i] = acc[k];
+    for (int k = 0; k < K; ++k) sk[(size_t)k * ni + i] = acc[k];
 }
 
 // Fisher weights W_i = J^T diag(w) J, J[c,k] = -sum_E S_cE D_E Q_Ek, with the
@@ -260,6 +307,7 @@ __global__ __launch_bounds__(kRayThreads) void k_fisher_mix(int ni, int K, const
 // precond 0: plain SPS, x -= g / d.  precond 3: p = -M0 M0 g, per-ray alpha
 // from the 1D majoriser.  Objective partials of iteration it go to
 // partials[it * stride + block], the final one to partials[n_iter * stride + block].
+template <int KT, int CT>
 __global__ __launch_bounds__(kRayThreads) void k_identity_iterate(RayModel m, int ni, float* __restrict__ x,
                                                                   const float* __restrict__ y,
                                                                   const float* __restrict__ w,
@@ -268,13 +316,16 @@ __global__ __launch_bounds__(kRayThreads) void k_identity_iterate(RayModel m, in
                                                                   double* __restrict__ partials,
                                                                   int stride) {
     __shared__ double sh[kRayThreads / 64];
+    __shared__ SharedModel sm;
+    stage_model<KT, CT>(m, sm);
+    const int K = KT ? KT : K, C = CT ? CT : C;
     const int i = blockIdx.x * kRayThreads + threadIdx.x;
     const bool act = i < ni;
     float xk[kMaxMat], yc[kMaxChan], wc[kMaxChan], sig[kMaxChan], Mb[kMaxPacked];
-    const int npk = m.K * (m.K + 1) / 2;
+    const int npk = K * (K + 1) / 2;
     if (act) {
-        for (int k = 0; k < m.K; ++k) xk[k] = x[(size_t)k * ni + i];
-        for (int c = 0; c < m.C; ++c) {
+        for (int k = 0; k < K; ++k) xk[k] = x[(size_t)k * ni + i];
+        for (int c = 0; c < C; ++c) {
             yc[c] = y[(size_t)c * ni + i];
             wc[c] = w[(size_t)c * ni + i];
             sig[c] = wc[c] * m.rowS[c];
@@ -286,8 +337,8 @@ __global__ __launch_bounds__(kRayThreads) void k_identity_iterate(RayModel m, in
         double phi = 0.0;
         float rc[kMaxChan], ybar[kMaxChan];
         if (act) {
-            channel_means(m, xk, ybar);
-            for (int c = 0; c < m.C; ++c) {
+            channel_means<KT, CT>(m, sm, xk, ybar);
+            for (int c = 0; c < C; ++c) {
                 const float dv = ybar[c] - yc[c];
                 rc[c] = wc[c] * dv;
                 phi += 0.5 * (double)wc[c] * (double)dv * (double)dv;
@@ -297,53 +348,55 @@ __global__ __launch_bounds__(kRayThreads) void k_identity_iterate(RayModel m, in
         if (threadIdx.x == 0) partials[(size_t)it * stride + blockIdx.x] = tot;
         if (it == n_iter || !act) continue;
         float gk[kMaxMat], dk[kMaxMat];
-        for (int k = 0; k < m.K; ++k) gk[k] = dk[k] = 0.0f;
+        for (int k = 0; k < K; ++k) gk[k] = dk[k] = 0.0f;
+#pragma unroll 2
         for (int e = 0; e < m.E; ++e) {
             float le = 0.0f;
-            for (int k = 0; k < m.K; ++k) le = fmaf(m.Q[e * m.K + k], xk[k], le);
+            for (int k = 0; k < K; ++k) le = fmaf(sm.Q[e * K + k], xk[k], le);
             const float t = expf(-le);
             float s = 0.0f, eta = 0.0f;
-            for (int c = 0; c < m.C; ++c) {
-                const float sce = m.S[c * m.E + e];
+            for (int c = 0; c < C; ++c) {
+                const float sce = sm.S[e * C + c];
                 s = fmaf(sce, rc[c], s);
                 eta = fmaf(sce, sig[c], eta);
             }
             const float hdot = -t * s;
             const float ce = fmaxf(2.0f * eta + s - eta * t, 0.0f);
-            const float gc = m.Qsum[e] * ce;
-            for (int k = 0; k < m.K; ++k) {
-                gk[k] = fmaf(m.Q[e * m.K + k], hdot, gk[k]);
-                dk[k] = fmaf(m.Q[e * m.K + k], gc, dk[k]);
+            const float gc = sm.Qsum[e] * ce;
+            for (int k = 0; k < K; ++k) {
+                gk[k] = fmaf(sm.Q[e * K + k], hdot, gk[k]);
+                dk[k] = fmaf(sm.Q[e * K + k], gc, dk[k]);
             }
         }
         if (precond != MBMD_PRECOND_BLOCKDIAG) {
-            for (int k = 0; k < m.K; ++k) xk[k] -= gk[k] / fmaxf(dk[k], 1e-30f);
+            for (int k = 0; k < K; ++k) xk[k] -= gk[k] / fmaxf(dk[k], 1e-30f);
             continue;
         }
         float h[kMaxMat], p[kMaxMat];
-        for (int k = 0; k < m.K; ++k) {
+        for (int k = 0; k < K; ++k) {
             float s = 0.0f;
-            for (int l2 = 0; l2 < m.K; ++l2) s = fmaf(Mb[packed_index(k, l2, m.K)], gk[l2], s);
+            for (int l2 = 0; l2 < K; ++l2) s = fmaf(Mb[packed_index(k, l2, K)], gk[l2], s);
             h[k] = s;
         }
         float num = 0.0f;
-        for (int k = 0; k < m.K; ++k) {
+        for (int k = 0; k < K; ++k) {
             float s = 0.0f;
-            for (int l2 = 0; l2 < m.K; ++l2) s = fmaf(Mb[packed_index(k, l2, m.K)], h[l2], s);
+            for (int l2 = 0; l2 < K; ++l2) s = fmaf(Mb[packed_index(k, l2, K)], h[l2], s);
             p[k] = -s;
             num = fmaf(-gk[k], p[k], num);
         }
         float den = 0.0f;
+#pragma unroll 2
         for (int e = 0; e < m.E; ++e) {
             float le = 0.0f, qe = 0.0f;
-            for (int k = 0; k < m.K; ++k) {
-                le = fmaf(m.Q[e * m.K + k], xk[k], le);
-                qe = fmaf(m.Q[e * m.K + k], p[k], qe);
+            for (int k = 0; k < K; ++k) {
+                le = fmaf(sm.Q[e * K + k], xk[k], le);
+                qe = fmaf(sm.Q[e * K + k], p[k], qe);
             }
             const float t = expf(-le);
             float s = 0.0f, eta = 0.0f;
-            for (int c = 0; c < m.C; ++c) {
-                const float sce = m.S[c * m.E + e];
+            for (int c = 0; c < C; ++c) {
+                const float sce = sm.S[e * C + c];
                 s = fmaf(sce, rc[c], s);
                 eta = fmaf(sce, sig[c], eta);
             }
@@ -351,15 +404,26 @@ __global__ __launch_bounds__(kRayThreads) void k_identity_iterate(RayModel m, in
             den = fmaf(ce * qe, qe, den);
         }
         const float alpha = den > 0.0f ? num / den : 0.0f;
-        for (int k = 0; k < m.K; ++k) xk[k] = fmaf(alpha, p[k], xk[k]);
+        for (int k = 0; k < K; ++k) xk[k] = fmaf(alpha, p[k], xk[k]);
     }
     if (act)
-        for (int k = 0; k < m.K; ++k) x[(size_t)k * ni + i] = xk[k];
+        for (int k = 0; k < K; ++k) x[(size_t)k * ni + i] = xk[k];
 }
 
 RayModel model_of(const RayArgs& a) { return RayModel{a.K, a.E, a.C, a.Q, a.S, a.rowS, a.Qsum}; }
 
 int blocks_for(int n) { return (n + kRayThreads - 1) / kRayThreads; }
+
+// Compile-time (N_k, N_c) for the shapes in use; anything else runs the generic form.
+#define MBMD_RAY_DISPATCH(K, C, LAUNCH)                \
+    do {                                                \
+        if ((K) == 1 && (C) == 1) { LAUNCH(1, 1); }     \
+        else if ((K) == 2 && (C) == 2) { LAUNCH(2, 2); } \
+        else if ((K) == 3 && (C) == 4) { LAUNCH(3, 4); } \
+        else { LAUNCH(0, 0); }                          \
+    } while (0)
+
+
 
 }  // namespace
 
@@ -369,8 +433,10 @@ int launch_ray_grad(const RayArgs& a, const float* l, float* u, float* v, float*
     MBMD_REQUIRE(nb <= kMaxPartials, MBMD_ERR_SHAPE, "too many rays for the partial-sum buffer");
     {
         KernelTimer kt_("k_ray_grad", s);
-        hipLaunchKernelGGL(k_ray_grad, dim3(nb), dim3(kRayThreads), 0, s, model_of(a), a.ni, l, a.y, a.w,
-                       a.gammaA, u, v, r, phi_partials);
+#define L_(KT, CT) hipLaunchKernelGGL((k_ray_grad<KT, CT>), dim3(nb), dim3(kRayThreads), 0, s, model_of(a), a.ni, \
+                                   l, a.y, a.w, a.gammaA, u, v, r, phi_partials)
+        MBMD_RAY_DISPATCH(a.K, a.C, L_);
+#undef L_
         kt_.stop();
     }
     MBMD_LAUNCHED();
@@ -383,8 +449,10 @@ int launch_ray_curv(const RayArgs& a, const float* l, const float* r, const floa
     MBMD_REQUIRE(nb <= kMaxPartials, MBMD_ERR_SHAPE, "too many rays for the partial-sum buffer");
     {
         KernelTimer kt_("k_ray_curv", s);
-        hipLaunchKernelGGL(k_ray_curv, dim3(nb), dim3(kRayThreads), 0, s, model_of(a), a.ni, l, r, a.w, q,
-                       partials);
+#define L_(KT, CT) hipLaunchKernelGGL((k_ray_curv<KT, CT>), dim3(nb), dim3(kRayThreads), 0, s, model_of(a), a.ni, \
+                                   l, r, a.w, q, partials)
+        MBMD_RAY_DISPATCH(a.K, a.C, L_);
+#undef L_
         kt_.stop();
     }
     MBMD_LAUNCHED();
@@ -394,8 +462,10 @@ int launch_ray_curv(const RayArgs& a, const float* l, const float* r, const floa
 void launch_forward_model(const RayArgs& a, const float* l, float* ybar, hipStream_t s) {
     {
         KernelTimer kt_("k_forward_model", s);
-        hipLaunchKernelGGL(k_forward_model, dim3(blocks_for(a.ni)), dim3(kRayThreads), 0, s, model_of(a), a.ni,
-                       l, ybar);
+#define L_(KT, CT) hipLaunchKernelGGL((k_forward_model<KT, CT>), dim3(blocks_for(a.ni)), dim3(kRayThreads), 0, s, \
+                                   model_of(a), a.ni, l, ybar)
+        MBMD_RAY_DISPATCH(a.K, a.C, L_);
+#undef L_
         kt_.stop();
     }
     MBMD_LAUNCHED();
@@ -404,8 +474,10 @@ void launch_forward_model(const RayArgs& a, const float* l, float* ybar, hipStre
 void launch_forward_vjp(const RayArgs& a, const float* l, const float* gbar, float* sk, hipStream_t s) {
     {
         KernelTimer kt_("k_forward_vjp", s);
-        hipLaunchKernelGGL(k_forward_vjp, dim3(blocks_for(a.ni)), dim3(kRayThreads), 0, s, model_of(a), a.ni,
-                       l, gbar, sk);
+#define L_(KT, CT) hipLaunchKernelGGL((k_forward_vjp<KT, CT>), dim3(blocks_for(a.ni)), dim3(kRayThreads), 0, s, \
+                                   model_of(a), a.ni, l, gbar, sk)
+        MBMD_RAY_DISPATCH(a.K, a.C, L_);
+#undef L_
         kt_.stop();
     }
     MBMD_LAUNCHED();
@@ -436,8 +508,10 @@ int launch_identity_iterate(const RayArgs& a, float* x, const float* M0, int pre
     MBMD_REQUIRE(nb <= stride, MBMD_ERR_SHAPE, "too many rays for the partial-sum buffer");
     {
         KernelTimer kt_("k_identity_iterate", s);
-        hipLaunchKernelGGL(k_identity_iterate, dim3(nb), dim3(kRayThreads), 0, s, model_of(a), a.ni, x, a.y,
-                       a.w, M0, precond, n_iter, partials_per_iter, stride);
+#define L_(KT, CT) hipLaunchKernelGGL((k_identity_iterate<KT, CT>), dim3(nb), dim3(kRayThreads), 0, s, model_of(a), \
+                                   a.ni, x, a.y, a.w, M0, precond, n_iter, partials_per_iter, stride)
+        MBMD_RAY_DISPATCH(a.K, a.C, L_);
+#undef L_
         kt_.stop();
     }
     MBMD_LAUNCHED();
