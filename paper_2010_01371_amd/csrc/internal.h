@@ -121,6 +121,8 @@ struct GeomTables {
     double* det_prefix = nullptr;    // scratch: [back_ch][V][B] pairs (C[b], C[b+1]-C[b]) (FP64)
     // scratch: [back_ch][nx][ny] column-sweep part of a back projection
     float* back_part = nullptr;
+    // tile shape picked for the back projector per channel count (-1: not yet tuned)
+    mutable int back_variant[kMaxBackCh + 1] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
     int back_ch = 0;
     void* mem = nullptr;
     int device = -1;

@@ -44,6 +44,7 @@
 // part of a back projection is written in its own (transposed) layout and
 // added by a tiled transpose.
 #include <cmath>
+#include <cstdlib>
 
 #include "internal.h"
 
@@ -247,7 +248,7 @@ __global__ __launch_bounds__(kThreads) void k_dd_forward(const ViewParams* __res
 // resident waves.  Row sweeps write x; column sweeps write their partial image
 // to part in the image's own layout (scattered 4-byte stores, once per pixel),
 // which the caller adds -- the iteration does it inside the penalty kernel.
-template <int NCH, int LPW>
+template <int NCH, int LPW, int U>
 __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__ line_tab, int nv0, int nv1,
                                                       FrameSplit fs, int nx, int ny, int V, int B,
                                                       const double2* __restrict__ C, float* __restrict__ x,
@@ -276,11 +277,10 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
     for (int j = 0; j < LPW; ++j)
 #pragma unroll
         for (int c = 0; c < NCH; ++c) acc[j][c] = 0.0;
-    // Software pipeline over pairs of views: the per-line tables of the next
-    // pair are requested (scalar loads) only after this pair's values are in
+    // Software pipeline over groups of U views: the per-line tables of the next
+    // group are requested (scalar loads) only after this group's values are in
     // registers -- scalar loads complete out of order, so a wait for one waits
-    // for all -- and land while this pair's detector gathers are in flight.
-    constexpr int U = 2;
+    // for all -- and land while this group's detector gathers are in flight.
     float4 tm[U][LPW], tf[U][LPW];
     auto fetch = [&](int is) {
 #pragma unroll
@@ -327,11 +327,13 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) acc[j][c] += fma(h[u][j][c].y, (double)frs[u][j], h[u][j][c].x);
     }
-    static_assert(U == 2, "the tail below handles one remaining view");
-    if (is < nv) {                         // one remaining view; its tables were fetched into slot 0
+    // the remaining views (fewer than U); their tables were fetched into slots 0..
+#pragma unroll
+    for (int u = 0; u < U - 1; ++u) {
+        if (nfull + u >= nv) break;        // uniform
 #pragma unroll
         for (int j = 0; j < LPW; ++j) {
-            const float4 m = tm[0][j], f = tf[0][j];
+            const float4 m = tm[u][j], f = tf[u][j];
             const float num = fmaf(m.y, K, m.x);
             const float den = fmaf(m.w, K, m.z);
             const float bf = __builtin_amdgcn_fmed3f(floorf(num * fast_rcp(den)), f.z, f.w);
@@ -339,7 +341,7 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
             const float fr = __builtin_amdgcn_fmed3f(fmaf(-bf, den, num) * fmaf(-f.y, bf, f.x), 0.0f, 1.0f);
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
-                const double2 h = load_d2(tc, o, (c * V + slot0 + is) * crow);   // C[b], C[b+1] - C[b]
+                const double2 h = load_d2(tc, o, (c * V + slot0 + nfull + u) * crow);   // C[b], C[b+1] - C[b]
                 acc[j][c] += fma(h.y, (double)fr, h.x);
             }
         }
@@ -395,7 +397,7 @@ void fwd_launch(const GeomTables& t, float* sino, hipStream_t s) {
     MBMD_LAUNCHED();
 }
 
-// Wavefronts of k_dd_back<NCH, LPW> resident on the whole device at once.
+// Wavefronts of k_dd_back<NCH, LPW, 2> resident on the whole device at once.
 template <int NCH, int LPW>
 int back_waves_per_round() {
     static int cached[kMaxGpus] = {};
@@ -405,10 +407,27 @@ int back_waves_per_round() {
     if (!cached[dev]) {
         int cus = 0, occ = 0;
         MBMD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        MBMD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_dd_back<NCH, LPW>, kThreads, 0));
+        MBMD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_dd_back<NCH, LPW, 2>, kThreads, 0));
         cached[dev] = (cus > 0 ? cus : 1) * (occ > 0 ? occ : 1) * kWaves;
     }
     return cached[dev];
+}
+
+// Run-time tuning of tile shapes; MBMD_AUTOTUNE=0 in the environment turns it
+// off (the cost model then decides).
+bool autotune_enabled() {
+    static const bool on = [] {
+        const char* e = std::getenv("MBMD_AUTOTUNE");
+        return !(e && e[0] == '0');
+    }();
+    return on;
+}
+
+// MBMD_BACK_VARIANT=v (read on every call) forces back projector candidate v,
+// for tests that compare the candidates; -1 or unset leaves the choice to tuning.
+int forced_back_variant() {
+    const char* e = std::getenv("MBMD_BACK_VARIANT");
+    return e && e[0] ? std::atoi(e) : -1;
 }
 
 // Relative time of a back projection launch with LPW lines per wavefront:
@@ -427,7 +446,7 @@ double back_cost(long long waves, int per_round, int lpw, int simds) {
     return t;
 }
 
-template <int NCH, int LPW>
+template <int NCH, int LPW, int U>
 void back_kernel_launch(const GeomTables& t, float* x, hipStream_t s) {
     const int nv0 = t.n_frame_views[0], nv1 = t.n_frame_views[1];
     const int lines = kWaves * LPW;
@@ -435,7 +454,7 @@ void back_kernel_launch(const GeomTables& t, float* x, hipStream_t s) {
     const int u1 = nv1 ? ((t.ny + kPerWave - 1) / kPerWave) * ((t.nx + lines - 1) / lines) : 0;
     const FrameSplit fs = split(u0, u1);
     KernelTimer kt_("k_dd_back", s);
-    hipLaunchKernelGGL((k_dd_back<NCH, LPW>), dim3(grid_blocks(fs)), dim3(kThreads), 0, s, t.back_line, nv0, nv1, fs,
+    hipLaunchKernelGGL((k_dd_back<NCH, LPW, U>), dim3(grid_blocks(fs)), dim3(kThreads), 0, s, t.back_line, nv0, nv1, fs,
                        t.nx, t.ny, t.V, t.B, reinterpret_cast<const double2*>(t.det_prefix), x, t.back_part);
     kt_.stop();
 }
@@ -453,28 +472,69 @@ const float* back_launch(const GeomTables& t, const float* sino, float* x, hipSt
     MBMD_LAUNCHED();
     const int nv0 = t.n_frame_views[0], nv1 = t.n_frame_views[1];
     if (!nv0) launch_fill(NCH * t.nx * t.ny, x, 0.0f, s);
-    // two lines per wavefront when that is expected to be faster (NCH <= 2 keeps
-    // the registers of two lines' loads within full occupancy)
-    bool two = false;
-    if (NCH <= 2) {
-        int cus = 0, dev = 0;
-        MBMD_HIP(hipGetDevice(&dev));
-        MBMD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        const int simds = 4 * (cus > 0 ? cus : 1);
-        auto waves = [&](int lpw) {
-            const int lines = kWaves * lpw;
-            const long long u0 = nv0 ? (long long)((t.nx + kPerWave - 1) / kPerWave) * ((t.ny + lines - 1) / lines) : 0;
-            const long long u1 = nv1 ? (long long)((t.ny + kPerWave - 1) / kPerWave) * ((t.nx + lines - 1) / lines) : 0;
-            return (u0 + u1) * kWaves;
-        };
-        const double c1 = back_cost(waves(1), back_waves_per_round<NCH, 1>(), 1, simds);
-        const double c2 = back_cost(waves(2), back_waves_per_round<NCH <= 2 ? NCH : 1, 2>(), 2, simds);
-        two = c2 < c1;
+    // Tile shape: lines per wavefront x views in flight.  The first back
+    // projection of a geometry and channel count outside graph capture times
+    // the candidates on its own inputs (they give bit-identical results: the
+    // order of the sums over views is the same) and keeps the fastest; under
+    // capture, or when tuning is switched off, a round-count cost model picks.
+    using Launch = void (*)(const GeomTables&, float*, hipStream_t);
+    constexpr int N2 = NCH <= 2 ? NCH : 1;
+    const Launch cand[3] = {back_kernel_launch<NCH, 1, 2>, back_kernel_launch<NCH, 1, 4>,
+                            back_kernel_launch<N2, 2, 2>};
+    const int n_cand = NCH <= 2 ? 3 : 2;
+    int& choice = t.back_variant[NCH];
+    const int forced = forced_back_variant();
+    if (forced >= 0 && forced < n_cand) {           // testing hook: no tuning, nothing cached
+        cand[forced](t, x, s);
+        MBMD_LAUNCHED();
+        return nv1 ? t.back_part : nullptr;
     }
-    if (two)
-        back_kernel_launch<NCH <= 2 ? NCH : 1, 2>(t, x, s);
-    else
-        back_kernel_launch<NCH, 1>(t, x, s);
+    if (choice < 0) {
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        MBMD_HIP(hipStreamIsCapturing(s, &cap));
+        if (cap == hipStreamCaptureStatusNone && autotune_enabled()) {
+            hipEvent_t ev[2];
+            MBMD_HIP(hipEventCreate(&ev[0]));
+            MBMD_HIP(hipEventCreate(&ev[1]));
+            float best = 1e30f;
+            for (int v = 0; v < n_cand; ++v) {
+                cand[v](t, x, s);                      // warm-up
+                MBMD_HIP(hipEventRecord(ev[0], s));
+                for (int r = 0; r < 3; ++r) cand[v](t, x, s);
+                MBMD_HIP(hipEventRecord(ev[1], s));
+                MBMD_HIP(hipEventSynchronize(ev[1]));
+                float ms = 0.0f;
+                MBMD_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+                if (ms < best) {
+                    best = ms;
+                    choice = v;
+                }
+            }
+            (void)hipEventDestroy(ev[0]);
+            (void)hipEventDestroy(ev[1]);
+        } else {
+            int cus = 0, dev = 0;
+            MBMD_HIP(hipGetDevice(&dev));
+            MBMD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+            const int simds = 4 * (cus > 0 ? cus : 1);
+            auto waves = [&](int lpw) {
+                const int lines = kWaves * lpw;
+                const long long u0 = nv0 ? (long long)((t.nx + kPerWave - 1) / kPerWave) * ((t.ny + lines - 1) / lines) : 0;
+                const long long u1 = nv1 ? (long long)((t.ny + kPerWave - 1) / kPerWave) * ((t.nx + lines - 1) / lines) : 0;
+                return (u0 + u1) * kWaves;
+            };
+            const double c1 = back_cost(waves(1), back_waves_per_round<NCH, 1>(), 1, simds);
+            const double c2 = NCH <= 2 ? back_cost(waves(2), back_waves_per_round<N2, 2>(), 2, simds) : 1e300;
+            const int pick = c2 < c1 ? 2 : 0;
+            if (cap != hipStreamCaptureStatusNone) {
+                cand[pick](t, x, s);                   // not cached: tune on a later uncaptured call
+                MBMD_LAUNCHED();
+                return nv1 ? t.back_part : nullptr;
+            }
+            choice = pick;
+        }
+    }
+    cand[choice](t, x, s);
     MBMD_LAUNCHED();
     return nv1 ? t.back_part : nullptr;
 }

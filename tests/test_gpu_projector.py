@@ -138,3 +138,22 @@ def test_nonzero_count_matches_oracle(name):
     got = mb.projector_nnz(g)
     want = sum(OP.ray_weights(g, v, b)[0].size for v in range(g["n_views"]) for b in range(g["n_bins"]))
     assert abs(got - want) <= 5e-3 * want, (got, want)
+
+
+@pytest.mark.parametrize("nch", [1, 2, 3])
+def test_back_projector_tile_shapes_agree(nch, monkeypatch):
+    """Every tile shape the autotuner may pick (lines per wavefront x views in
+    flight) sums each pixel's views in the same order, so their outputs are
+    bitwise equal; and they match the oracle."""
+    g = GEOMS["fan_ragged"]
+    s = np.random.default_rng(7).uniform(size=(nch, g["n_views"], g["n_bins"]))
+    sd = dev(s)
+    outs = []
+    for v in range(3 if nch <= 2 else 2):
+        monkeypatch.setenv("MBMD_BACK_VARIANT", str(v))
+        announce("back tile shape", nch, v)
+        outs.append(host(mb.backproject(g, sd)))
+    monkeypatch.delenv("MBMD_BACK_VARIANT")
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+    assert maxrel(outs[0], OP.backproject(g, s)) <= TOL_PROJ
