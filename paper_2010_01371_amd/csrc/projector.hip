@@ -135,40 +135,34 @@ __global__ __launch_bounds__(kScanThreads) void k_line_prefix(const float* __res
 
 // Per slot and channel, for b = 0..B-1: the pair (C[b], C[b+1] - C[b]) with
 // C[b] = orient * sum_{b'<b} sino[b'] path[b'] (FP64); the view's orientation
-// sign makes H(K+1) - H(K) the pixel value.
-__global__ __launch_bounds__(kScanThreads) void k_detector_prefix(const float* __restrict__ sino,
-                                                                   const float* __restrict__ path,
-                                                                   const ViewParams* __restrict__ view, int V,
-                                                                   int B, double2* __restrict__ C) {
-    const int slot = blockIdx.x, ch = blockIdx.y;
+// sign makes H(K+1) - H(K) the pixel value.  One wavefront per (slot,
+// channel) walks the bins 64 at a time (coalesced loads and stores): an FP64
+// shuffle scan within the chunk plus the running total of the chunks before;
+// no barriers.
+constexpr int kPrefixWaves = 4;
+__global__ __launch_bounds__(64 * kPrefixWaves) void k_detector_prefix(const float* __restrict__ sino,
+                                                                        const float* __restrict__ path,
+                                                                        const ViewParams* __restrict__ view, int V,
+                                                                        int B, int nch, double2* __restrict__ C) {
+    const int task = blockIdx.x * kPrefixWaves + (threadIdx.x >> 6);   // slot-major, then channel
+    if (task >= V * nch) return;                                      // whole wavefront
+    const int slot = task / nch, ch = task - slot * nch;
+    const int lane = threadIdx.x & 63;
     const double orient = (double)view[slot].orient;
     const float* s = sino + ((size_t)ch * V + vp_view(view[slot])) * B;
     const float* pa = path + (size_t)slot * B;
     double2* dst = C + ((size_t)ch * V + slot) * B;
-    __shared__ double part[kScanThreads];
-    const int per = (B + kScanThreads - 1) / kScanThreads;
-    const int b0 = threadIdx.x * per;
-    double acc = 0.0;
-    for (int i = 0; i < per; ++i) {
-        const int b = b0 + i;
-        if (b < B) acc += orient * ((double)s[b] * (double)pa[b]);
-    }
-    part[threadIdx.x] = acc;
-    __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-        const double add = threadIdx.x >= off ? part[threadIdx.x - off] : 0.0;
-        __syncthreads();
-        part[threadIdx.x] += add;
-        __syncthreads();
-    }
-    double run = threadIdx.x ? part[threadIdx.x - 1] : 0.0;
-    for (int i = 0; i < per; ++i) {
-        const int b = b0 + i;
-        if (b < B) {
-            const double d = orient * ((double)s[b] * (double)pa[b]);
-            dst[b] = make_double2(run, d);
-            run += d;
+    double carry = 0.0;
+    for (int b0 = 0; b0 < B; b0 += 64) {                               // uniform trip count
+        const int b = b0 + lane;
+        const double d = b < B ? orient * ((double)s[b] * (double)pa[b]) : 0.0;
+        double inc = d;
+        for (int off = 1; off < 64; off <<= 1) {
+            const double t = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += t;
         }
+        if (b < B) dst[b] = make_double2(carry + (inc - d), d);
+        carry += __shfl(inc, 63, 64);
     }
 }
 
@@ -184,6 +178,44 @@ __device__ __forceinline__ bool decode_block(const FrameSplit& fs, int& frame, i
     frame = xcd >> 2;
     item = (id >> 3) * 4 + (xcd & 3);
     return item < (frame ? fs.n_items[1] : fs.n_items[0]);   // no dynamic index into the by-value array
+}
+
+// Lines q in [0, Nq) are active unless the first and the last boundary of a
+// wavefront (positions X = x0 + x1 q, affine in q) both lie at least a margin
+// beyond the same end of the line; the inactive lines form at most two
+// intervals, and [q_lo, q_hi] is the hull of what remains (empty: q_lo > q_hi).
+// FP64 with a margin of 1/64 pixel, far above the FP32 error of the positions
+// the line loop evaluates, so no line with a nonzero contribution is dropped.
+__device__ __forceinline__ void active_lines(float2 bf, float2 bl, int Np, int Nq, int& q_lo, int& q_hi) {
+    const double m = 1.0 / 64.0, last = (double)(Nq - 1);
+    // {q in [0, last] : a + b q <= c} as [lo, hi]
+    auto half = [&](double a, double b, double c, double& lo, double& hi) {
+        lo = 0.0;
+        hi = last;
+        if (b == 0.0) {
+            if (a > c) lo = 1.0, hi = 0.0;
+        } else if (b > 0.0) {
+            hi = fmin(last, floor((c - a) / b));
+        } else {
+            lo = fmax(0.0, ceil((c - a) / b));
+        }
+    };
+    double lo1a, hi1a, lo1b, hi1b, lo2a, hi2a, lo2b, hi2b;
+    half(bf.x, bf.y, -m, lo1a, hi1a);                              // first boundary left of the line
+    half(bl.x, bl.y, -m, lo1b, hi1b);                              // last boundary left of the line
+    half(-(double)bf.x, -(double)bf.y, -((double)Np + m), lo2a, hi2a);   // first right of it
+    half(-(double)bl.x, -(double)bl.y, -((double)Np + m), lo2b, hi2b);   // last right of it
+    const double i1lo = fmax(lo1a, lo1b), i1hi = fmin(hi1a, hi1b);
+    const double i2lo = fmax(lo2a, lo2b), i2hi = fmin(hi2a, hi2b);
+    double a = 0.0, b = last;
+    for (int r = 0; r < 2; ++r) {                                  // strip inactive runs at both ends
+        if (i1lo <= i1hi && i1lo <= a && a <= i1hi) a = i1hi + 1.0;
+        if (i2lo <= i2hi && i2lo <= a && a <= i2hi) a = i2hi + 1.0;
+        if (i1lo <= i1hi && i1lo <= b && b <= i1hi) b = i1lo - 1.0;
+        if (i2lo <= i2hi && i2lo <= b && b <= i2hi) b = i2lo - 1.0;
+    }
+    q_lo = (int)a;
+    q_hi = (int)b;
 }
 
 template <int NK>
@@ -225,14 +257,26 @@ __global__ __launch_bounds__(kThreads) void k_dd_forward(const ViewParams* __res
             acc[m] = fmaf(next_lane(F) - F, s, acc[m]);
         }
     };
-    int q = 0;
-    for (; q + 4 <= Nq; q += 4) {     // trip counts are uniform over the wavefront
+    // Only lines on which some boundary of this wavefront lies inside the image
+    // contribute: elsewhere every lane's position clamps to the same end of the
+    // line, F is equal across lanes and the differences are exactly zero.
+    int q_lo = 0, q_hi = -1;
+    {
+        const int e_first = (chunk * kWaves + wave) * kPerWave;
+        if (e_first <= B) {
+            const float2 bf = bound[(size_t)slot * (B + 1) + e_first];
+            const float2 bl = bound[(size_t)slot * (B + 1) + min(e_first + kPerWave, B)];
+            active_lines(bf, bl, Np, Nq, q_lo, q_hi);
+        }
+    }
+    int q = q_lo;
+    for (; q + 4 <= q_hi + 1; q += 4) {   // trip counts are uniform over the wavefront
         line_step(q);
         line_step(q + 1);
         line_step(q + 2);
         line_step(q + 3);
     }
-    for (; q < Nq; ++q) line_step(q);
+    for (; q <= q_hi; ++q) line_step(q);
     if (lane < kPerWave && edge < B) {
         const int v = vp_view(view[slot]);
         const float L = path[(size_t)slot * B + edge];
@@ -465,8 +509,9 @@ template <int NCH>
 const float* back_launch(const GeomTables& t, const float* sino, float* x, hipStream_t s) {
     {
         KernelTimer kt_("k_detector_prefix", s);
-        hipLaunchKernelGGL(k_detector_prefix, dim3(t.V, NCH), dim3(kScanThreads), 0, s, sino, t.path,
-                           t.view, t.V, t.B, reinterpret_cast<double2*>(t.det_prefix));
+        hipLaunchKernelGGL(k_detector_prefix, dim3((t.V * NCH + kPrefixWaves - 1) / kPrefixWaves),
+                           dim3(64 * kPrefixWaves), 0, s, sino, t.path, t.view, t.V, t.B, NCH,
+                           reinterpret_cast<double2*>(t.det_prefix));
         kt_.stop();
     }
     MBMD_LAUNCHED();
