@@ -126,6 +126,7 @@ void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int b
             }
         MBMD_REQUIRE(n_pos == 0 || n_neg == 0, MBMD_ERR_SHAPE,
                      "fan beam: the source lies between the sweep lines of a view (source too close)");
+        if (n_neg) std::reverse(bound.begin() + (size_t)slot * (B + 1), bound.begin() + (size_t)(slot + 1) * (B + 1));
         for (int b = 0; b < B; ++b) {
             const double u = (b - 0.5 * (B - 1)) * g.du + g.u_offset;
             const Ray r = boundary_ray(g, c, s, u);
@@ -193,7 +194,7 @@ void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int b
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
     const size_t b_view = al(sizeof(ViewParams) * V), b_bound = al(sizeof(float2) * bound.size()),
                  b_path = al(sizeof(float) * path.size()), b_fv = al(sizeof(int) * V),
-                 b_pre = al(sizeof(float2) * prefix_elems(g.nx, g.ny) * prefix_mat),
+                 b_pre = al(sizeof(float) * prefix_elems(g.nx, g.ny) * prefix_mat),
                  b_line = al(sizeof(float4) * line.size()),
                  b_det = al(sizeof(double) * 2 * (size_t)back_ch * V * B),
                  b_tmp = al(sizeof(float) * (size_t)back_ch * nj);
@@ -208,7 +209,7 @@ void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int b
     t.bound = reinterpret_cast<float2*>(base + b_view);
     t.path = reinterpret_cast<float*>(base + b_view + b_bound);
     t.frame_views = reinterpret_cast<int*>(base + b_view + b_bound + b_path);
-    t.prefix = prefix_mat ? reinterpret_cast<float2*>(base + b_view + b_bound + b_path + b_fv) : nullptr;
+    t.prefix = prefix_mat ? reinterpret_cast<float*>(base + b_view + b_bound + b_path + b_fv) : nullptr;
     t.back_line = reinterpret_cast<float4*>(base + b_view + b_bound + b_path + b_fv + b_pre);
     t.back_line_q = QL;
     char* after_pre = base + b_view + b_bound + b_path + b_fv + b_pre + b_line;

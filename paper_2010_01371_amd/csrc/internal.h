@@ -103,14 +103,15 @@ struct GeomTables {
     int n_frame_views[2] = {0, 0};
     ViewParams* view = nullptr;      // [slot]
     // [slot][B+1]: boundary b' crosses sweep line q (0..Nq-1) at along-line
-    // position X0 + X1 q, in pixels from the line's first pixel edge
+    // position X0 + X1 q, in pixels from the line's first pixel edge; stored in
+    // increasing X (boundary B - b' at entry b' for views with orient < 0)
     float2* bound = nullptr;
     float* path = nullptr;           // [slot][B]: path length per sweep line of the bin-centre ray
     int* frame_views = nullptr;      // [slot] -> view index
-    // scratch: line prefix sums, entries (F[k], img[k]) for k < Np and (line total, 0)
-    // at k = Np; frame 0 lines [n_mat][ny][prefix_row(nx)], then frame 1 lines
-    // [n_mat][nx][prefix_row(ny)]
-    float2* prefix = nullptr;
+    // scratch: line prefix sums F[k] = sum_{p<k} img[p] for k < Np and the line total
+    // at k = Np .. Np+3; frame 0 lines [n_mat][ny][prefix_row(nx)], then frame 1
+    // lines [n_mat][nx][prefix_row(ny)]
+    float* prefix = nullptr;
     int prefix_mat = 0;
     // [max(nx,ny)][slot][2]: per sweep line q of the slot's frame, the fractional
     // bin index shifted by an integer s_q: beta - s_q = (N + nK K) / (D + dK K), as
@@ -128,9 +129,10 @@ struct GeomTables {
     int device = -1;
 };
 
-// Row stride (entries) of the line prefix table for lines of Np pixels: Np + 1
-// entries rounded up to even, so that rows start 16-byte aligned.
-__host__ __device__ inline int prefix_row(int Np) { return (Np + 2) & ~1; }
+// Row stride (floats) of the line prefix table for lines of Np pixels: Np + 4
+// entries (a 16-byte read at any k <= Np stays in the row) rounded up to a
+// multiple of 4, so that rows start 16-byte aligned.
+__host__ __device__ inline int prefix_row(int Np) { return (Np + 4 + 3) & ~3; }
 inline size_t prefix_elems(int nx, int ny) { return (size_t)ny * prefix_row(nx) + (size_t)nx * prefix_row(ny); }
 
 // Builds the tables in FP64 on the host and uploads them (synchronous copy).

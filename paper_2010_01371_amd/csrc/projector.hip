@@ -44,6 +44,7 @@
 // part of a back projection is written in its own (transposed) layout and
 // added by a tiled transpose.
 #include <cmath>
+#include <type_traits>
 #include <cstdlib>
 
 #include "internal.h"
@@ -54,7 +55,8 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr int kPerWave = 63;                 // bins (forward) or pixels (back) per wavefront
+constexpr int kPerWave = 63;                 // pixels per wavefront (back projection)
+constexpr int kFwdBinsPerWave = 127;         // bins per wavefront (forward: two boundaries per lane)
 constexpr int kScanThreads = 256;
 constexpr int kBufferWord3 = 0x00020000;     // raw buffer resource, gfx9 family
 
@@ -87,12 +89,12 @@ __device__ __forceinline__ double2 load_d2(__amdgpu_buffer_rsrc_t r, int voff, i
 }
 
 // Exclusive prefix sums F[p] = sum_{p'<p} img[p'] (FP64 accumulation, stored
-// FP32 next to img[p]) of every sweep line of n_mat images, entry Np holding
-// (line total, 0).  One block per line: blocks [0, ny) take the rows (frame 0),
-// blocks [ny, ny+nx) the columns (frame 1); a frame without views is skipped by
-// the caller's grid.
+// FP32) of every sweep line of n_mat images, entries Np .. Np+3 holding the line
+// total.  One block per line: blocks [0, ny) take the rows (frame 0), blocks
+// [ny, ny+nx) the columns (frame 1); a frame without views is skipped by the
+// caller's grid.
 __global__ __launch_bounds__(kScanThreads) void k_line_prefix(const float* __restrict__ img,
-                                                               float2* __restrict__ rows, float2* __restrict__ cols,
+                                                               float* __restrict__ rows, float* __restrict__ cols,
                                                                int nx, int ny, int line0) {
     const int line = line0 + blockIdx.x;
     const int m = blockIdx.y;
@@ -103,7 +105,7 @@ __global__ __launch_bounds__(kScanThreads) void k_line_prefix(const float* __res
     const float* src = img + (size_t)m * nx * ny;
     const size_t elem_stride = frame ? (size_t)nx : 1;
     const size_t line_off = frame ? (size_t)q : (size_t)q * nx;
-    float2* dst = (frame ? cols : rows) + ((size_t)m * Nq + q) * prefix_row(Np);
+    float* dst = (frame ? cols : rows) + ((size_t)m * Nq + q) * prefix_row(Np);
 
     __shared__ double part[kScanThreads];
     const int per = (Np + kScanThreads - 1) / kScanThreads;
@@ -125,12 +127,11 @@ __global__ __launch_bounds__(kScanThreads) void k_line_prefix(const float* __res
     for (int i = 0; i < per; ++i) {
         const int p = p0 + i;
         if (p < Np) {
-            const float val = src[line_off + (size_t)p * elem_stride];
-            dst[p] = make_float2((float)run, val);
-            run += (double)val;
+            dst[p] = (float)run;
+            run += (double)src[line_off + (size_t)p * elem_stride];
         }
     }
-    if (threadIdx.x == kScanThreads - 1) dst[Np] = make_float2((float)part[kScanThreads - 1], 0.0f);
+    if (threadIdx.x < 4) dst[Np + threadIdx.x] = (float)part[kScanThreads - 1];
 }
 
 // Per slot and channel, for b = 0..B-1: the pair (C[b], C[b+1] - C[b]) with
@@ -222,8 +223,8 @@ template <int NK>
 __global__ __launch_bounds__(kThreads) void k_dd_forward(const ViewParams* __restrict__ view,
                                                          const float2* __restrict__ bound,
                                                          const float* __restrict__ path,
-                                                         const float2* __restrict__ pre_rows,
-                                                         const float2* __restrict__ pre_cols, int nv0,
+                                                         const float* __restrict__ pre_rows,
+                                                         const float* __restrict__ pre_cols, int nv0,
                                                          FrameSplit fs, int chunks, int nx, int ny, int V, int B,
                                                          float* __restrict__ sino) {
     int frame, item;
@@ -232,56 +233,100 @@ __global__ __launch_bounds__(kThreads) void k_dd_forward(const ViewParams* __res
     const int chunk = item % chunks;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int edge = (chunk * kWaves + wave) * kPerWave + lane;   // boundary index; valid ones are 0..B
+    const int e0 = (chunk * kWaves + wave) * kFwdBinsPerWave;     // first boundary of the wavefront
+    if (e0 >= B) return;                                          // whole wavefront: no bins
     const int Nq = frame ? nx : ny;
     const int Np = frame ? ny : nx;
     const int Lp = prefix_row(Np);
-    const __amdgpu_buffer_rsrc_t pre = rsrc(frame ? pre_cols : pre_rows, sizeof(float2) * (size_t)NK * Nq * Lp);
-    const float2 bd = bound[(size_t)slot * (B + 1) + min(edge, B)];
+    const __amdgpu_buffer_rsrc_t pre = rsrc(frame ? pre_cols : pre_rows, sizeof(float) * (size_t)NK * Nq * Lp);
+    // boundaries ea (bin ea = [ea, eb] in this lane) and eb (bin eb = [eb, next lane's ea])
+    const int ea = min(e0 + 2 * lane, B), eb = min(e0 + 2 * lane + 1, B);
+    const float2* brow = bound + (size_t)slot * (B + 1);
+    const float2 ba = brow[ea], bb = brow[eb];
     const float Npf = (float)Np;
-    float acc[NK];
+    float acc_a[NK], acc_b[NK];
 #pragma unroll
-    for (int m = 0; m < NK; ++m) acc[m] = 0.0f;
-    // one sweep line: F at this lane's boundary, the neighbour's from lane + 1
-    auto line_step = [&](int q) {
-        const float X = fmaf(bd.y, (float)q, bd.x);
-        const float Xc = __builtin_amdgcn_fmed3f(X, 0.0f, Npf);
-        const int k = (int)Xc;                                   // >= 0, so truncation is floor
-        const float f = __builtin_amdgcn_fractf(Xc);
-        const float s = fast_rcp(next_lane(X) - X);
-        const int voff = k * (int)sizeof(float2);
-#pragma unroll
-        for (int m = 0; m < NK; ++m) {
-            const float2 e = load_f2(pre, voff, (m * Nq + q) * Lp * (int)sizeof(float2));   // F[k], img[k]
-            const float F = fmaf(f, e.y, e.x);
-            acc[m] = fmaf(next_lane(F) - F, s, acc[m]);
-        }
-    };
+    for (int m = 0; m < NK; ++m) acc_a[m] = acc_b[m] = 0.0f;
     // Only lines on which some boundary of this wavefront lies inside the image
     // contribute: elsewhere every lane's position clamps to the same end of the
     // line, F is equal across lanes and the differences are exactly zero.
     int q_lo = 0, q_hi = -1;
-    {
-        const int e_first = (chunk * kWaves + wave) * kPerWave;
-        if (e_first <= B) {
-            const float2 bf = bound[(size_t)slot * (B + 1) + e_first];
-            const float2 bl = bound[(size_t)slot * (B + 1) + min(e_first + kPerWave, B)];
-            active_lines(bf, bl, Np, Nq, q_lo, q_hi);
-        }
+    active_lines(brow[e0], brow[min(e0 + kFwdBinsPerWave, B)], Np, Nq, q_lo, q_hi);
+    // The in-lane bin width is affine in q, so its largest value over the active
+    // lines is at an end: at most two pixels everywhere means X_b lies in the
+    // four-entry window that starts at floor(X_a).
+    float wmax = 0.0f;
+    if (q_lo <= q_hi) {
+        const float w0 = fabsf(fmaf(bb.y - ba.y, (float)q_lo, bb.x - ba.x));
+        const float w1 = fabsf(fmaf(bb.y - ba.y, (float)q_hi, bb.x - ba.x));
+        wmax = fmaxf(w0, w1);
+        for (int off = 32; off > 0; off >>= 1) wmax = fmaxf(wmax, __shfl_xor(wmax, off, 64));
     }
-    int q = q_lo;
-    for (; q + 4 <= q_hi + 1; q += 4) {   // trip counts are uniform over the wavefront
-        line_step(q);
-        line_step(q + 1);
-        line_step(q + 2);
-        line_step(q + 3);
-    }
-    for (; q <= q_hi; ++q) line_step(q);
-    if (lane < kPerWave && edge < B) {
-        const int v = vp_view(view[slot]);
-        const float L = path[(size_t)slot * B + edge];
+    const bool narrow = wmax < 1.99f;                             // uniform over the wavefront
+    // one sweep line; NARROW: both boundaries' F from one 16-byte read of F[k..k+3],
+    // else one 8-byte read of F[k], F[k+1] per boundary
+    auto line_step = [&](int q, auto narrow_tag) {
+        constexpr bool NARROW = decltype(narrow_tag)::value;
+        const float qf = (float)q;
+        const float Xa = fmaf(ba.y, qf, ba.x), Xb = fmaf(bb.y, qf, bb.x);
+        const float Xca = __builtin_amdgcn_fmed3f(Xa, 0.0f, Npf), Xcb = __builtin_amdgcn_fmed3f(Xb, 0.0f, Npf);
+        const float sa = fast_rcp(Xb - Xa);                        // in-lane bin width
+        const float sb = fast_rcp(next_lane(Xa) - Xb);             // bin across to the next lane
+        const float kf = floorf(Xca);
+        const int k = (int)kf;
+        const float da = Xca - kf;
 #pragma unroll
-        for (int m = 0; m < NK; ++m) sino[((size_t)m * V + v) * B + edge] = acc[m] * L;
+        for (int m = 0; m < NK; ++m) {
+            const int row = (m * Nq + q) * Lp * (int)sizeof(float);
+            float Fa, Fb;
+            if constexpr (NARROW) {
+                const float db = Xcb - kf;                         // in [0, 3)
+                const int j = (int)db;
+                const float fb = __builtin_amdgcn_fractf(db);
+                const float4 e = load_f4(pre, k * (int)sizeof(float), row);
+                Fa = fmaf(da, e.y - e.x, e.x);
+                const float f0 = j == 0 ? e.x : (j == 1 ? e.y : e.z);
+                const float f1 = j == 0 ? e.y : (j == 1 ? e.z : e.w);
+                Fb = fmaf(fb, f1 - f0, f0);
+            } else {
+                const float2 ea2 = load_f2(pre, k * (int)sizeof(float), row);
+                const float2 eb2 = load_f2(pre, (int)Xcb * (int)sizeof(float), row);
+                Fa = fmaf(da, ea2.y - ea2.x, ea2.x);
+                Fb = fmaf(__builtin_amdgcn_fractf(Xcb), eb2.y - eb2.x, eb2.x);
+            }
+            acc_a[m] = fmaf(Fb - Fa, sa, acc_a[m]);
+            acc_b[m] = fmaf(next_lane(Fa) - Fb, sb, acc_b[m]);
+        }
+    };
+    auto sweep = [&](auto narrow_tag) {
+        int q = q_lo;
+        for (; q + 4 <= q_hi + 1; q += 4) {   // trip counts are uniform over the wavefront
+            line_step(q, narrow_tag);
+            line_step(q + 1, narrow_tag);
+            line_step(q + 2, narrow_tag);
+            line_step(q + 3, narrow_tag);
+        }
+        for (; q <= q_hi; ++q) line_step(q, narrow_tag);
+    };
+    if (narrow)
+        sweep(std::true_type{});
+    else
+        sweep(std::false_type{});
+    // bins in table order; views stored reversed map bin i to B - 1 - i
+    const bool rev = view[slot].orient < 0.0f;
+    const int v = vp_view(view[slot]);
+    const int bin_a = ea, bin_b = eb;
+    if (bin_a < B && bin_a < e0 + kFwdBinsPerWave) {
+        const int o = rev ? B - 1 - bin_a : bin_a;
+        const float L = path[(size_t)slot * B + o];
+#pragma unroll
+        for (int m = 0; m < NK; ++m) sino[((size_t)m * V + v) * B + o] = acc_a[m] * L;
+    }
+    if (lane < 63 && bin_b < B && bin_b < e0 + kFwdBinsPerWave) {
+        const int o = rev ? B - 1 - bin_b : bin_b;
+        const float L = path[(size_t)slot * B + o];
+#pragma unroll
+        for (int m = 0; m < NK; ++m) sino[((size_t)m * V + v) * B + o] = acc_b[m] * L;
     }
 }
 
@@ -428,10 +473,10 @@ int grid_blocks(const FrameSplit& fs) {
 
 template <int NK>
 void fwd_launch(const GeomTables& t, float* sino, hipStream_t s) {
-    const int chunks = (t.B + 1 + kWaves * kPerWave - 1) / (kWaves * kPerWave);
+    const int chunks = (t.B + kWaves * kFwdBinsPerWave - 1) / (kWaves * kFwdBinsPerWave);
     const FrameSplit fs = split(t.n_frame_views[0] * chunks, t.n_frame_views[1] * chunks);
-    const float2* rows = t.prefix;
-    const float2* cols = t.prefix + (size_t)t.prefix_mat * t.ny * prefix_row(t.nx);
+    const float* rows = t.prefix;
+    const float* cols = t.prefix + (size_t)t.prefix_mat * t.ny * prefix_row(t.nx);
     {
         KernelTimer kt_("k_dd_forward", s);
         hipLaunchKernelGGL(k_dd_forward<NK>, dim3(grid_blocks(fs)), dim3(kThreads), 0, s, t.view, t.bound,
@@ -626,7 +671,7 @@ void launch_project(const GeomTables& t, const float* x, float* sino, int n_mat,
         // lines [line0, line1): rows then columns, only the frames that have views
         const int line0 = t.n_frame_views[0] ? 0 : t.ny;
         const int line1 = t.n_frame_views[1] ? t.ny + t.nx : t.ny;
-        float2* cols = t.prefix + (size_t)t.prefix_mat * t.ny * prefix_row(t.nx);
+        float* cols = t.prefix + (size_t)t.prefix_mat * t.ny * prefix_row(t.nx);
         KernelTimer kt_("k_line_prefix", s);
         hipLaunchKernelGGL(k_line_prefix, dim3(line1 - line0, n_mat), dim3(kScanThreads), 0, s, x, t.prefix, cols,
                            t.nx, t.ny, line0);
