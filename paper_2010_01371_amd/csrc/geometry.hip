@@ -166,21 +166,22 @@ void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int b
         // beta(K_b) = b; the map is projective, so
         //   (K - K_b) / (K_{b+1} - K_b) = (num - b den) (nK - (b+1) dK) / Delta,
         // Delta = D nK - N dK (nonzero: boundaries are distinct and not parallel to
-        // the line).  The bin origin is shifted by s_q = beta(0) rounded, which
-        // keeps the FP32 operands of the residual small.
+        // the line).  Numerator and denominator are divided by D, so that the
+        // denominator is 1 + c K, and the bin origin moves to the detector centre,
+        // which bounds the in-range FP32 map values by half the detector and makes
+        // the clamp of the bin index symmetric.
         const int Nq = frame == 0 ? g.ny : g.nx;
+        const double sh = (double)back_shift(B);
         for (int q = 0; q < Nq; ++q) {
             const double qq = q - 0.5 * (Nq - 1);
             const double N = n0 + nq * qq, D = d0 + dqq * qq;
             const double delta = D * nK - N * dK;
             MBMD_REQUIRE(std::fabs(delta) > 0.0 && D > 0.0, MBMD_ERR_SHAPE,
                          "degenerate bin map on a sweep line (source too close)");
-            double sq = std::nearbyint(N / D);
-            sq = sq < 0.0 ? 0.0 : (sq > B - 1 ? B - 1 : sq);
             float4* L = &line[((size_t)q * V + slot) * 2];
-            L[0] = make_float4((float)(N - sq * D), (float)(nK - sq * dK), (float)D, (float)dK);
-            L[1] = make_float4((float)((nK - (sq + 1.0) * dK) / delta), (float)(dK / delta), (float)(-sq),
-                               (float)(B - 1 - sq));
+            L[0] = make_float4((float)((N - sh * D) / D), (float)((nK - sh * dK) / D), (float)(dK / D),
+                               (float)(D * (nK - (sh + 1.0) * dK) / delta));
+            L[1] = make_float4((float)(D * dK / delta), 0.0f, 0.0f, 0.0f);
         }
         p.orient = n_neg == 0 ? 1.0f : -1.0f;
         p.view_frame = v | (frame << 16);
@@ -196,7 +197,7 @@ void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int b
                  b_path = al(sizeof(float) * path.size()), b_fv = al(sizeof(int) * V),
                  b_pre = al(sizeof(float) * prefix_elems(g.nx, g.ny) * prefix_mat),
                  b_line = al(sizeof(float4) * line.size()),
-                 b_det = al(sizeof(double) * 2 * (size_t)back_ch * V * B),
+                 b_det = al(sizeof(DetEntry) * (size_t)back_ch * V * det_row(B)),
                  b_tmp = al(sizeof(float) * (size_t)back_ch * nj);
     t.back_ch = back_ch;
     char* base = nullptr;
@@ -213,7 +214,7 @@ void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int b
     t.back_line = reinterpret_cast<float4*>(base + b_view + b_bound + b_path + b_fv + b_pre);
     t.back_line_q = QL;
     char* after_pre = base + b_view + b_bound + b_path + b_fv + b_pre + b_line;
-    t.det_prefix = back_ch ? reinterpret_cast<double*>(after_pre) : nullptr;
+    t.det_prefix = back_ch ? reinterpret_cast<DetEntry*>(after_pre) : nullptr;
     t.back_part = back_ch ? reinterpret_cast<float*>(after_pre + b_det) : nullptr;
     MBMD_HIP(hipMemcpy(t.view, vp.data(), sizeof(ViewParams) * V, hipMemcpyHostToDevice));
     MBMD_HIP(hipMemcpy(t.bound, bound.data(), sizeof(float2) * bound.size(), hipMemcpyHostToDevice));

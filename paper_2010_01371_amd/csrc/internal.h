@@ -96,6 +96,14 @@ struct ViewParams {
 __host__ __device__ inline int vp_view(const ViewParams& p) { return p.view_frame & 0xffff; }
 __host__ __device__ inline int vp_frame(const ViewParams& p) { return p.view_frame >> 16; }
 
+// One detector cell of the back projector's cumulative integral: C[b] in FP64
+// and the width C[b+1] - C[b] of the bin in FP32 (16 bytes, one vector load).
+struct alignas(16) DetEntry {
+    double c;
+    float d;
+    float pad;
+};
+
 // Per-view tables are in slot order (views of frame 0, then of frame 1).
 struct GeomTables {
     mbmd_geometry g{};
@@ -114,12 +122,13 @@ struct GeomTables {
     float* prefix = nullptr;
     int prefix_mat = 0;
     // [max(nx,ny)][slot][2]: per sweep line q of the slot's frame, the fractional
-    // bin index shifted by an integer s_q: beta - s_q = (N + nK K) / (D + dK K), as
-    // {N, nK, D, dK} and {a, c, -s_q, B-1-s_q}, where (a - c (beta' floor)) scales
-    // (N + nK K) - floor(beta') (D + dK K) to the fraction of the bin
+    // bin index counted from the detector centre, beta - back_shift(B) =
+    // (n + m K) / (1 + c K), as {n, m, c, a} and {g, 0, 0, 0}: with
+    // f = floor(beta - back_shift(B)), (a - g f) scales (n + m K) - f (1 + c K)
+    // to the fraction (K - K_b) / (K_b+1 - K_b) of bin b
     float4* back_line = nullptr;
     int back_line_q = 0;             // max(nx, ny)
-    double* det_prefix = nullptr;    // scratch: [back_ch][V][B] pairs (C[b], C[b+1]-C[b]) (FP64)
+    DetEntry* det_prefix = nullptr;  // scratch: [back_ch][V][det_row(B)] detector entries
     // scratch: [back_ch][nx][ny] column-sweep part of a back projection
     float* back_part = nullptr;
     // tile shape picked for the back projector per channel count (-1: not yet tuned)
@@ -133,6 +142,12 @@ struct GeomTables {
 // entries (a 16-byte read at any k <= Np stays in the row) rounded up to a
 // multiple of 4, so that rows start 16-byte aligned.
 __host__ __device__ inline int prefix_row(int Np) { return (Np + 4 + 3) & ~3; }
+// Detector rows of the back projector: entries 0 .. B-1 are the bins, B and
+// B+1 repeat the total with zero width, so that the bin index clamped to the
+// symmetric range [-back_shift(B), back_shift(B)] around the detector centre
+// (shifted by back_shift(B)) always lands inside the row.
+__host__ __device__ inline int det_row(int B) { return B + 2; }
+__host__ __device__ inline int back_shift(int B) { return (B + 1) / 2; }
 inline size_t prefix_elems(int nx, int ny) { return (size_t)ny * prefix_row(nx) + (size_t)nx * prefix_row(ny); }
 
 // Builds the tables in FP64 on the host and uploads them (synchronous copy).

@@ -84,9 +84,19 @@ __device__ __forceinline__ float2 load_f2(__amdgpu_buffer_rsrc_t r, int voff, in
 __device__ __forceinline__ float4 load_f4(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
     return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
-__device__ __forceinline__ double2 load_d2(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+// One detector entry as loaded: C[b], the width, and the pad word, which is
+// kept live until the entry is consumed (see keep()), since otherwise the
+// compiler reuses its register as a temporary and must wait for the load.
+struct DetValue {
+    double c;
+    float d;
+    float pad;
+};
+__device__ __forceinline__ DetValue load_det(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(DetValue, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
+// Marks a register as read here (an empty instruction string: no code).
+__device__ __forceinline__ void keep(float v) { asm volatile("" ::"v"(v)); }
 
 // Exclusive prefix sums F[p] = sum_{p'<p} img[p'] (FP64 accumulation, stored
 // FP32) of every sweep line of n_mat images, entries Np .. Np+3 holding the line
@@ -134,36 +144,52 @@ __global__ __launch_bounds__(kScanThreads) void k_line_prefix(const float* __res
     if (threadIdx.x < 4) dst[Np + threadIdx.x] = (float)part[kScanThreads - 1];
 }
 
-// Per slot and channel, for b = 0..B-1: the pair (C[b], C[b+1] - C[b]) with
-// C[b] = orient * sum_{b'<b} sino[b'] path[b'] (FP64); the view's orientation
-// sign makes H(K+1) - H(K) the pixel value.  One wavefront per (slot,
-// channel) walks the bins 64 at a time (coalesced loads and stores): an FP64
-// shuffle scan within the chunk plus the running total of the chunks before;
-// no barriers.
-constexpr int kPrefixWaves = 4;
-__global__ __launch_bounds__(64 * kPrefixWaves) void k_detector_prefix(const float* __restrict__ sino,
-                                                                        const float* __restrict__ path,
-                                                                        const ViewParams* __restrict__ view, int V,
-                                                                        int B, int nch, double2* __restrict__ C) {
-    const int task = blockIdx.x * kPrefixWaves + (threadIdx.x >> 6);   // slot-major, then channel
-    if (task >= V * nch) return;                                      // whole wavefront
-    const int slot = task / nch, ch = task - slot * nch;
-    const int lane = threadIdx.x & 63;
-    const double orient = (double)view[slot].orient;
+// Per slot and channel, the row of detector entries (C[b], C[b+1] - C[b]) with
+// C[b] = orient * sum_{b'<b} sino[b'] path[b'] (FP64 sums of the FP32 widths,
+// so that C[b] + width reaches C[b+1] up to FP64 rounding), and the total with
+// zero width at entries B and B+1; the view's orientation sign makes
+// H(K+1) - H(K) the pixel value.  One workgroup per (slot, channel); each lane
+// takes a contiguous run of bins, an FP64 shuffle scan combines the lanes of a
+// wavefront and one barrier the wavefronts.
+constexpr int kPrefixThreads = 256;
+__global__ __launch_bounds__(kPrefixThreads) void k_detector_prefix(const float* __restrict__ sino,
+                                                                     const float* __restrict__ path,
+                                                                     const ViewParams* __restrict__ view, int V,
+                                                                     int B, DetEntry* __restrict__ C) {
+    const int slot = blockIdx.x, ch = blockIdx.y;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const float orient = view[slot].orient;
     const float* s = sino + ((size_t)ch * V + vp_view(view[slot])) * B;
     const float* pa = path + (size_t)slot * B;
-    double2* dst = C + ((size_t)ch * V + slot) * B;
-    double carry = 0.0;
-    for (int b0 = 0; b0 < B; b0 += 64) {                               // uniform trip count
-        const int b = b0 + lane;
-        const double d = b < B ? orient * ((double)s[b] * (double)pa[b]) : 0.0;
-        double inc = d;
-        for (int off = 1; off < 64; off <<= 1) {
-            const double t = __shfl_up(inc, off, 64);
-            if (lane >= off) inc += t;
+    DetEntry* dst = C + ((size_t)ch * V + slot) * det_row(B);
+    __shared__ double wave_total[kPrefixThreads / 64];
+    const int per = (B + kPrefixThreads - 1) / kPrefixThreads;
+    const int b0 = threadIdx.x * per;
+    double acc = 0.0;
+    for (int i = 0; i < per; ++i) {
+        const int b = b0 + i;
+        if (b < B) acc += (double)(orient * (float)((double)s[b] * (double)pa[b]));
+    }
+    double inc = acc;                                             // inclusive scan over the wavefront
+    for (int off = 1; off < 64; off <<= 1) {
+        const double t = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += t;
+    }
+    if (lane == 63) wave_total[wave] = inc;
+    __syncthreads();
+    double run = inc - acc;
+    for (int w = 0; w < wave; ++w) run += wave_total[w];          // fixed order
+    for (int i = 0; i < per; ++i) {
+        const int b = b0 + i;
+        if (b < B) {
+            const float d = orient * (float)((double)s[b] * (double)pa[b]);
+            dst[b] = DetEntry{run, d, 0.0f};
+            run += (double)d;
         }
-        if (b < B) dst[b] = make_double2(carry + (inc - d), d);
-        carry += __shfl(inc, 63, 64);
+    }
+    if (threadIdx.x == kPrefixThreads - 1) {                      // holds the total after its run
+        dst[B] = DetEntry{run, 0.0f, 0.0f};
+        dst[B + 1] = DetEntry{run, 0.0f, 0.0f};
     }
 }
 
@@ -340,7 +366,7 @@ __global__ __launch_bounds__(kThreads) void k_dd_forward(const ViewParams* __res
 template <int NCH, int LPW, int U>
 __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__ line_tab, int nv0, int nv1,
                                                       FrameSplit fs, int nx, int ny, int V, int B,
-                                                      const double2* __restrict__ C, float* __restrict__ x,
+                                                      const DetEntry* __restrict__ C, float* __restrict__ x,
                                                       float* __restrict__ part) {
     int frame, item;
     if (!decode_block(fs, frame, item)) return;
@@ -356,29 +382,46 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
     const float K = (float)min(pe, Np) - 0.5f * (float)Np;
     const int nv = frame ? nv1 : nv0;
     const int slot0 = frame ? nv0 : 0;
-    const float4* lt[LPW];
+    // first table entry of each line, kept in scalar registers
+    int lt0[LPW];
 #pragma unroll
-    for (int j = 0; j < LPW; ++j) lt[j] = line_tab + (size_t)min(q0 + j, Nq - 1) * V * 2;
-    const __amdgpu_buffer_rsrc_t tc = rsrc(C, sizeof(double2) * (size_t)NCH * V * B);
-    const int crow = B * (int)sizeof(double2);
-    double acc[LPW][NCH];                           // sum over views of H(K)
+    for (int j = 0; j < LPW; ++j) lt0[j] = __builtin_amdgcn_readfirstlane(min(q0 + j, Nq - 1) * V * 2);
+    const int row = det_row(B) * (int)sizeof(DetEntry);
+    const __amdgpu_buffer_rsrc_t tc = rsrc(C, (size_t)row * NCH * V);
+    const int shift = back_shift(B);
+    const float span = (float)shift;               // bin index clamp, symmetric about the centre
+    const int origin = shift * (int)sizeof(DetEntry);
+    double acc[LPW][NCH];                           // sum over views of C[b]
+    float accw[LPW][NCH];                           // sum over views of fraction x width
 #pragma unroll
     for (int j = 0; j < LPW; ++j)
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) acc[j][c] = 0.0;
+        for (int c = 0; c < NCH; ++c) {
+            acc[j][c] = 0.0;
+            accw[j][c] = 0.0f;
+        }
+    // one (line, view): byte offset of the edge's detector entry and its fraction
+    auto locate = [&](const float4& m, float g, int& off, float& fr) {
+        const float den = fmaf(m.z, K, 1.0f);
+        const float num = fmaf(m.y, K, m.x);
+        const float bf = __builtin_amdgcn_fmed3f(floorf(num * fast_rcp(den)), -span, span);
+        off = (int)bf * (int)sizeof(DetEntry) + origin;          // entry in [0, B + 1]
+        fr = __builtin_amdgcn_fmed3f(fmaf(-bf, den, num) * fmaf(-g, bf, m.w), 0.0f, 1.0f);
+    };
     // Software pipeline over groups of U views: the per-line tables of the next
     // group are requested (scalar loads) only after this group's values are in
     // registers -- scalar loads complete out of order, so a wait for one waits
     // for all -- and land while this group's detector gathers are in flight.
-    float4 tm[U][LPW], tf[U][LPW];
+    float4 tm[U][LPW];
+    float tg[U][LPW];
     auto fetch = [&](int is) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int slot = slot0 + min(is + u, nv - 1);
 #pragma unroll
             for (int j = 0; j < LPW; ++j) {
-                tm[u][j] = lt[j][2 * slot];         // {N, nK, D, dK}, shifted by s_q
-                tf[u][j] = lt[j][2 * slot + 1];     // {a, c, -s_q, B-1-s_q}
+                tm[u][j] = line_tab[lt0[j] + 2 * slot];                                          // {n, m, c, a}
+                tg[u][j] = reinterpret_cast<const float*>(line_tab)[4 * (lt0[j] + 2 * slot + 1)];   // g
             }
         }
     };
@@ -391,21 +434,14 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int j = 0; j < LPW; ++j) {
-                const float4 m = tm[u][j], f = tf[u][j];
-                const float num = fmaf(m.y, K, m.x);
-                const float den = fmaf(m.w, K, m.z);
-                const float bf = __builtin_amdgcn_fmed3f(floorf(num * fast_rcp(den)), f.z, f.w);
-                off[u][j] = (int)(bf - f.z) * (int)sizeof(double2);   // bin in [0, B-1]
-                frs[u][j] = __builtin_amdgcn_fmed3f(fmaf(-bf, den, num) * fmaf(-f.y, bf, f.x), 0.0f, 1.0f);
-            }
-        double2 h[U][LPW][NCH];
+            for (int j = 0; j < LPW; ++j) locate(tm[u][j], tg[u][j], off[u][j], frs[u][j]);
+        DetValue h[U][LPW][NCH];
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int j = 0; j < LPW; ++j)
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) h[u][j][c] = load_d2(tc, off[u][j], (c * V + slot0 + is + u) * crow);
+                for (int c = 0; c < NCH; ++c) h[u][j][c] = load_det(tc, off[u][j], (c * V + slot0 + is + u) * row);
         __builtin_amdgcn_sched_barrier(0);
         fetch(is + U);
         __builtin_amdgcn_sched_barrier(0);
@@ -414,7 +450,11 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
 #pragma unroll
             for (int j = 0; j < LPW; ++j)
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) acc[j][c] += fma(h[u][j][c].y, (double)frs[u][j], h[u][j][c].x);
+                for (int c = 0; c < NCH; ++c) {
+                    acc[j][c] += h[u][j][c].c;
+                    accw[j][c] = fmaf(frs[u][j], h[u][j][c].d, accw[j][c]);
+                    keep(h[u][j][c].pad);
+                }
     }
     // the remaining views (fewer than U); their tables were fetched into slots 0..
 #pragma unroll
@@ -422,16 +462,14 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
         if (nfull + u >= nv) break;        // uniform
 #pragma unroll
         for (int j = 0; j < LPW; ++j) {
-            const float4 m = tm[u][j], f = tf[u][j];
-            const float num = fmaf(m.y, K, m.x);
-            const float den = fmaf(m.w, K, m.z);
-            const float bf = __builtin_amdgcn_fmed3f(floorf(num * fast_rcp(den)), f.z, f.w);
-            const int o = (int)(bf - f.z) * (int)sizeof(double2);
-            const float fr = __builtin_amdgcn_fmed3f(fmaf(-bf, den, num) * fmaf(-f.y, bf, f.x), 0.0f, 1.0f);
+            int o;
+            float fr;
+            locate(tm[u][j], tg[u][j], o, fr);
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
-                const double2 h = load_d2(tc, o, (c * V + slot0 + nfull + u) * crow);   // C[b], C[b+1] - C[b]
-                acc[j][c] += fma(h.y, (double)fr, h.x);
+                const DetValue h = load_det(tc, o, (c * V + slot0 + nfull + u) * row);
+                acc[j][c] += h.c;
+                accw[j][c] = fmaf(fr, h.d, accw[j][c]);
             }
         }
     }
@@ -441,7 +479,8 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
     for (int j = 0; j < LPW; ++j) {
         float val[NCH];
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) val[c] = (float)(next_lane(acc[j][c]) - acc[j][c]);
+        for (int c = 0; c < NCH; ++c)
+            val[c] = (float)((next_lane(acc[j][c]) - acc[j][c]) + (double)(next_lane(accw[j][c]) - accw[j][c]));
         if (lane < kPerWave && pe < Np && q0 + j < Nq) {
             // image layout: rows sweep (iy = q, ix = pe), columns sweep (iy = pe, ix = q)
             const size_t pix = frame ? (size_t)pe * nx + (q0 + j) : (size_t)(q0 + j) * nx + pe;
@@ -544,7 +583,7 @@ void back_kernel_launch(const GeomTables& t, float* x, hipStream_t s) {
     const FrameSplit fs = split(u0, u1);
     KernelTimer kt_("k_dd_back", s);
     hipLaunchKernelGGL((k_dd_back<NCH, LPW, U>), dim3(grid_blocks(fs)), dim3(kThreads), 0, s, t.back_line, nv0, nv1, fs,
-                       t.nx, t.ny, t.V, t.B, reinterpret_cast<const double2*>(t.det_prefix), x, t.back_part);
+                       t.nx, t.ny, t.V, t.B, t.det_prefix, x, t.back_part);
     kt_.stop();
 }
 
@@ -554,9 +593,8 @@ template <int NCH>
 const float* back_launch(const GeomTables& t, const float* sino, float* x, hipStream_t s) {
     {
         KernelTimer kt_("k_detector_prefix", s);
-        hipLaunchKernelGGL(k_detector_prefix, dim3((t.V * NCH + kPrefixWaves - 1) / kPrefixWaves),
-                           dim3(64 * kPrefixWaves), 0, s, sino, t.path, t.view, t.V, t.B, NCH,
-                           reinterpret_cast<double2*>(t.det_prefix));
+        hipLaunchKernelGGL(k_detector_prefix, dim3(t.V, NCH), dim3(kPrefixThreads), 0, s, sino, t.path, t.view,
+                           t.V, t.B, t.det_prefix);
         kt_.stop();
     }
     MBMD_LAUNCHED();
