@@ -289,12 +289,11 @@ __global__ __launch_bounds__(kThreads) void k_dd_forward(const ViewParams* __res
         for (int off = 32; off > 0; off >>= 1) wmax = fmaxf(wmax, __shfl_xor(wmax, off, 64));
     }
     const bool narrow = wmax < 1.99f;                             // uniform over the wavefront
-    // one sweep line; NARROW: both boundaries' F from one 16-byte read of F[k..k+3],
-    // else one 8-byte read of F[k], F[k+1] per boundary
-    auto line_step = [&](int q, auto narrow_tag) {
+    // one sweep line at boundary positions Xa, Xb; NARROW: both boundaries' F
+    // from one 16-byte read of F[k..k+3], else one 8-byte read of F[k], F[k+1]
+    // per boundary
+    auto line_step = [&](int q, float Xa, float Xb, auto narrow_tag) {
         constexpr bool NARROW = decltype(narrow_tag)::value;
-        const float qf = (float)q;
-        const float Xa = fmaf(ba.y, qf, ba.x), Xb = fmaf(bb.y, qf, bb.x);
         const float Xca = __builtin_amdgcn_fmed3f(Xa, 0.0f, Npf), Xcb = __builtin_amdgcn_fmed3f(Xb, 0.0f, Npf);
         const float sa = fast_rcp(Xb - Xa);                        // in-lane bin width
         const float sb = fast_rcp(next_lane(Xa) - Xb);             // bin across to the next lane
@@ -306,14 +305,16 @@ __global__ __launch_bounds__(kThreads) void k_dd_forward(const ViewParams* __res
             const int row = (m * Nq + q) * Lp * (int)sizeof(float);
             float Fa, Fb;
             if constexpr (NARROW) {
-                const float db = Xcb - kf;                         // in [0, 3)
-                const int j = (int)db;
-                const float fb = __builtin_amdgcn_fractf(db);
+                // F is piecewise linear on [k, k+3]: its value at k + db is
+                // F[k] plus the clamped parts of db in each pixel times the pixel
+                const float db = Xcb - kf;                         // in [da, 3)
                 const float4 e = load_f4(pre, k * (int)sizeof(float), row);
-                Fa = fmaf(da, e.y - e.x, e.x);
-                const float f0 = j == 0 ? e.x : (j == 1 ? e.y : e.z);
-                const float f1 = j == 0 ? e.y : (j == 1 ? e.z : e.w);
-                Fb = fmaf(fb, f1 - f0, f0);
+                const float d0 = e.y - e.x;
+                Fa = fmaf(da, d0, e.x);
+                const float c0 = fminf(db, 1.0f);
+                const float c1 = __builtin_amdgcn_fmed3f(db - 1.0f, 0.0f, 1.0f);
+                const float c2 = __builtin_amdgcn_fmed3f(db - 2.0f, 0.0f, 1.0f);   // db < 3
+                Fb = fmaf(c2, e.w - e.z, fmaf(c1, e.z - e.y, fmaf(c0, d0, e.x)));
             } else {
                 const float2 ea2 = load_f2(pre, k * (int)sizeof(float), row);
                 const float2 eb2 = load_f2(pre, (int)Xcb * (int)sizeof(float), row);
@@ -324,15 +325,23 @@ __global__ __launch_bounds__(kThreads) void k_dd_forward(const ViewParams* __res
             acc_b[m] = fmaf(next_lane(Fa) - Fb, sb, acc_b[m]);
         }
     };
+    // Positions are affine in q: one FMA from the line index per group of four
+    // lines, then steps of the slope with inline-constant multipliers.
     auto sweep = [&](auto narrow_tag) {
         int q = q_lo;
         for (; q + 4 <= q_hi + 1; q += 4) {   // trip counts are uniform over the wavefront
-            line_step(q, narrow_tag);
-            line_step(q + 1, narrow_tag);
-            line_step(q + 2, narrow_tag);
-            line_step(q + 3, narrow_tag);
+            const float qf = (float)q;
+            const float Xa0 = fmaf(ba.y, qf, ba.x), Xb0 = fmaf(bb.y, qf, bb.x);
+            const float Xa1 = Xa0 + ba.y, Xb1 = Xb0 + bb.y;
+            line_step(q, Xa0, Xb0, narrow_tag);
+            line_step(q + 1, Xa1, Xb1, narrow_tag);
+            line_step(q + 2, fmaf(ba.y, 2.0f, Xa0), fmaf(bb.y, 2.0f, Xb0), narrow_tag);
+            line_step(q + 3, fmaf(ba.y, 2.0f, Xa1), fmaf(bb.y, 2.0f, Xb1), narrow_tag);
         }
-        for (; q <= q_hi; ++q) line_step(q, narrow_tag);
+        for (; q <= q_hi; ++q) {
+            const float qf = (float)q;
+            line_step(q, fmaf(ba.y, qf, ba.x), fmaf(bb.y, qf, bb.x), narrow_tag);
+        }
     };
     if (narrow)
         sweep(std::true_type{});
