@@ -15,6 +15,7 @@
 // reduced per block in a fixed order.
 #include <cmath>
 
+#include "device_common.h"
 #include "internal.h"
 
 namespace mbmd {
@@ -23,19 +24,7 @@ namespace {
 
 constexpr int kRayThreads = 256;
 
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) sh[wv] = v;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0) {
-        const int nw = (blockDim.x + 63) >> 6;
-        for (int i = 0; i < nw; ++i) t += sh[i];
-    }
-    return t;
-}
+using dev::block_sum;
 
 struct RayModel {
     int K, E, C;
@@ -138,7 +127,44 @@ __global__ __launch_bounds__(kRayThreads) void k_ray_grad(RayModel m, int ni, co
     if (threadIdx.x == 0 && partials) partials[blockIdx.x] = tot;
 }
 
-// sum_iE c_iE q_iE^2 with q_iE = sum_k Q_Ek q_ik, c recomputed from l and r.
+// Ray i's share of sum_iE c_iE q_iE^2 with q_iE = sum_k Q_Ek q_ik, c recomputed
+// from l and r.
+template <int KT, int CT>
+__device__ __forceinline__ double ray_curv_at(const RayModel& m, const SharedModel& sm, int ni,
+                                              const float* __restrict__ l, const float* __restrict__ r,
+                                              const float* __restrict__ w, const float* __restrict__ q, int i) {
+    const int K = KT ? KT : m.K, C = CT ? CT : m.C;
+    float lk[kMaxMat], qk[kMaxMat], rc[kMaxChan], sig[kMaxChan];
+    for (int k = 0; k < K; ++k) {
+        lk[k] = l[(size_t)k * ni + i];
+        qk[k] = q[(size_t)k * ni + i];
+    }
+    for (int c = 0; c < C; ++c) {
+        rc[c] = r[(size_t)c * ni + i];
+        sig[c] = w[(size_t)c * ni + i] * m.rowS[c];
+    }
+    float a = 0.0f;
+#pragma unroll 2
+    for (int e = 0; e < m.E; ++e) {
+        float le = 0.0f, qe = 0.0f;
+        for (int k = 0; k < K; ++k) {
+            const float qek = sm.Q[e * K + k];
+            le = fmaf(qek, lk[k], le);
+            qe = fmaf(qek, qk[k], qe);
+        }
+        const float t = expf(-le);
+        float s = 0.0f, eta = 0.0f;
+        for (int c = 0; c < C; ++c) {
+            const float sce = sm.S[e * C + c];
+            s = fmaf(sce, rc[c], s);
+            eta = fmaf(sce, sig[c], eta);
+        }
+        const float ce = fmaxf(2.0f * eta + s - eta * t, 0.0f);
+        a = fmaf(ce * qe, qe, a);
+    }
+    return (double)a;
+}
+
 template <int KT, int CT>
 __global__ __launch_bounds__(kRayThreads) void k_ray_curv(RayModel m, int ni, const float* __restrict__ l,
                                                           const float* __restrict__ r,
@@ -148,42 +174,41 @@ __global__ __launch_bounds__(kRayThreads) void k_ray_curv(RayModel m, int ni, co
     __shared__ double sh[kRayThreads / 64];
     __shared__ SharedModel sm;
     stage_model<KT, CT>(m, sm);
-    const int K = KT ? KT : m.K, C = CT ? CT : m.C;
     const int i = blockIdx.x * kRayThreads + threadIdx.x;
-    double acc = 0.0;
-    if (i < ni) {
-        float lk[kMaxMat], qk[kMaxMat], rc[kMaxChan], sig[kMaxChan];
-        for (int k = 0; k < K; ++k) {
-            lk[k] = l[(size_t)k * ni + i];
-            qk[k] = q[(size_t)k * ni + i];
-        }
-        for (int c = 0; c < C; ++c) {
-            rc[c] = r[(size_t)c * ni + i];
-            sig[c] = w[(size_t)c * ni + i] * m.rowS[c];
-        }
-        float a = 0.0f;
-#pragma unroll 2
-        for (int e = 0; e < m.E; ++e) {
-            float le = 0.0f, qe = 0.0f;
-            for (int k = 0; k < K; ++k) {
-                const float qek = sm.Q[e * K + k];
-                le = fmaf(qek, lk[k], le);
-                qe = fmaf(qek, qk[k], qe);
-            }
-            const float t = expf(-le);
-            float s = 0.0f, eta = 0.0f;
-            for (int c = 0; c < C; ++c) {
-                const float sce = sm.S[e * C + c];
-                s = fmaf(sce, rc[c], s);
-                eta = fmaf(sce, sig[c], eta);
-            }
-            const float ce = fmaxf(2.0f * eta + s - eta * t, 0.0f);
-            a = fmaf(ce * qe, qe, a);
-        }
-        acc = (double)a;
-    }
+    const double acc = i < ni ? ray_curv_at<KT, CT>(m, sm, ni, l, r, w, q, i) : 0.0;
     const double tot = block_sum(acc, sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// The curvature of the objective along the direction in one launch: blocks
+// [0, nb_ray) write the rays' partial sums of c q^2 (region CQ2), blocks
+// [nb_ray, nb_ray + nb_pen) the penalty's partial sums of p^T R''(x) p (region
+// PRP).  (A last-block reduction in the same launch was tried: the per-block
+// device-scope release and the single-address ticket cost far more than the
+// separate reduction launch on a GPU whose L2s are per XCD.)
+template <int KT, int CT>
+__global__ __launch_bounds__(kRayThreads) void k_curvature(RayModel m, int ni, const float* __restrict__ l,
+                                                           const float* __restrict__ r,
+                                                           const float* __restrict__ w,
+                                                           const float* __restrict__ q, int nb_ray,
+                                                           PenaltyArgs pa, const float* __restrict__ x,
+                                                           const float* __restrict__ p,
+                                                           double* __restrict__ partials) {
+    __shared__ double sh[kRayThreads / 64];
+    __shared__ SharedModel sm;
+    const int b = blockIdx.x;
+    double acc = 0.0;
+    if (b < nb_ray) {                                      // uniform over the block
+        stage_model<KT, CT>(m, sm);
+        const int i = b * kRayThreads + threadIdx.x;
+        if (i < ni) acc = ray_curv_at<KT, CT>(m, sm, ni, l, r, w, q, i);
+    } else {
+        const int j = (b - nb_ray) * kRayThreads + threadIdx.x;
+        if (j < pa.nx * pa.ny) acc = dev::penalty_quadform_at(pa, x, p, j);
+    }
+    const double tot = block_sum(acc, sh);
+    if (threadIdx.x == 0)
+        partials[b < nb_ray ? (size_t)R_CQ2 * kMaxPartials + b : (size_t)R_PRP * kMaxPartials + (b - nb_ray)] = tot;
 }
 
 template <int KT, int CT>
@@ -318,7 +343,7 @@ __global__ __launch_bounds__(kRayThreads) void k_identity_iterate(RayModel m, in
     __shared__ double sh[kRayThreads / 64];
     __shared__ SharedModel sm;
     stage_model<KT, CT>(m, sm);
-    const int K = KT ? KT : K, C = CT ? CT : C;
+    const int K = KT ? KT : m.K, C = CT ? CT : m.C;
     const int i = blockIdx.x * kRayThreads + threadIdx.x;
     const bool act = i < ni;
     float xk[kMaxMat], yc[kMaxChan], wc[kMaxChan], sig[kMaxChan], Mb[kMaxPacked];
@@ -457,6 +482,26 @@ int launch_ray_curv(const RayArgs& a, const float* l, const float* r, const floa
     }
     MBMD_LAUNCHED();
     return nb;
+}
+
+void launch_curvature(const RayArgs& a, const float* l, const float* r, const float* q, const PenaltyArgs* pen,
+                      const float* x, const float* p, double* partials, int* counts, hipStream_t s) {
+    const int nb_ray = blocks_for(a.ni);
+    const int nb_pen = pen ? (pen->nx * pen->ny + kRayThreads - 1) / kRayThreads : 0;
+    MBMD_REQUIRE(nb_ray <= kMaxPartials && nb_pen <= kMaxPartials, MBMD_ERR_SHAPE,
+                 "too many rays or pixels for the partial-sum buffer");
+    const PenaltyArgs pa = pen ? *pen : PenaltyArgs{1, 0, 0, 0, nullptr, 0.0f};
+    {
+        KernelTimer kt_("k_curvature", s);
+#define L_(KT, CT) hipLaunchKernelGGL((k_curvature<KT, CT>), dim3(nb_ray + nb_pen), dim3(kRayThreads), 0, s,         \
+                                   model_of(a), a.ni, l, r, a.w, q, nb_ray, pa, x, p, partials)
+        MBMD_RAY_DISPATCH(a.K, a.C, L_);
+#undef L_
+        kt_.stop();
+    }
+    MBMD_LAUNCHED();
+    counts[R_CQ2] = nb_ray;
+    counts[R_PRP] = nb_pen;
 }
 
 void launch_forward_model(const RayArgs& a, const float* l, float* ybar, hipStream_t s) {
