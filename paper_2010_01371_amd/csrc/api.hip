@@ -151,8 +151,8 @@ void carve(Problem& P) {
     if (!P.identity && is_pow2(P.nx) && is_pow2(P.ny)) {
         P.spec = A.take<float2>(K * nj);
         P.Linv = A.take<float>(npk * nj);
-        P.tw_x = A.take<float2>(P.nx / 2);
-        P.tw_y = A.take<float2>(P.ny / 2);
+        P.tw_x = A.take<float2>(P.nx);
+        P.tw_y = A.take<float2>(P.ny);
         if (P.nx == P.ny) {
             const int T = haar_tile(P.nx), nt = P.nx / T;
             P.coef = A.take<float>(K * nj);
@@ -298,8 +298,8 @@ void precond_iteration(Problem& P, float* x, int kind, double* trace_slot, hipSt
                                           region(P, R_PHI_R), s, part);
     counts[R_GP] = apply_direction(P, kind, P.g_img, P.p_img, -1.0f, region(P, R_GP), s);
     project(P, P.p_img, P.q, P.K, s);
-    counts[R_CQ2] = launch_ray_curv(ray_args(P), P.l, P.r, P.q, region(P, R_CQ2), s);
-    if (P.has_penalty) counts[R_PRP] = launch_penalty_quadform(pen_args(P), x, P.p_img, region(P, R_PRP), s);
+    const PenaltyArgs pa = pen_args(P);
+    launch_curvature(ray_args(P), P.l, P.r, P.q, P.has_penalty ? &pa : nullptr, x, P.p_img, P.partials, counts, s);
     launch_reduce_final(P.partials, counts, P.scal, trace_slot, 1, P.flags, s);
     launch_axpy2_alpha(P.K * P.nj, x, P.p_img, P.K * P.ni, P.l, P.q, P.scal + S_ALPHA, s);
 }

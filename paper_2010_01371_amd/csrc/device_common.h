@@ -1,0 +1,109 @@
+// Device helpers shared by the image-space and per-ray kernels: FP64 block
+// sums, the Huber weight, the penalty's curvature along a direction for one
+// pixel, and the final reduction of the partial-sum regions into the objective
+// and the step size.
+#pragma once
+
+#include "internal.h"
+
+namespace mbmd {
+namespace dev {
+
+// Sum over the block (any multiple of 64 threads), valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int i = 0; i < nw; ++i) t += sh[i];
+    }
+    return t;
+}
+
+__device__ __forceinline__ float huber_omega(float t, float d) {
+    const float a = fabsf(t);
+    return a <= d ? 1.0f : d / a;
+}
+
+// Pixel j's share of p^T R''(x) p: the pairs (j, right) and (j, down).  Huber
+// (one material): beta sum omega(x_j - x_j') (p_j - p_j')^2; quadratic:
+// sum_kl beta_kl (p_k,j - p_k,j')(p_l,j - p_l,j').
+__device__ __forceinline__ double penalty_quadform_at(const PenaltyArgs& a, const float* __restrict__ x,
+                                                      const float* __restrict__ p, int j) {
+    const int nj = a.nx * a.ny;
+    const int iy = j / a.nx, ix = j - iy * a.nx;
+    const bool R = ix + 1 < a.nx, D = iy + 1 < a.ny;
+    double acc = 0.0;
+    if (a.kind == MBMD_PENALTY_HUBER) {
+        float s = 0.0f;
+        if (R) { const float dp = p[j] - p[j + 1]; s += huber_omega(x[j] - x[j + 1], a.delta) * dp * dp; }
+        if (D) { const float dp = p[j] - p[j + a.nx]; s += huber_omega(x[j] - x[j + a.nx], a.delta) * dp * dp; }
+        acc = (double)a.beta[0] * (double)s;
+    } else {
+        for (int k = 0; k < a.K; ++k)
+            for (int l2 = 0; l2 < a.K; ++l2) {
+                const float* pk = p + (size_t)k * nj;
+                const float* pl = p + (size_t)l2 * nj;
+                float s = 0.0f;
+                if (R) s += (pk[j] - pk[j + 1]) * (pl[j] - pl[j + 1]);
+                if (D) s += (pk[j] - pk[j + a.nx]) * (pl[j] - pl[j + a.nx]);
+                acc += (double)a.beta[k * a.K + l2] * (double)s;
+            }
+    }
+    return acc;
+}
+
+struct Counts {
+    int c[kRegions];
+};
+
+// Threads of the final reduction: two wavefronts per region.
+constexpr int kReduceThreads = 128 * kRegions;
+
+// Sums every partial-sum region (region r at partials + r kMaxPartials, counts.c[r]
+// entries) -- two wavefronts per region, each lane adding a strided share with
+// eight loads in flight, in a fixed order -- and forms the scalars:
+// phi = PHI_L + PHI_R, and with mode bit 1 the step alpha = -GP / (CQ2 + PRP).
+// A non-finite phi or alpha raises flags[0].  Block of kReduceThreads threads;
+// sh: 2 kRegions doubles of shared memory.
+__device__ __forceinline__ void final_reduce(const double* partials, const Counts& counts, double* scal,
+                                             double* trace_slot, int mode, int* flags, double* sh) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = wave >> 1, t = (wave & 1) * 64 + lane;
+    const double* pr = partials + (size_t)r * kMaxPartials;
+    const int n = counts.c[r];
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int i = t; i < n; i += 128 * 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (i + 128 * u < n) acc[u] += pr[i + 128 * u];
+    }
+    double v = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double sums[kRegions];
+    for (int k = 0; k < kRegions; ++k) sums[k] = sh[2 * k] + sh[2 * k + 1];
+    const double phi = sums[R_PHI_L] + sums[R_PHI_R];
+    scal[S_PHI] = phi;
+    if (trace_slot) *trace_slot = phi;
+    bool bad = !isfinite(phi);
+    if (mode & 1) {
+        const double gp = sums[R_GP];
+        const double den = sums[R_CQ2] + sums[R_PRP];
+        const double alpha = den > 0.0 ? -gp / den : 0.0;
+        scal[S_GP] = gp;
+        scal[S_DEN] = den;
+        scal[S_ALPHA] = isfinite(alpha) ? alpha : 0.0;
+        bad = bad || !isfinite(alpha);
+    }
+    if (bad && flags) flags[0] = 1;
+}
+
+}  // namespace dev
+}  // namespace mbmd

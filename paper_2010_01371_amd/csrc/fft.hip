@@ -4,17 +4,21 @@
 // applied to every material image: M M^T v = M0 U^H L^-1 U M0 v, so one
 // iteration needs one forward and one inverse 2D transform per material.
 // Three passes:
-//   rows   : one workgroup per image row (all materials); optional packed
+//   rows   : a few image rows per workgroup (all materials); optional packed
 //            per-pixel blocks applied on load (M0) and a circular shift
-//            (used by the impulse-response build); radix-2 decimation in
-//            time in LDS from bit-reversed loads.
-//   columns: a group of columns per workgroup; forward DIT, then (apply
-//            only) the per-frequency N_k x N_k filter and an inverse
-//            decimation-in-frequency transform in the same LDS buffer, so the
-//            spectrum makes one round trip through memory.
-//   rows^-1: inverse DIT per row, real part, 1/(nx ny), packed blocks (M0)
-//            on store, sign, and per-block FP64 partials of g . out.
-// Twiddles exp(-2 pi i k / N) are computed in FP64 on the host.
+//            (used by the impulse-response build).
+//   columns: a few columns per workgroup; forward transform, then (apply
+//            only) the per-frequency N_k x N_k filter and the inverse
+//            transform in the same LDS buffer, so the spectrum makes one
+//            round trip through memory.
+//   rows^-1: inverse transform per row, real part, 1/(nx ny), packed blocks
+//            (M0) on store, sign, and per-block FP64 partials of g . out.
+// Each 1D transform is a mixed-radix Stockham autosort FFT (radix 8, then 4 or
+// 2 for the last pass): natural order in and out, so no bit reversal; N/8
+// threads per transform, each holding eight values in registers per pass, with
+// one read phase and one write phase through LDS per pass.  For N = 512 that
+// is three passes (the first without twiddles) instead of nine radix-2 stages.
+// Twiddles exp(-2 pi i m / N), m < N, are computed in FP64 on the host.
 #include <cmath>
 #include <vector>
 
@@ -26,60 +30,132 @@ namespace {
 
 constexpr int kThreads = 256;
 
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-__device__ __forceinline__ int bitrev(int x, int logn) { return (int)(__brev((unsigned)x) >> (32 - logn)); }
-
-// In-place radix-2 DIT over nbuf contiguous transforms of length N (input in
-// bit-reversed order, output natural).  INV conjugates the twiddles.
+// z times -i (forward) or +i (inverse)
 template <bool INV>
-__device__ void fft_dit(float2* buf, int nbuf, int N, int logN, const float2* __restrict__ tw) {
-    const int halfN = N >> 1;
-    const int total = nbuf * halfN;
-    for (int s = 1; s <= logN; ++s) {
-        const int half = 1 << (s - 1);
-        const int tstride = N >> s;
-        for (int t = threadIdx.x; t < total; t += blockDim.x) {
-            const int bidx = t >> (logN - 1);
-            const int bi = t & (halfN - 1);
-            const int grp = bi >> (s - 1);
-            const int pos = bi & (half - 1);
-            const int i0 = bidx * N + grp * 2 * half + pos;
-            const int i1 = i0 + half;
-            float2 w = tw[pos * tstride];
-            if (INV) w.y = -w.y;
-            const float2 a = buf[i0];
-            const float2 bw = cmul(buf[i1], w);
-            buf[i0] = make_float2(a.x + bw.x, a.y + bw.y);
-            buf[i1] = make_float2(a.x - bw.x, a.y - bw.y);
-        }
-        __syncthreads();
+__device__ __forceinline__ float2 mul_mi(float2 z) {
+    return INV ? make_float2(-z.y, z.x) : make_float2(z.y, -z.x);
+}
+
+// 4-point DFT in place, natural order in and out.
+template <bool INV>
+__device__ __forceinline__ void dft4(float2& v0, float2& v1, float2& v2, float2& v3) {
+    const float2 b0 = cadd(v0, v2), b1 = cadd(v1, v3), b2 = csub(v0, v2), b3 = mul_mi<INV>(csub(v1, v3));
+    v0 = cadd(b0, b1);
+    v1 = cadd(b2, b3);
+    v2 = csub(b0, b1);
+    v3 = csub(b2, b3);
+}
+
+// 8-point DFT in place: one radix-2 split into even and odd outputs, then two
+// 4-point DFTs.
+template <bool INV>
+__device__ __forceinline__ void dft8(float2* v) {
+    const float h = 0.70710678118654752f;
+    const float2 w1 = make_float2(h, INV ? h : -h), w3 = make_float2(-h, INV ? h : -h);
+    float2 a0 = cadd(v[0], v[4]), a1 = cadd(v[1], v[5]), a2 = cadd(v[2], v[6]), a3 = cadd(v[3], v[7]);
+    float2 o0 = csub(v[0], v[4]), o1 = cmul(csub(v[1], v[5]), w1), o2 = mul_mi<INV>(csub(v[2], v[6])),
+           o3 = cmul(csub(v[3], v[7]), w3);
+    dft4<INV>(a0, a1, a2, a3);
+    dft4<INV>(o0, o1, o2, o3);
+    v[0] = a0;
+    v[1] = o0;
+    v[2] = a1;
+    v[3] = o1;
+    v[4] = a2;
+    v[5] = o2;
+    v[6] = a3;
+    v[7] = o3;
+}
+
+template <bool INV, int R>
+__device__ __forceinline__ void dftR(float2* v) {
+    if constexpr (R == 8) {
+        dft8<INV>(v);
+    } else if constexpr (R == 4) {
+        dft4<INV>(v[0], v[1], v[2], v[3]);
+    } else {
+        const float2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
     }
 }
 
-// In-place radix-2 DIF (natural input, bit-reversed output).
-template <bool INV>
-__device__ void fft_dif(float2* buf, int nbuf, int N, int logN, const float2* __restrict__ tw) {
-    const int halfN = N >> 1;
-    const int total = nbuf * halfN;
-    for (int s = logN; s >= 1; --s) {
-        const int half = 1 << (s - 1);
-        const int tstride = N >> s;
-        for (int t = threadIdx.x; t < total; t += blockDim.x) {
-            const int bidx = t >> (logN - 1);
-            const int bi = t & (halfN - 1);
-            const int grp = bi >> (s - 1);
-            const int pos = bi & (half - 1);
-            const int i0 = bidx * N + grp * 2 * half + pos;
-            const int i1 = i0 + half;
-            float2 w = tw[pos * tstride];
-            if (INV) w.y = -w.y;
-            const float2 a = buf[i0], b = buf[i1];
-            buf[i0] = make_float2(a.x + b.x, a.y + b.y);
-            buf[i1] = cmul(make_float2(a.x - b.x, a.y - b.y), w);
+__host__ __device__ inline int fft_threads(int N) { return N >= 8 ? N / 8 : 1; }
+// LDS position of element i of a transform: one pad slot after every eight
+// elements, which keeps the strided write phases of the radix-8 passes (stride 8
+// in the first, 64 apart in groups of 8 in the second) at most 2-way bank
+// conflicted; a transform of length N takes lds_len(N) slots, an odd number, so
+// that the same element of neighbouring transforms falls in different banks.
+__host__ __device__ inline int pad(int i) { return i + (i >> 3); }
+__host__ __device__ inline int lds_len(int N) { return (N + (N >> 3)) | 1; }
+
+// One Stockham pass of radix R over a length-N transform held in LDS (buf),
+// after Ns points have been combined: butterfly j reads buf[j + r N/R],
+// multiplies by W_{Ns R}^{r (j mod Ns)}, takes the R-point DFT and writes
+// buf[(j / Ns) Ns R + (j mod Ns) + q Ns].  t in [0, T) is the thread's index in
+// its transform; all threads of the block read before any writes (barrier).
+template <bool INV, int R>
+__device__ __forceinline__ void stockham_pass(float2* buf, int N, int Ns, int t, int T, bool active,
+                                              const float2* __restrict__ tw) {
+    constexpr int NB = 8 / R;                  // butterflies per thread (T = N / 8 for N >= 8)
+    const int nbf = N / R;
+    const int step = N / (Ns * R);             // twiddle table stride
+    float2 v[NB][R];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int j = t + b * T;
+        if (active && j < nbf) {
+            const int k = j & (Ns - 1);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                v[b][r] = buf[pad(j + r * nbf)];
+                if (r > 0 && Ns > 1) {
+                    float2 w = tw[r * k * step];
+                    if (INV) w.y = -w.y;
+                    v[b][r] = cmul(v[b][r], w);
+                }
+            }
         }
-        __syncthreads();
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int j = t + b * T;
+        if (active && j < nbf) {
+            dftR<INV, R>(v[b]);
+            const int k = j & (Ns - 1);
+            const int d = (j - k) * R + k;
+#pragma unroll
+            for (int q = 0; q < R; ++q) buf[pad(d + q * Ns)] = v[b][q];
+        }
+    }
+    __syncthreads();
+}
+
+// Full length-N transform (N a power of two) of the block's transforms; each
+// thread owns index t of the transform at buf (inactive threads only join the
+// barriers).  The pass sequence depends on N alone, so it is uniform.
+template <bool INV>
+__device__ __forceinline__ void fft_lds(float2* buf, int N, int t, int T, bool active,
+                                        const float2* __restrict__ tw) {
+    int Ns = 1;
+    while (Ns < N) {
+        const int rem = N / Ns;
+        if (rem % 8 == 0) {
+            stockham_pass<INV, 8>(buf, N, Ns, t, T, active, tw);
+            Ns *= 8;
+        } else if (rem == 4) {
+            stockham_pass<INV, 4>(buf, N, Ns, t, T, active, tw);
+            Ns *= 4;
+        } else {
+            stockham_pass<INV, 2>(buf, N, Ns, t, T, active, tw);
+            Ns *= 2;
+        }
     }
 }
 
@@ -97,88 +173,134 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return t;
 }
 
-__global__ __launch_bounds__(kThreads) void k_fft_rows_fwd(int K, int nx, int ny, int logx,
+// RB rows per block: transform (rr, k) of row y0 + rr lives at buf[(rr K + k) nx].
+__global__ __launch_bounds__(kThreads) void k_fft_rows_fwd(int K, int nx, int ny, int RB,
                                                            const float* __restrict__ in,
                                                            const float* __restrict__ M, int sy, int sx,
                                                            float2* __restrict__ spec,
                                                            const float2* __restrict__ tw) {
     extern __shared__ float2 buf[];
-    const int y = blockIdx.x;
+    const int PN = lds_len(nx);
+    float2* twl = buf + (size_t)RB * K * PN;               // twiddle table staged in LDS
+    const int y0 = blockIdx.x * RB;
     const int nj = nx * ny;
-    const int ys = (y + sy) % ny;
-    for (int xx = threadIdx.x; xx < nx; xx += blockDim.x) {
-        const int j = ys * nx + (xx + sx) % nx;
-        float a[kMaxMat];
-        for (int k = 0; k < K; ++k) a[k] = in[(size_t)k * nj + j];
-        const int br = bitrev(xx, logx);
-        for (int k = 0; k < K; ++k) {
+    const int lx = __builtin_ctz(nx);                     // sizes are powers of two
+    for (int idx = threadIdx.x; idx < nx; idx += blockDim.x) twl[idx] = tw[idx];
+    for (int idx = threadIdx.x; idx < RB * nx; idx += blockDim.x) {
+        const int rr = idx >> lx, xx = idx & (nx - 1);
+        if (y0 + rr >= ny) continue;
+        const int j = ((y0 + rr + sy) & (ny - 1)) * nx + ((xx + sx) & (nx - 1));
+        float a[kMaxMat];                                  // static indices: registers
+#pragma unroll
+        for (int k = 0; k < kMaxMat; ++k) a[k] = k < K ? in[(size_t)k * nj + j] : 0.0f;
+#pragma unroll
+        for (int k = 0; k < kMaxMat; ++k) {
+            if (k >= K) break;
             float v = a[k];
             if (M) {
                 v = 0.0f;
-                for (int l2 = 0; l2 < K; ++l2) v = fmaf(M[(size_t)packed_index(k, l2, K) * nj + j], a[l2], v);
+#pragma unroll
+                for (int l2 = 0; l2 < kMaxMat; ++l2)
+                    if (l2 < K) v = fmaf(M[(size_t)packed_index(k, l2, K) * nj + j], a[l2], v);
             }
-            buf[k * nx + br] = make_float2(v, 0.0f);
+            buf[(rr * K + k) * PN + pad(xx)] = make_float2(v, 0.0f);
         }
     }
     __syncthreads();
-    fft_dit<false>(buf, K, nx, logx, tw);
-    for (int idx = threadIdx.x; idx < K * nx; idx += blockDim.x) {
-        const int k = idx / nx, xx = idx - k * nx;
-        spec[(size_t)k * nj + (size_t)y * nx + xx] = buf[idx];
+    const int T = fft_threads(nx);
+    const int tr = threadIdx.x / T;                        // transform index rr K + k
+    const bool active = tr < RB * K && y0 + tr / K < ny;
+    fft_lds<false>(buf + (size_t)(active ? tr : 0) * PN, nx, threadIdx.x - tr * T, T, active, twl);
+    for (int idx = threadIdx.x; idx < RB * K * nx; idx += blockDim.x) {
+        const int trn = idx >> lx, xx = idx & (nx - 1);
+        const int rr = trn / K, k = trn - rr * K;
+        if (y0 + rr < ny) spec[(size_t)k * nj + (size_t)(y0 + rr) * nx + xx] = buf[trn * PN + pad(xx)];
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_fft_cols(int K, int nx, int ny, int logy, int C,
-                                                       float2* __restrict__ spec,
+// C columns per block: transform (c, k) of column x0 + c lives at buf[(c K + k) ny];
+// the block's filter blocks are staged at fl[(p ny + yy) C + c].  All global
+// reads of the block (spectrum, twiddles, filter) are issued in batches before
+// any is waited for.
+constexpr int kBatch = 8;
+__global__ __launch_bounds__(kThreads) void k_fft_cols(int K, int nx, int ny, int C, float2* __restrict__ spec,
                                                        const float* __restrict__ filt,
                                                        const float2* __restrict__ tw) {
     extern __shared__ float2 buf[];
+    const int PN = lds_len(ny);
+    float2* twl = buf + (size_t)K * C * PN;                // twiddle table staged in LDS
+    float* fl = reinterpret_cast<float*>(twl + ny);        // filter blocks staged in LDS
     const int x0 = blockIdx.x * C;
     const int nj = nx * ny;
-    const int tot = K * C * ny;
-    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-        const int c = idx % C;
-        const int rest = idx / C;
-        const int yy = rest % ny, k = rest / ny;
-        buf[(k * C + c) * ny + bitrev(yy, logy)] = spec[(size_t)k * nj + (size_t)yy * nx + x0 + c];
+    const int npk = K * (K + 1) / 2;
+    const int tot = K * C * ny, fl_tot = filt ? npk * C * ny : 0;
+    const int lc = __builtin_ctz(C), ly = __builtin_ctz(ny);   // powers of two
+    for (int idx = threadIdx.x; idx < ny; idx += kThreads) twl[idx] = tw[idx];
+    for (int base = threadIdx.x; base < tot || base < fl_tot; base += kThreads * kBatch) {
+        float2 v[kBatch];
+        float fv[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int idx = base + u * kThreads;
+            const int c = idx & (C - 1), rest = idx >> lc;       // c fastest: neighbouring columns
+            const int yy = rest & (ny - 1), k = rest >> ly;
+            if (idx < tot) v[u] = spec[(size_t)k * nj + (size_t)yy * nx + x0 + c];
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int idx = base + u * kThreads;
+            const int c = idx & (C - 1), rest = idx >> lc;
+            const int yy = rest & (ny - 1), p = rest >> ly;
+            if (idx < fl_tot) fv[u] = filt[(size_t)p * nj + (size_t)yy * nx + x0 + c];
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int idx = base + u * kThreads;
+            const int c = idx & (C - 1), rest = idx >> lc;
+            const int yy = rest & (ny - 1), k = rest >> ly;
+            if (idx < tot) buf[(c * K + k) * PN + pad(yy)] = v[u];
+            if (idx < fl_tot) fl[idx] = fv[u];
+        }
     }
     __syncthreads();
-    fft_dit<false>(buf, K * C, ny, logy, tw);
+    const int T = fft_threads(ny);
+    const int tr = threadIdx.x / T;
+    const bool active = tr < C * K;
+    float2* mine = buf + (size_t)(active ? tr : 0) * PN;
+    const int t = threadIdx.x - tr * T;
+    fft_lds<false>(mine, ny, t, T, active, twl);
     if (filt) {
-        for (int idx = threadIdx.x; idx < C * ny; idx += blockDim.x) {
-            const int c = idx % C, yy = idx / C;
-            const size_t f = (size_t)yy * nx + x0 + c;
-            float2 a[kMaxMat];
-            for (int k = 0; k < K; ++k) a[k] = buf[(k * C + c) * ny + yy];
-            for (int k = 0; k < K; ++k) {
+        for (int idx = threadIdx.x; idx < C * ny; idx += kThreads) {
+            const int c = idx & (C - 1), yy = idx >> lc;
+            float2 a[kMaxMat];                             // static indices: registers
+#pragma unroll
+            for (int k = 0; k < kMaxMat; ++k) a[k] = k < K ? buf[(c * K + k) * PN + pad(yy)] : make_float2(0.0f, 0.0f);
+#pragma unroll
+            for (int k = 0; k < kMaxMat; ++k) {
+                if (k >= K) break;
                 float re = 0.0f, im = 0.0f;
-                for (int l2 = 0; l2 < K; ++l2) {
-                    const float m = filt[(size_t)packed_index(k, l2, K) * nj + f];
+#pragma unroll
+                for (int l2 = 0; l2 < kMaxMat; ++l2) {
+                    if (l2 >= K) break;
+                    const float m = fl[(packed_index(k, l2, K) * ny + yy) * C + c];
                     re = fmaf(m, a[l2].x, re);
                     im = fmaf(m, a[l2].y, im);
                 }
-                buf[(k * C + c) * ny + yy] = make_float2(re, im);
+                buf[(c * K + k) * PN + pad(yy)] = make_float2(re, im);
             }
         }
         __syncthreads();
-        fft_dif<true>(buf, K * C, ny, logy, tw);
-        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-            const int c = idx % C;
-            const int rest = idx / C;
-            const int yy = rest % ny, k = rest / ny;
-            spec[(size_t)k * nj + (size_t)yy * nx + x0 + c] = buf[(k * C + c) * ny + bitrev(yy, logy)];
-        }
-    } else {
-        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-            const int c = idx % C;
-            const int rest = idx / C;
-            const int yy = rest % ny, k = rest / ny;
-            spec[(size_t)k * nj + (size_t)yy * nx + x0 + c] = buf[(k * C + c) * ny + yy];
-        }
+        fft_lds<true>(mine, ny, t, T, active, twl);
+    }
+    for (int idx = threadIdx.x; idx < tot; idx += kThreads) {
+        const int c = idx & (C - 1);
+        const int rest = idx >> lc;
+        const int yy = rest & (ny - 1), k = rest >> ly;
+        spec[(size_t)k * nj + (size_t)yy * nx + x0 + c] = buf[(c * K + k) * PN + pad(yy)];
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_fft_rows_inv(int K, int nx, int ny, int logx,
+__global__ __launch_bounds__(kThreads) void k_fft_rows_inv(int K, int nx, int ny, int RB,
                                                            const float2* __restrict__ spec,
                                                            const float* __restrict__ M, float scale,
                                                            float* __restrict__ out,
@@ -187,24 +309,39 @@ __global__ __launch_bounds__(kThreads) void k_fft_rows_inv(int K, int nx, int ny
                                                            const float2* __restrict__ tw) {
     extern __shared__ float2 buf[];
     __shared__ double sh[kThreads / 64];
-    const int y = blockIdx.x;
+    const int PN = lds_len(nx);
+    float2* twl = buf + (size_t)RB * K * PN;               // twiddle table staged in LDS
+    const int y0 = blockIdx.x * RB;
     const int nj = nx * ny;
-    for (int idx = threadIdx.x; idx < K * nx; idx += blockDim.x) {
-        const int k = idx / nx, xx = idx - k * nx;
-        buf[k * nx + bitrev(xx, logx)] = spec[(size_t)k * nj + (size_t)y * nx + xx];
+    const int lx = __builtin_ctz(nx);                     // sizes are powers of two
+    for (int idx = threadIdx.x; idx < nx; idx += blockDim.x) twl[idx] = tw[idx];
+    for (int idx = threadIdx.x; idx < RB * K * nx; idx += blockDim.x) {
+        const int trn = idx >> lx, xx = idx & (nx - 1);
+        const int rr = trn / K, k = trn - rr * K;
+        if (y0 + rr < ny) buf[trn * PN + pad(xx)] = spec[(size_t)k * nj + (size_t)(y0 + rr) * nx + xx];
     }
     __syncthreads();
-    fft_dit<true>(buf, K, nx, logx, tw);
+    const int T = fft_threads(nx);
+    const int tr = threadIdx.x / T;
+    const bool active = tr < RB * K && y0 + tr / K < ny;
+    fft_lds<true>(buf + (size_t)(active ? tr : 0) * PN, nx, threadIdx.x - tr * T, T, active, twl);
     double dot = 0.0;
-    for (int xx = threadIdx.x; xx < nx; xx += blockDim.x) {
-        const int j = y * nx + xx;
-        float a[kMaxMat];
-        for (int k = 0; k < K; ++k) a[k] = buf[k * nx + xx].x * scale;
-        for (int k = 0; k < K; ++k) {
+    for (int idx = threadIdx.x; idx < RB * nx; idx += blockDim.x) {
+        const int rr = idx >> lx, xx = idx & (nx - 1);
+        if (y0 + rr >= ny) continue;
+        const int j = (y0 + rr) * nx + xx;
+        float a[kMaxMat];                                  // static indices: registers
+#pragma unroll
+        for (int k = 0; k < kMaxMat; ++k) a[k] = k < K ? buf[(rr * K + k) * PN + pad(xx)].x * scale : 0.0f;
+#pragma unroll
+        for (int k = 0; k < kMaxMat; ++k) {
+            if (k >= K) break;
             float v = a[k];
             if (M) {
                 v = 0.0f;
-                for (int l2 = 0; l2 < K; ++l2) v = fmaf(M[(size_t)packed_index(k, l2, K) * nj + j], a[l2], v);
+#pragma unroll
+                for (int l2 = 0; l2 < kMaxMat; ++l2)
+                    if (l2 < K) v = fmaf(M[(size_t)packed_index(k, l2, K) * nj + j], a[l2], v);
             }
             out[(size_t)k * nj + j] = v;
             if (g) dot += (double)g[(size_t)k * nj + j] * (double)v;
@@ -224,32 +361,44 @@ __global__ void k_spectrum_real_to_blocks(int K, int nj, int k_col, const float2
     }
 }
 
-int ilog2(int n) {
-    int l = 0;
-    while ((1 << l) < n) ++l;
-    return l;
+// Rows per block of the row passes: enough transforms for about one wavefront of
+// FFT threads.  Blocks always have kThreads threads, so that the loads and stores
+// of a block are spread over all of them (few in flight per thread); threads
+// beyond the transforms only join the barriers.
+int rows_per_block(int K, int nx, int ny) {
+    int RB = 1;
+    while (RB * 2 * K * fft_threads(nx) <= 64 && RB * 2 <= ny) RB *= 2;
+    return RB;
 }
 
+// Columns per block of the column pass: as many as keep every thread of the
+// block in a transform, at most 8 (C-column row segments per load).
 int col_group(int K, int nx, int ny) {
-    int C = 8;
-    while (C > 1 && (size_t)K * C * ny * sizeof(float2) > 32768) C >>= 1;
-    while (C > 1 && nx / C < 256) C >>= 1;
-    while (C > nx) C >>= 1;
+    int C = 1;
+    while (C < 8 && C * 2 * K * fft_threads(ny) <= kThreads && C * 2 <= nx) C *= 2;
     return C;
 }
+
+size_t cols_lds(int K, int C, int ny, bool filt) {
+    return sizeof(float2) * ((size_t)K * C * lds_len(ny) + ny) +
+           (filt ? sizeof(float) * (size_t)(K * (K + 1) / 2) * C * ny : 0);
+}
+
+size_t rows_lds(int K, int RB, int nx) { return sizeof(float2) * ((size_t)RB * K * lds_len(nx) + nx); }
 
 void check_sizes(int K, int nx, int ny) {
     MBMD_REQUIRE(nx >= 2 && ny >= 2 && (nx & (nx - 1)) == 0 && (ny & (ny - 1)) == 0, MBMD_ERR_SHAPE,
                  "the Fourier preconditioner needs power-of-two image sizes");
-    MBMD_REQUIRE((size_t)K * nx * sizeof(float2) <= 65536 && (size_t)K * ny * sizeof(float2) <= 65536,
+    MBMD_REQUIRE(K * fft_threads(nx) <= kThreads && K * fft_threads(ny) <= kThreads &&
+                     rows_lds(K, 1, nx) <= 65536 && cols_lds(K, 1, ny, true) <= 65536,
                  MBMD_ERR_SHAPE, "image too large for the LDS-resident FFT");
 }
 
 }  // namespace
 
 void fill_twiddles(float2* tw, int n, hipStream_t s) {
-    std::vector<float2> h(n / 2 > 0 ? n / 2 : 1);
-    for (int k = 0; k < n / 2; ++k) {
+    std::vector<float2> h(n);
+    for (int k = 0; k < n; ++k) {
         const double a = -2.0 * M_PI * (double)k / (double)n;
         h[k] = make_float2((float)std::cos(a), (float)std::sin(a));
     }
@@ -260,18 +409,19 @@ void fill_twiddles(float2* tw, int n, hipStream_t s) {
 void launch_fft2_forward(int K, int nx, int ny, const float* in, const float* M, int sy, int sx, float2* spec,
                          const float2* twx, const float2* twy, hipStream_t s) {
     check_sizes(K, nx, ny);
+    const int RB = rows_per_block(K, nx, ny);
     {
         KernelTimer kt_("k_fft_rows_fwd", s);
-        hipLaunchKernelGGL(k_fft_rows_fwd, dim3(ny), dim3(kThreads), sizeof(float2) * K * nx, s, K, nx, ny,
-                       ilog2(nx), in, M, sy, sx, spec, twx);
+        hipLaunchKernelGGL(k_fft_rows_fwd, dim3((ny + RB - 1) / RB), dim3(kThreads),
+                           rows_lds(K, RB, nx), s, K, nx, ny, RB, in, M, sy, sx, spec, twx);
         kt_.stop();
     }
     MBMD_LAUNCHED();
     const int C = col_group(K, nx, ny);
     {
         KernelTimer kt_("k_fft_cols", s);
-        hipLaunchKernelGGL(k_fft_cols, dim3(nx / C), dim3(kThreads), sizeof(float2) * K * C * ny, s, K, nx, ny,
-                       ilog2(ny), C, spec, (const float*)nullptr, twy);
+        hipLaunchKernelGGL(k_fft_cols, dim3(nx / C), dim3(kThreads), cols_lds(K, C, ny, false), s, K, nx, ny, C, spec,
+                           (const float*)nullptr, twy);
         kt_.stop();
     }
     MBMD_LAUNCHED();
@@ -281,30 +431,33 @@ int launch_fourier_apply(int K, int nx, int ny, const float* in, const float* M,
                          const float2* twx, const float2* twy, float* out, float out_sign, const float* g,
                          double* partials, hipStream_t s) {
     check_sizes(K, nx, ny);
-    MBMD_REQUIRE(ny <= kMaxPartials, MBMD_ERR_SHAPE, "too many rows for the partial-sum buffer");
+    const int RB = rows_per_block(K, nx, ny);
+    const int nblk = (ny + RB - 1) / RB;
+    MBMD_REQUIRE(nblk <= kMaxPartials, MBMD_ERR_SHAPE, "too many rows for the partial-sum buffer");
     {
         KernelTimer kt_("k_fft_rows_fwd", s);
-        hipLaunchKernelGGL(k_fft_rows_fwd, dim3(ny), dim3(kThreads), sizeof(float2) * K * nx, s, K, nx, ny,
-                       ilog2(nx), in, M, 0, 0, spec, twx);
+        hipLaunchKernelGGL(k_fft_rows_fwd, dim3(nblk), dim3(kThreads), rows_lds(K, RB, nx), s, K, nx, ny, RB, in, M,
+                           0, 0, spec, twx);
         kt_.stop();
     }
     MBMD_LAUNCHED();
     const int C = col_group(K, nx, ny);
+    MBMD_REQUIRE(cols_lds(K, C, ny, true) <= 65536, MBMD_ERR_SHAPE, "image too large for the LDS-resident FFT");
     {
         KernelTimer kt_("k_fft_cols", s);
-        hipLaunchKernelGGL(k_fft_cols, dim3(nx / C), dim3(kThreads), sizeof(float2) * K * C * ny, s, K, nx, ny,
-                       ilog2(ny), C, spec, Filt, twy);
+        hipLaunchKernelGGL(k_fft_cols, dim3(nx / C), dim3(kThreads), cols_lds(K, C, ny, true), s, K, nx, ny, C, spec,
+                           Filt, twy);
         kt_.stop();
     }
     MBMD_LAUNCHED();
     {
         KernelTimer kt_("k_fft_rows_inv", s);
-        hipLaunchKernelGGL(k_fft_rows_inv, dim3(ny), dim3(kThreads), sizeof(float2) * K * nx, s, K, nx, ny,
-                       ilog2(nx), spec, M, out_sign / (float)((double)nx * ny), out, g, partials, twx);
+        hipLaunchKernelGGL(k_fft_rows_inv, dim3(nblk), dim3(kThreads), rows_lds(K, RB, nx), s, K, nx, ny, RB, spec, M,
+                           out_sign / (float)((double)nx * ny), out, g, partials, twx);
         kt_.stop();
     }
     MBMD_LAUNCHED();
-    return ny;
+    return nblk;
 }
 
 void launch_spectrum_real_to_blocks(int K, int nj, int k_col, const float2* spec, float* blocks, hipStream_t s) {

@@ -16,6 +16,7 @@
 #include <cfloat>
 #include <cmath>
 
+#include "device_common.h"
 #include "internal.h"
 
 namespace mbmd {
@@ -24,25 +25,11 @@ namespace {
 
 constexpr int kThreads = 256;
 
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) sh[wv] = v;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0) {
-        const int nw = (blockDim.x + 63) >> 6;
-        for (int i = 0; i < nw; ++i) t += sh[i];
-    }
-    return t;
-}
+using dev::block_sum;
+using dev::huber_omega;
+using dev::Counts;
 
 __device__ __forceinline__ float huber_dpsi(float t, float d) { return fminf(fmaxf(t, -d), d); }
-__device__ __forceinline__ float huber_omega(float t, float d) {
-    const float a = fabsf(t);
-    return a <= d ? 1.0f : d / a;
-}
 __device__ __forceinline__ double huber_psi(double t, double d) {
     const double a = fabs(t);
     return a <= d ? 0.5 * t * t : d * a - 0.5 * d * d;
@@ -109,30 +96,8 @@ __global__ __launch_bounds__(kThreads) void k_penalty_quadform(PenaltyArgs a, co
                                                                const float* __restrict__ p,
                                                                double* __restrict__ partials) {
     __shared__ double sh[kThreads / 64];
-    const int nj = a.nx * a.ny;
     const int j = blockIdx.x * kThreads + threadIdx.x;
-    double acc = 0.0;
-    if (j < nj) {
-        const int iy = j / a.nx, ix = j - iy * a.nx;
-        const bool R = ix + 1 < a.nx, D = iy + 1 < a.ny;
-        if (a.kind == MBMD_PENALTY_HUBER) {
-            float s = 0.0f;
-            if (R) { const float dp = p[j] - p[j + 1]; s += huber_omega(x[j] - x[j + 1], a.delta) * dp * dp; }
-            if (D) { const float dp = p[j] - p[j + a.nx]; s += huber_omega(x[j] - x[j + a.nx], a.delta) * dp * dp; }
-            acc = (double)a.beta[0] * (double)s;
-        } else {
-            // sum over pairs of sum_kl beta_kl (p_k - p_k')(p_l - p_l') = p^T (beta (x) Gamma) p
-            for (int k = 0; k < a.K; ++k)
-                for (int l2 = 0; l2 < a.K; ++l2) {
-                    const float* pk = p + (size_t)k * nj;
-                    const float* pl = p + (size_t)l2 * nj;
-                    float s = 0.0f;
-                    if (R) s += (pk[j] - pk[j + 1]) * (pl[j] - pl[j + 1]);
-                    if (D) s += (pk[j] - pk[j + a.nx]) * (pl[j] - pl[j + a.nx]);
-                    acc += (double)a.beta[k * a.K + l2] * (double)s;
-                }
-        }
-    }
+    const double acc = j < a.nx * a.ny ? dev::penalty_quadform_at(a, x, p, j) : 0.0;
     const double tot = block_sum(acc, sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
@@ -347,45 +312,15 @@ __global__ void k_fill_double(int n, double* __restrict__ x, double value) {
     if (i < n) x[i] = value;
 }
 
-struct Counts {
-    int c[kRegions];
-};
 
-// Sums every region in a fixed order; mode bit 1: compute alpha.
-// Sums of the partial-sum regions and the scalars formed from them.  Two
-// wavefronts per region, each adding a strided half in a fixed order, then a
-// fixed combination: the result does not depend on timing.
-constexpr int kReduceThreads = 128 * kRegions;
-__global__ __launch_bounds__(kReduceThreads) void k_reduce_final(const double* __restrict__ partials,
-                                                                 Counts counts, double* __restrict__ scal,
-                                                                 double* __restrict__ trace_slot, int mode,
-                                                                 int* __restrict__ flags) {
+// Sums of the partial-sum regions and the scalars formed from them, in an
+// order fixed by the block size: the result does not depend on timing.
+__global__ __launch_bounds__(dev::kReduceThreads) void k_reduce_final(const double* __restrict__ partials,
+                                                                      Counts counts, double* __restrict__ scal,
+                                                                      double* __restrict__ trace_slot, int mode,
+                                                                      int* __restrict__ flags) {
     __shared__ double sh[2 * kRegions];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int r = wave >> 1, half = wave & 1;
-    double v = 0.0;
-    const double* pr = partials + (size_t)r * kMaxPartials;
-    for (int i = half * 64 + lane; i < counts.c[r]; i += 128) v += pr[i];
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if (lane == 0) sh[wave] = v;
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    double sums[kRegions];
-    for (int k = 0; k < kRegions; ++k) sums[k] = sh[2 * k] + sh[2 * k + 1];
-    const double phi = sums[R_PHI_L] + sums[R_PHI_R];
-    scal[S_PHI] = phi;
-    if (trace_slot) *trace_slot = phi;
-    bool bad = !isfinite(phi);
-    if (mode & 1) {
-        const double gp = sums[R_GP];
-        const double den = sums[R_CQ2] + sums[R_PRP];
-        const double alpha = den > 0.0 ? -gp / den : 0.0;
-        scal[S_GP] = gp;
-        scal[S_DEN] = den;
-        scal[S_ALPHA] = isfinite(alpha) ? alpha : 0.0;
-        bad = bad || !isfinite(alpha);
-    }
-    if (bad && flags) flags[0] = 1;
+    dev::final_reduce(partials, counts, scal, trace_slot, mode, flags, sh);
 }
 
 int nblk(int n) { return (n + kThreads - 1) / kThreads; }
@@ -550,7 +485,7 @@ void launch_reduce_final(double* partials, const int* counts, double* scal, doub
     }
     {
         KernelTimer kt_("k_reduce_final", s);
-        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kReduceThreads), 0, s, partials, c, scal, trace_slot,
+        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(dev::kReduceThreads), 0, s, partials, c, scal, trace_slot,
                            mode, flags);
         kt_.stop();
     }

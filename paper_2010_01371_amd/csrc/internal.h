@@ -224,10 +224,20 @@ struct RayArgs {
     const float *Q, *S, *rowS, *Qsum;    // device spectral model
     const float *y, *w, *gammaA;         // [C][ni], [C][ni], [ni] (NULL gammaA = 1)
 };
+struct PenaltyArgs {
+    int K, nx, ny, kind;
+    const float* beta;     // device [K][K]
+    float delta;
+};
 int launch_ray_grad(const RayArgs& a, const float* l, float* u, float* v, float* r,
                     double* phi_partials, hipStream_t s);
 int launch_ray_curv(const RayArgs& a, const float* l, const float* r, const float* q,
                     double* partials, hipStream_t s);
+// Curvature along the direction in one launch: the rays' c q^2 into region CQ2
+// and, with pen, the penalty's p^T R''(x) p into region PRP of partials (the
+// base of all regions); sets counts[R_CQ2] and counts[R_PRP].
+void launch_curvature(const RayArgs& a, const float* l, const float* r, const float* q, const PenaltyArgs* pen,
+                      const float* x, const float* p, double* partials, int* counts, hipStream_t s);
 void launch_forward_model(const RayArgs& a, const float* l, float* ybar, hipStream_t s);
 void launch_forward_vjp(const RayArgs& a, const float* l, const float* gbar, float* sk, hipStream_t s);
 void launch_fisher(const RayArgs& a, float* W, hipStream_t s);
@@ -236,11 +246,6 @@ int launch_identity_iterate(const RayArgs& a, float* x, const float* M0, int pre
                             double* partials_per_iter, int stride, hipStream_t s);
 
 // ---------------------------------------------------------------- image passes
-struct PenaltyArgs {
-    int K, nx, ny, kind;
-    const float* beta;     // device [K][K]
-    float delta;
-};
 int launch_penalty_grad(const PenaltyArgs& a, const float* x, const float* gL, const float* dL,
                         float* g, float* d, double* phi_partials, hipStream_t s, const float* gL2 = nullptr);
 int launch_penalty_quadform(const PenaltyArgs& a, const float* x, const float* p, double* partials,
