@@ -61,17 +61,14 @@ struct Counts {
     int c[kRegions];
 };
 
-// Threads of the final reduction: two wavefronts per region.
+// Threads of a block that sums the regions: two wavefronts per region.
 constexpr int kReduceThreads = 128 * kRegions;
 
 // Sums every partial-sum region (region r at partials + r kMaxPartials, counts.c[r]
-// entries) -- two wavefronts per region, each lane adding a strided share with
-// eight loads in flight, in a fixed order -- and forms the scalars:
-// phi = PHI_L + PHI_R, and with mode bit 1 the step alpha = -GP / (CQ2 + PRP).
-// A non-finite phi or alpha raises flags[0].  Block of kReduceThreads threads;
-// sh: 2 kRegions doubles of shared memory.
-__device__ __forceinline__ void final_reduce(const double* partials, const Counts& counts, double* scal,
-                                             double* trace_slot, int mode, int* flags, double* sh) {
+// entries): two wavefronts per region, each lane adding a strided share with
+// eight loads in flight, in a fixed order.  Block of kReduceThreads threads; on
+// return (after a barrier) region r's sum is sh[2 r] + sh[2 r + 1].
+__device__ __forceinline__ void region_sums(const double* partials, const Counts& counts, double* sh) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r = wave >> 1, t = (wave & 1) * 64 + lane;
     const double* pr = partials + (size_t)r * kMaxPartials;
@@ -86,23 +83,38 @@ __device__ __forceinline__ void final_reduce(const double* partials, const Count
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     if (lane == 0) sh[wave] = v;
     __syncthreads();
-    if (threadIdx.x != 0) return;
+}
+
+// The scalars formed from the region sums (sh as left by region_sums):
+// phi = PHI_L + PHI_R and, with mode bit 1, the step alpha = -GP / (CQ2 + PRP)
+// (0 when the denominator is not positive or alpha is not finite).  With write,
+// stores them to scal (and phi to trace_slot) and raises flags[0] when phi or
+// alpha is not finite.  Returns alpha (0 without mode bit 1).
+__device__ __forceinline__ double form_scalars(const double* sh, int mode, double* scal, double* trace_slot,
+                                               int* flags, bool write) {
     double sums[kRegions];
     for (int k = 0; k < kRegions; ++k) sums[k] = sh[2 * k] + sh[2 * k + 1];
     const double phi = sums[R_PHI_L] + sums[R_PHI_R];
-    scal[S_PHI] = phi;
-    if (trace_slot) *trace_slot = phi;
     bool bad = !isfinite(phi);
+    double alpha_out = 0.0;
     if (mode & 1) {
         const double gp = sums[R_GP];
         const double den = sums[R_CQ2] + sums[R_PRP];
         const double alpha = den > 0.0 ? -gp / den : 0.0;
-        scal[S_GP] = gp;
-        scal[S_DEN] = den;
-        scal[S_ALPHA] = isfinite(alpha) ? alpha : 0.0;
+        alpha_out = isfinite(alpha) ? alpha : 0.0;
         bad = bad || !isfinite(alpha);
+        if (write) {
+            scal[S_GP] = gp;
+            scal[S_DEN] = den;
+            scal[S_ALPHA] = alpha_out;
+        }
     }
-    if (bad && flags) flags[0] = 1;
+    if (write) {
+        scal[S_PHI] = phi;
+        if (trace_slot) *trace_slot = phi;
+        if (bad && flags) flags[0] = 1;
+    }
+    return alpha_out;
 }
 
 }  // namespace dev

@@ -14,6 +14,7 @@
 //     used by the pixel-driven back projector to find the bins a pixel sees,
 //     and per sweep line its restriction to that line with the factor that
 //     turns a residual of the map into the fraction of the bin.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -190,13 +191,46 @@ void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int b
     t.n_frame_views[0] = (int)views[0].size();
     t.n_frame_views[1] = (int)views[1].size();
 
+    // Forward items of each frame in order of decreasing work: the active lines
+    // of the item's half, summed over its wavefronts, from the same hull the
+    // kernel computes.  Dispatching the heaviest first balances the CUs (the
+    // fan is usually wider than the image, so many items have no lines at all).
+    std::vector<int> order;
+    {
+        const int chunks = fwd_chunks(B);
+        for (int f = 0; f < 2; ++f) {
+            const int nv = (int)views[f].size(), slot0 = f ? (int)views[0].size() : 0;
+            const int Nq = f ? g.nx : g.ny, Np = f ? g.ny : g.nx;
+            std::vector<std::pair<long long, int>> w;
+            w.reserve((size_t)nv * chunks * 2);
+            for (int sl = 0; sl < nv; ++sl)
+                for (int c = 0; c < chunks; ++c)
+                    for (int h = 0; h < 2; ++h) {
+                        long long work = 0;
+                        const float2* brow = &bound[(size_t)(slot0 + sl) * (B + 1)];
+                        for (int wv = 0; wv < kFwdWaves; ++wv) {
+                            const int e0 = (c * kFwdWaves + wv) * kFwdBinsPerWave;
+                            if (e0 >= B) break;
+                            int lo = 0, hi = -1;
+                            active_lines(brow[e0], brow[std::min(e0 + kFwdBinsPerWave, B)], Np, Nq, lo, hi);
+                            const int mid = (lo + hi + 1) >> 1;
+                            work += std::max(0, h ? hi - mid + 1 : mid - lo);
+                        }
+                        w.emplace_back(work, (sl * chunks + c) * 2 + h);
+                    }
+            std::stable_sort(w.begin(), w.end(), [](const std::pair<long long, int>& a,
+                                                    const std::pair<long long, int>& b) { return a.first > b.first; });
+            for (const auto& e : w) order.push_back(e.second);
+        }
+    }
+
     const size_t nj = (size_t)g.nx * g.ny;
     t.prefix_mat = prefix_mat;
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
     const size_t b_view = al(sizeof(ViewParams) * V), b_bound = al(sizeof(float2) * bound.size()),
                  b_path = al(sizeof(float) * path.size()), b_fv = al(sizeof(int) * V),
                  b_pre = al(sizeof(float) * prefix_elems(g.nx, g.ny) * prefix_mat),
-                 b_line = al(sizeof(float4) * line.size()),
+                 b_line = al(sizeof(float4) * line.size()), b_ord = al(sizeof(int) * order.size()),
                  b_det = al(sizeof(DetEntry) * (size_t)back_ch * V * det_row(B)),
                  b_tmp = al(sizeof(float) * (size_t)back_ch * nj);
     t.back_ch = back_ch;
@@ -204,7 +238,7 @@ void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int b
     MBMD_HIP(hipGetDevice(&t.device));
     // the back projector addresses the detector prefix with 32-bit buffer offsets
     MBMD_REQUIRE(b_det < (size_t(1) << 31), MBMD_ERR_SHAPE, "too many views x bins x channels for a back projection");
-    MBMD_HIP(hipMalloc(&base, b_view + b_bound + b_path + b_fv + b_pre + b_line + b_det + b_tmp));
+    MBMD_HIP(hipMalloc(&base, b_view + b_bound + b_path + b_fv + b_pre + b_line + b_ord + b_det + b_tmp));
     t.mem = base;
     t.view = reinterpret_cast<ViewParams*>(base);
     t.bound = reinterpret_cast<float2*>(base + b_view);
@@ -213,7 +247,8 @@ void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int b
     t.prefix = prefix_mat ? reinterpret_cast<float*>(base + b_view + b_bound + b_path + b_fv) : nullptr;
     t.back_line = reinterpret_cast<float4*>(base + b_view + b_bound + b_path + b_fv + b_pre);
     t.back_line_q = QL;
-    char* after_pre = base + b_view + b_bound + b_path + b_fv + b_pre + b_line;
+    t.fwd_order = reinterpret_cast<int*>(base + b_view + b_bound + b_path + b_fv + b_pre + b_line);
+    char* after_pre = base + b_view + b_bound + b_path + b_fv + b_pre + b_line + b_ord;
     t.det_prefix = back_ch ? reinterpret_cast<DetEntry*>(after_pre) : nullptr;
     t.back_part = back_ch ? reinterpret_cast<float*>(after_pre + b_det) : nullptr;
     MBMD_HIP(hipMemcpy(t.view, vp.data(), sizeof(ViewParams) * V, hipMemcpyHostToDevice));
@@ -221,6 +256,7 @@ void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int b
     MBMD_HIP(hipMemcpy(t.path, path.data(), sizeof(float) * path.size(), hipMemcpyHostToDevice));
     MBMD_HIP(hipMemcpy(t.frame_views, fv.data(), sizeof(int) * V, hipMemcpyHostToDevice));
     MBMD_HIP(hipMemcpy(t.back_line, line.data(), sizeof(float4) * line.size(), hipMemcpyHostToDevice));
+    MBMD_HIP(hipMemcpy(t.fwd_order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice));
 }
 
 void free_geometry(GeomTables& t) {

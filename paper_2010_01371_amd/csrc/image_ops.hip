@@ -320,7 +320,8 @@ __global__ __launch_bounds__(dev::kReduceThreads) void k_reduce_final(const doub
                                                                       double* __restrict__ trace_slot, int mode,
                                                                       int* __restrict__ flags) {
     __shared__ double sh[2 * kRegions];
-    dev::final_reduce(partials, counts, scal, trace_slot, mode, flags, sh);
+    dev::region_sums(partials, counts, sh);
+    if (threadIdx.x == 0) dev::form_scalars(sh, mode, scal, trace_slot, flags, true);
 }
 
 int nblk(int n) { return (n + kThreads - 1) / kThreads; }

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstddef>
 #include <cstdint>
 #include <string>
@@ -114,6 +115,9 @@ struct GeomTables {
     // position X0 + X1 q, in pixels from the line's first pixel edge; stored in
     // increasing X (boundary B - b' at entry b' for views with orient < 0)
     float2* bound = nullptr;
+    // [frame 0 items][frame 1 items]: forward items of each frame in order of
+    // decreasing work (active lines), so the heaviest blocks are dispatched first
+    int* fwd_order = nullptr;
     float* path = nullptr;           // [slot][B]: path length per sweep line of the bin-centre ray
     int* frame_views = nullptr;      // [slot] -> view index
     // scratch: line prefix sums F[k] = sum_{p<k} img[p] for k < Np and the line total
@@ -147,6 +151,56 @@ __host__ __device__ inline int prefix_row(int Np) { return (Np + 4 + 3) & ~3; }
 // symmetric range [-back_shift(B), back_shift(B)] around the detector centre
 // (shifted by back_shift(B)) always lands inside the row.
 __host__ __device__ inline int det_row(int B) { return B + 2; }
+
+// Forward projection tiling: wavefronts of two bin boundaries per lane (127 bins),
+// blocks of kFwdWaves such wavefronts along the detector ("chunks"), and each
+// block's active lines split into two halves.  Items of a frame are
+// (slot in frame, chunk, half), numbered ((slot chunks) + chunk) 2 + half.  One
+// wavefront per block lets the dispatcher balance the CUs wavefront by wavefront
+// (the work per wavefront ranges from no lines to every line).
+constexpr int kFwdBinsPerWave = 127;
+constexpr int kFwdWaves = 1;
+__host__ __device__ inline int fwd_chunks(int B) { return (B + kFwdWaves * kFwdBinsPerWave - 1) / (kFwdWaves * kFwdBinsPerWave); }
+
+// Lines q in [0, Nq) are active unless the first and the last boundary of a
+// wavefront (positions X = x0 + x1 q, affine in q) both lie at least a margin
+// beyond the same end of the line; the inactive lines form at most two
+// intervals, and [q_lo, q_hi] is the hull of what remains (empty: q_lo > q_hi).
+// FP64 with a margin of 1/64 pixel, far above the FP32 error of the positions
+// the line loop evaluates, so no line with a nonzero contribution is dropped.
+__host__ __device__ inline void active_lines(float2 bf, float2 bl, int Np, int Nq, int& q_lo, int& q_hi) {
+    const double m = 1.0 / 64.0, last = (double)(Nq - 1);
+    // {q in [0, last] : a + b q <= c} as [lo, hi]
+    auto half = [&](double a, double b, double c, double& lo, double& hi) {
+        lo = 0.0;
+        hi = last;
+        if (b == 0.0) {
+            if (a > c) lo = 1.0, hi = 0.0;
+        } else if (b > 0.0) {
+            hi = fmin(last, floor((c - a) / b));
+        } else {
+            lo = fmax(0.0, ceil((c - a) / b));
+        }
+    };
+    double lo1a, hi1a, lo1b, hi1b, lo2a, hi2a, lo2b, hi2b;
+    half(bf.x, bf.y, -m, lo1a, hi1a);                              // first boundary left of the line
+    half(bl.x, bl.y, -m, lo1b, hi1b);                              // last boundary left of the line
+    half(-(double)bf.x, -(double)bf.y, -((double)Np + m), lo2a, hi2a);   // first right of it
+    half(-(double)bl.x, -(double)bl.y, -((double)Np + m), lo2b, hi2b);   // last right of it
+    const double i1lo = fmax(lo1a, lo1b), i1hi = fmin(hi1a, hi1b);
+    const double i2lo = fmax(lo2a, lo2b), i2hi = fmin(hi2a, hi2b);
+    double a = 0.0, b = last;
+    for (int r = 0; r < 2; ++r) {                                  // strip inactive runs at both ends
+        if (i1lo <= i1hi && i1lo <= a && a <= i1hi) a = i1hi + 1.0;
+        if (i2lo <= i2hi && i2lo <= a && a <= i2hi) a = i2hi + 1.0;
+        if (i1lo <= i1hi && i1lo <= b && b <= i1hi) b = i1lo - 1.0;
+        if (i2lo <= i2hi && i2lo <= b && b <= i2hi) b = i2lo - 1.0;
+    }
+    q_lo = (int)a;
+    q_hi = (int)b;
+}
+
+
 __host__ __device__ inline int back_shift(int B) { return (B + 1) / 2; }
 inline size_t prefix_elems(int nx, int ny) { return (size_t)ny * prefix_row(nx) + (size_t)nx * prefix_row(ny); }
 

@@ -56,7 +56,6 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kPerWave = 63;                 // pixels per wavefront (back projection)
-constexpr int kFwdBinsPerWave = 127;         // bins per wavefront (forward: two boundaries per lane)
 constexpr int kScanThreads = 256;
 constexpr int kBufferWord3 = 0x00020000;     // raw buffer resource, gfx9 family
 
@@ -105,7 +104,12 @@ __device__ __forceinline__ void keep(float v) { asm volatile("" ::"v"(v)); }
 // caller's grid.
 __global__ __launch_bounds__(kScanThreads) void k_line_prefix(const float* __restrict__ img,
                                                                float* __restrict__ rows, float* __restrict__ cols,
-                                                               int nx, int ny, int line0) {
+                                                               int nx, int ny, int line0,
+                                                               float* __restrict__ zero_out, int zero_n) {
+    // side job: clear the projection's output, which the forward adds into
+    for (int i = (blockIdx.y * gridDim.x + blockIdx.x) * kScanThreads + threadIdx.x; i < zero_n;
+         i += gridDim.x * gridDim.y * kScanThreads)
+        zero_out[i] = 0.0f;
     const int line = line0 + blockIdx.x;
     const int m = blockIdx.y;
     const int frame = line >= ny ? 1 : 0;
@@ -207,59 +211,24 @@ __device__ __forceinline__ bool decode_block(const FrameSplit& fs, int& frame, i
     return item < (frame ? fs.n_items[1] : fs.n_items[0]);   // no dynamic index into the by-value array
 }
 
-// Lines q in [0, Nq) are active unless the first and the last boundary of a
-// wavefront (positions X = x0 + x1 q, affine in q) both lie at least a margin
-// beyond the same end of the line; the inactive lines form at most two
-// intervals, and [q_lo, q_hi] is the hull of what remains (empty: q_lo > q_hi).
-// FP64 with a margin of 1/64 pixel, far above the FP32 error of the positions
-// the line loop evaluates, so no line with a nonzero contribution is dropped.
-__device__ __forceinline__ void active_lines(float2 bf, float2 bl, int Np, int Nq, int& q_lo, int& q_hi) {
-    const double m = 1.0 / 64.0, last = (double)(Nq - 1);
-    // {q in [0, last] : a + b q <= c} as [lo, hi]
-    auto half = [&](double a, double b, double c, double& lo, double& hi) {
-        lo = 0.0;
-        hi = last;
-        if (b == 0.0) {
-            if (a > c) lo = 1.0, hi = 0.0;
-        } else if (b > 0.0) {
-            hi = fmin(last, floor((c - a) / b));
-        } else {
-            lo = fmax(0.0, ceil((c - a) / b));
-        }
-    };
-    double lo1a, hi1a, lo1b, hi1b, lo2a, hi2a, lo2b, hi2b;
-    half(bf.x, bf.y, -m, lo1a, hi1a);                              // first boundary left of the line
-    half(bl.x, bl.y, -m, lo1b, hi1b);                              // last boundary left of the line
-    half(-(double)bf.x, -(double)bf.y, -((double)Np + m), lo2a, hi2a);   // first right of it
-    half(-(double)bl.x, -(double)bl.y, -((double)Np + m), lo2b, hi2b);   // last right of it
-    const double i1lo = fmax(lo1a, lo1b), i1hi = fmin(hi1a, hi1b);
-    const double i2lo = fmax(lo2a, lo2b), i2hi = fmin(hi2a, hi2b);
-    double a = 0.0, b = last;
-    for (int r = 0; r < 2; ++r) {                                  // strip inactive runs at both ends
-        if (i1lo <= i1hi && i1lo <= a && a <= i1hi) a = i1hi + 1.0;
-        if (i2lo <= i2hi && i2lo <= a && a <= i2hi) a = i2hi + 1.0;
-        if (i1lo <= i1hi && i1lo <= b && b <= i1hi) b = i1lo - 1.0;
-        if (i2lo <= i2hi && i2lo <= b && b <= i2hi) b = i2lo - 1.0;
-    }
-    q_lo = (int)a;
-    q_hi = (int)b;
-}
-
 template <int NK>
-__global__ __launch_bounds__(kThreads) void k_dd_forward(const ViewParams* __restrict__ view,
+__global__ __launch_bounds__(kFwdWaves * 64) void k_dd_forward(const ViewParams* __restrict__ view,
                                                          const float2* __restrict__ bound,
                                                          const float* __restrict__ path,
                                                          const float* __restrict__ pre_rows,
                                                          const float* __restrict__ pre_cols, int nv0,
-                                                         FrameSplit fs, int chunks, int nx, int ny, int V, int B,
-                                                         float* __restrict__ sino) {
+                                                         FrameSplit fs, const int* __restrict__ order, int chunks,
+                                                         int nx, int ny, int V, int B, float* __restrict__ sino) {
     int frame, item;
     if (!decode_block(fs, frame, item)) return;
+    item = order[(frame ? fs.n_items[0] : 0) + item];             // heaviest items first
+    const int half = item & 1;                                    // which half of the active lines
+    item >>= 1;
     const int slot = (frame ? nv0 : 0) + item / chunks;
     const int chunk = item % chunks;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int e0 = (chunk * kWaves + wave) * kFwdBinsPerWave;     // first boundary of the wavefront
+    const int e0 = (chunk * kFwdWaves + wave) * kFwdBinsPerWave;  // first boundary of the wavefront
     if (e0 >= B) return;                                          // whole wavefront: no bins
     const int Nq = frame ? nx : ny;
     const int Np = frame ? ny : nx;
@@ -278,6 +247,15 @@ __global__ __launch_bounds__(kThreads) void k_dd_forward(const ViewParams* __res
     // line, F is equal across lanes and the differences are exactly zero.
     int q_lo = 0, q_hi = -1;
     active_lines(brow[e0], brow[min(e0 + kFwdBinsPerWave, B)], Np, Nq, q_lo, q_hi);
+    // Two wavefronts share these lines, one half each, and add their sums into
+    // the cleared output: the heavy wavefronts (bins that cross the image on
+    // every line) are then twice as many and half as long.  Two additions onto
+    // zero give the same result in either order.
+    {
+        const int q_mid = (q_lo + q_hi + 1) >> 1;
+        if (half) q_lo = q_mid;
+        else q_hi = q_mid - 1;
+    }
     // The in-lane bin width is affine in q, so its largest value over the active
     // lines is at an end: at most two pixels everywhere means X_b lies in the
     // four-entry window that starts at floor(X_a).
@@ -355,13 +333,13 @@ __global__ __launch_bounds__(kThreads) void k_dd_forward(const ViewParams* __res
         const int o = rev ? B - 1 - bin_a : bin_a;
         const float L = path[(size_t)slot * B + o];
 #pragma unroll
-        for (int m = 0; m < NK; ++m) sino[((size_t)m * V + v) * B + o] = acc_a[m] * L;
+        for (int m = 0; m < NK; ++m) unsafeAtomicAdd(&sino[((size_t)m * V + v) * B + o], acc_a[m] * L);
     }
     if (lane < 63 && bin_b < B && bin_b < e0 + kFwdBinsPerWave) {
         const int o = rev ? B - 1 - bin_b : bin_b;
         const float L = path[(size_t)slot * B + o];
 #pragma unroll
-        for (int m = 0; m < NK; ++m) sino[((size_t)m * V + v) * B + o] = acc_b[m] * L;
+        for (int m = 0; m < NK; ++m) unsafeAtomicAdd(&sino[((size_t)m * V + v) * B + o], acc_b[m] * L);
     }
 }
 
@@ -521,14 +499,14 @@ int grid_blocks(const FrameSplit& fs) {
 
 template <int NK>
 void fwd_launch(const GeomTables& t, float* sino, hipStream_t s) {
-    const int chunks = (t.B + kWaves * kFwdBinsPerWave - 1) / (kWaves * kFwdBinsPerWave);
-    const FrameSplit fs = split(t.n_frame_views[0] * chunks, t.n_frame_views[1] * chunks);
+    const int chunks = fwd_chunks(t.B);
+    const FrameSplit fs = split(t.n_frame_views[0] * chunks * 2, t.n_frame_views[1] * chunks * 2);   // two halves
     const float* rows = t.prefix;
     const float* cols = t.prefix + (size_t)t.prefix_mat * t.ny * prefix_row(t.nx);
     {
         KernelTimer kt_("k_dd_forward", s);
-        hipLaunchKernelGGL(k_dd_forward<NK>, dim3(grid_blocks(fs)), dim3(kThreads), 0, s, t.view, t.bound,
-                           t.path, rows, cols, t.n_frame_views[0], fs, chunks, t.nx, t.ny, t.V, t.B, sino);
+        hipLaunchKernelGGL(k_dd_forward<NK>, dim3(grid_blocks(fs)), dim3(kFwdWaves * 64), 0, s, t.view, t.bound,
+                           t.path, rows, cols, t.n_frame_views[0], fs, t.fwd_order, chunks, t.nx, t.ny, t.V, t.B, sino);
         kt_.stop();
     }
     MBMD_LAUNCHED();
@@ -721,7 +699,7 @@ void launch_project(const GeomTables& t, const float* x, float* sino, int n_mat,
         float* cols = t.prefix + (size_t)t.prefix_mat * t.ny * prefix_row(t.nx);
         KernelTimer kt_("k_line_prefix", s);
         hipLaunchKernelGGL(k_line_prefix, dim3(line1 - line0, n_mat), dim3(kScanThreads), 0, s, x, t.prefix, cols,
-                           t.nx, t.ny, line0);
+                           t.nx, t.ny, line0, sino, n_mat * t.V * t.B);
         kt_.stop();
     }
     MBMD_LAUNCHED();
