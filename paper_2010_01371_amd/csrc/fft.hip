@@ -91,8 +91,8 @@ __host__ __device__ inline int fft_threads(int N) { return N >= 8 ? N / 8 : 1; }
 // in the first, 64 apart in groups of 8 in the second) at most 2-way bank
 // conflicted; a transform of length N takes lds_len(N) slots, an odd number, so
 // that the same element of neighbouring transforms falls in different banks.
-__host__ __device__ inline int pad(int i) { return i + (i >> 3); }
-__host__ __device__ inline int lds_len(int N) { return (N + (N >> 3)) | 1; }
+__host__ __device__ constexpr int pad(int i) { return i + (i >> 3); }
+__host__ __device__ constexpr int lds_len(int N) { return (N + (N >> 3)) | 1; }
 
 // One Stockham pass of radix R over a length-N transform held in LDS (buf),
 // after Ns points have been combined: butterfly j reads buf[j + r N/R],
@@ -159,6 +159,66 @@ __device__ __forceinline__ void fft_lds(float2* buf, int N, int t, int T, bool a
     }
 }
 
+// The same transform with N (and so the pass sequence, the thread count N/8 and
+// every LDS offset) fixed at compile time.
+template <bool INV, int R, int N, int NS>
+__device__ __forceinline__ void stockham_pass_ct(float2* buf, int t, bool active, const float2* __restrict__ tw) {
+    constexpr int T = N >= 8 ? N / 8 : 1;
+    constexpr int NB = 8 / R;
+    constexpr int nbf = N / R;
+    constexpr int step = N / (NS * R);
+    float2 v[NB][R];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int j = t + b * T;
+        if (active && j < nbf) {
+            const int k = j & (NS - 1);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                v[b][r] = buf[pad(j + r * nbf)];
+                if (r > 0 && NS > 1) {
+                    float2 w = tw[r * k * step];
+                    if (INV) w.y = -w.y;
+                    v[b][r] = cmul(v[b][r], w);
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int j = t + b * T;
+        if (active && j < nbf) {
+            dftR<INV, R>(v[b]);
+            const int k = j & (NS - 1);
+            const int d = (j - k) * R + k;
+#pragma unroll
+            for (int q = 0; q < R; ++q) buf[pad(d + q * NS)] = v[b][q];
+        }
+    }
+    __syncthreads();
+}
+
+template <bool INV, int N, int NS>
+__device__ __forceinline__ void fft_passes_ct(float2* buf, int t, bool active, const float2* __restrict__ tw) {
+    if constexpr (NS < N) {
+        constexpr int rem = N / NS;
+        constexpr int R = rem % 8 == 0 ? 8 : rem;            // radix 8, then the last 4 or 2
+        stockham_pass_ct<INV, R, N, NS>(buf, t, active, tw);
+        fft_passes_ct<INV, N, NS * R>(buf, t, active, tw);
+    }
+}
+
+// Transform of length NT (compile time) or N (run time, NT = 0).
+template <bool INV, int NT>
+__device__ __forceinline__ void fft_any(float2* buf, int N, int t, int T, bool active, const float2* __restrict__ tw) {
+    if constexpr (NT > 0) {
+        fft_passes_ct<INV, NT, 1>(buf, t, active, tw);
+    } else {
+        fft_lds<INV>(buf, N, t, T, active, tw);
+    }
+}
+
 __device__ __forceinline__ double block_sum(double v, double* sh) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -174,12 +234,14 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 // RB rows per block: transform (rr, k) of row y0 + rr lives at buf[(rr K + k) nx].
-__global__ __launch_bounds__(kThreads) void k_fft_rows_fwd(int K, int nx, int ny, int RB,
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_fft_rows_fwd(int K, int nx_rt, int ny, int RB,
                                                            const float* __restrict__ in,
                                                            const float* __restrict__ M, int sy, int sx,
                                                            float2* __restrict__ spec,
                                                            const float2* __restrict__ tw) {
     extern __shared__ float2 buf[];
+    const int nx = NT ? NT : nx_rt;                        // transform length (a constant when NT > 0)
     const int PN = lds_len(nx);
     float2* twl = buf + (size_t)RB * K * PN;               // twiddle table staged in LDS
     const int y0 = blockIdx.x * RB;
@@ -210,7 +272,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_rows_fwd(int K, int nx, int ny
     const int T = fft_threads(nx);
     const int tr = threadIdx.x / T;                        // transform index rr K + k
     const bool active = tr < RB * K && y0 + tr / K < ny;
-    fft_lds<false>(buf + (size_t)(active ? tr : 0) * PN, nx, threadIdx.x - tr * T, T, active, twl);
+    fft_any<false, NT>(buf + (size_t)(active ? tr : 0) * PN, nx, threadIdx.x - tr * T, T, active, twl);
     for (int idx = threadIdx.x; idx < RB * K * nx; idx += blockDim.x) {
         const int trn = idx >> lx, xx = idx & (nx - 1);
         const int rr = trn / K, k = trn - rr * K;
@@ -223,10 +285,12 @@ __global__ __launch_bounds__(kThreads) void k_fft_rows_fwd(int K, int nx, int ny
 // reads of the block (spectrum, twiddles, filter) are issued in batches before
 // any is waited for.
 constexpr int kBatch = 8;
-__global__ __launch_bounds__(kThreads) void k_fft_cols(int K, int nx, int ny, int C, float2* __restrict__ spec,
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_fft_cols(int K, int nx, int ny_rt, int C, float2* __restrict__ spec,
                                                        const float* __restrict__ filt,
                                                        const float2* __restrict__ tw) {
     extern __shared__ float2 buf[];
+    const int ny = NT ? NT : ny_rt;                        // transform length (a constant when NT > 0)
     const int PN = lds_len(ny);
     float2* twl = buf + (size_t)K * C * PN;                // twiddle table staged in LDS
     float* fl = reinterpret_cast<float*>(twl + ny);        // filter blocks staged in LDS
@@ -268,7 +332,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(int K, int nx, int ny, in
     const bool active = tr < C * K;
     float2* mine = buf + (size_t)(active ? tr : 0) * PN;
     const int t = threadIdx.x - tr * T;
-    fft_lds<false>(mine, ny, t, T, active, twl);
+    fft_any<false, NT>(mine, ny, t, T, active, twl);
     if (filt) {
         for (int idx = threadIdx.x; idx < C * ny; idx += kThreads) {
             const int c = idx & (C - 1), yy = idx >> lc;
@@ -290,7 +354,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(int K, int nx, int ny, in
             }
         }
         __syncthreads();
-        fft_lds<true>(mine, ny, t, T, active, twl);
+        fft_any<true, NT>(mine, ny, t, T, active, twl);
     }
     for (int idx = threadIdx.x; idx < tot; idx += kThreads) {
         const int c = idx & (C - 1);
@@ -300,7 +364,8 @@ __global__ __launch_bounds__(kThreads) void k_fft_cols(int K, int nx, int ny, in
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_fft_rows_inv(int K, int nx, int ny, int RB,
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_fft_rows_inv(int K, int nx_rt, int ny, int RB,
                                                            const float2* __restrict__ spec,
                                                            const float* __restrict__ M, float scale,
                                                            float* __restrict__ out,
@@ -309,6 +374,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_rows_inv(int K, int nx, int ny
                                                            const float2* __restrict__ tw) {
     extern __shared__ float2 buf[];
     __shared__ double sh[kThreads / 64];
+    const int nx = NT ? NT : nx_rt;                        // transform length (a constant when NT > 0)
     const int PN = lds_len(nx);
     float2* twl = buf + (size_t)RB * K * PN;               // twiddle table staged in LDS
     const int y0 = blockIdx.x * RB;
@@ -324,7 +390,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_rows_inv(int K, int nx, int ny
     const int T = fft_threads(nx);
     const int tr = threadIdx.x / T;
     const bool active = tr < RB * K && y0 + tr / K < ny;
-    fft_lds<true>(buf + (size_t)(active ? tr : 0) * PN, nx, threadIdx.x - tr * T, T, active, twl);
+    fft_any<true, NT>(buf + (size_t)(active ? tr : 0) * PN, nx, threadIdx.x - tr * T, T, active, twl);
     double dot = 0.0;
     for (int idx = threadIdx.x; idx < RB * nx; idx += blockDim.x) {
         const int rr = idx >> lx, xx = idx & (nx - 1);
@@ -394,6 +460,20 @@ void check_sizes(int K, int nx, int ny) {
                  MBMD_ERR_SHAPE, "image too large for the LDS-resident FFT");
 }
 
+// Transform lengths compiled as constants (the pass sequence and the LDS
+// offsets fold into immediates); other powers of two take the general form.
+#define MBMD_FFT_DISPATCH(N, LAUNCH)                  \
+    do {                                              \
+        switch (N) {                                  \
+            case 64: LAUNCH(64); break;               \
+            case 128: LAUNCH(128); break;             \
+            case 256: LAUNCH(256); break;             \
+            case 512: LAUNCH(512); break;             \
+            case 1024: LAUNCH(1024); break;           \
+            default: LAUNCH(0); break;                \
+        }                                             \
+    } while (0)
+
 }  // namespace
 
 void fill_twiddles(float2* tw, int n, hipStream_t s) {
@@ -412,16 +492,20 @@ void launch_fft2_forward(int K, int nx, int ny, const float* in, const float* M,
     const int RB = rows_per_block(K, nx, ny);
     {
         KernelTimer kt_("k_fft_rows_fwd", s);
-        hipLaunchKernelGGL(k_fft_rows_fwd, dim3((ny + RB - 1) / RB), dim3(kThreads),
-                           rows_lds(K, RB, nx), s, K, nx, ny, RB, in, M, sy, sx, spec, twx);
+#define L_(NT) hipLaunchKernelGGL((k_fft_rows_fwd<NT>), dim3((ny + RB - 1) / RB), dim3(kThreads), rows_lds(K, RB, nx), \
+                               s, K, nx, ny, RB, in, M, sy, sx, spec, twx)
+        MBMD_FFT_DISPATCH(nx, L_);
+#undef L_
         kt_.stop();
     }
     MBMD_LAUNCHED();
     const int C = col_group(K, nx, ny);
     {
         KernelTimer kt_("k_fft_cols", s);
-        hipLaunchKernelGGL(k_fft_cols, dim3(nx / C), dim3(kThreads), cols_lds(K, C, ny, false), s, K, nx, ny, C, spec,
-                           (const float*)nullptr, twy);
+#define L_(NT) hipLaunchKernelGGL((k_fft_cols<NT>), dim3(nx / C), dim3(kThreads), cols_lds(K, C, ny, false), s, K, nx, \
+                               ny, C, spec, (const float*)nullptr, twy)
+        MBMD_FFT_DISPATCH(ny, L_);
+#undef L_
         kt_.stop();
     }
     MBMD_LAUNCHED();
@@ -436,8 +520,10 @@ int launch_fourier_apply(int K, int nx, int ny, const float* in, const float* M,
     MBMD_REQUIRE(nblk <= kMaxPartials, MBMD_ERR_SHAPE, "too many rows for the partial-sum buffer");
     {
         KernelTimer kt_("k_fft_rows_fwd", s);
-        hipLaunchKernelGGL(k_fft_rows_fwd, dim3(nblk), dim3(kThreads), rows_lds(K, RB, nx), s, K, nx, ny, RB, in, M,
-                           0, 0, spec, twx);
+#define L_(NT) hipLaunchKernelGGL((k_fft_rows_fwd<NT>), dim3(nblk), dim3(kThreads), rows_lds(K, RB, nx), s, K, nx, ny, \
+                               RB, in, M, 0, 0, spec, twx)
+        MBMD_FFT_DISPATCH(nx, L_);
+#undef L_
         kt_.stop();
     }
     MBMD_LAUNCHED();
@@ -445,15 +531,19 @@ int launch_fourier_apply(int K, int nx, int ny, const float* in, const float* M,
     MBMD_REQUIRE(cols_lds(K, C, ny, true) <= 65536, MBMD_ERR_SHAPE, "image too large for the LDS-resident FFT");
     {
         KernelTimer kt_("k_fft_cols", s);
-        hipLaunchKernelGGL(k_fft_cols, dim3(nx / C), dim3(kThreads), cols_lds(K, C, ny, true), s, K, nx, ny, C, spec,
-                           Filt, twy);
+#define L_(NT) hipLaunchKernelGGL((k_fft_cols<NT>), dim3(nx / C), dim3(kThreads), cols_lds(K, C, ny, true), s, K, nx, \
+                               ny, C, spec, Filt, twy)
+        MBMD_FFT_DISPATCH(ny, L_);
+#undef L_
         kt_.stop();
     }
     MBMD_LAUNCHED();
     {
         KernelTimer kt_("k_fft_rows_inv", s);
-        hipLaunchKernelGGL(k_fft_rows_inv, dim3(nblk), dim3(kThreads), rows_lds(K, RB, nx), s, K, nx, ny, RB, spec, M,
-                           out_sign / (float)((double)nx * ny), out, g, partials, twx);
+#define L_(NT) hipLaunchKernelGGL((k_fft_rows_inv<NT>), dim3(nblk), dim3(kThreads), rows_lds(K, RB, nx), s, K, nx, ny, \
+                               RB, spec, M, out_sign / (float)((double)nx * ny), out, g, partials, twx)
+        MBMD_FFT_DISPATCH(nx, L_);
+#undef L_
         kt_.stop();
     }
     MBMD_LAUNCHED();
