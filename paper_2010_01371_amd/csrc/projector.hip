@@ -56,6 +56,38 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kPerWave = 63;                 // pixels per wavefront (back projection)
+
+// Back projection tiling of a sweep line of Np pixels (Np + 1 edges): full
+// segments of kPerWave pixels, then the pixels left over (Np mod kPerWave) as a
+// tail of tail_edges edges, packed tail_lines lines per wavefront -- one
+// wavefront per line there would spend a whole wavefront's time on a handful of
+// lanes.  A tail that would not fit two lines per wavefront is an ordinary
+// partial segment instead (counted in full; lanes past the last edge repeat it).
+struct BackTiling {
+    int full, tail_edges, tail_lines;
+};
+__host__ __device__ inline BackTiling back_tiling(int Np) {
+    BackTiling b{Np / kPerWave, 0, 0};
+    const int rem = Np - b.full * kPerWave;
+    if (rem > 0) {
+        b.tail_edges = rem + 1;
+        b.tail_lines = 64 / b.tail_edges;
+        if (b.tail_lines < 2) b = BackTiling{b.full + 1, 0, 0};
+    }
+    return b;
+}
+// Blocks (kWaves wavefronts) of one sweep frame: the tail, then segments x line groups.
+__host__ __device__ inline int back_main_items(int Np, int Nq, int lpw) {
+    return back_tiling(Np).full * ((Nq + kWaves * lpw - 1) / (kWaves * lpw));
+}
+// Tail blocks: each tail wavefront's views are split into two halves (items
+// 2 i and 2 i + 1), whose pixel values are added onto the cleared tail pixels.
+__host__ __device__ inline int back_tail_items(int Np, int Nq) {
+    const BackTiling b = back_tiling(Np);
+    if (!b.tail_lines) return 0;
+    const int waves = (Nq + b.tail_lines - 1) / b.tail_lines;
+    return 2 * ((waves + kWaves - 1) / kWaves);
+}
 constexpr int kScanThreads = 256;
 constexpr int kBufferWord3 = 0x00020000;     // raw buffer resource, gfx9 family
 
@@ -156,10 +188,34 @@ __global__ __launch_bounds__(kScanThreads) void k_line_prefix(const float* __res
 // takes a contiguous run of bins, an FP64 shuffle scan combines the lanes of a
 // wavefront and one barrier the wavefronts.
 constexpr int kPrefixThreads = 256;
+// Pixels that the back projection's tail wavefronts add into (see back_tiling):
+// the last w0 columns of x (row sweeps) and the last h1 rows of part (column
+// sweeps), nch channels each; zero sizes when there is no such tail.
+struct TailClear {
+    float* x;
+    float* part;
+    int nx, ny, w0, h1, nch;
+};
 __global__ __launch_bounds__(kPrefixThreads) void k_detector_prefix(const float* __restrict__ sino,
                                                                      const float* __restrict__ path,
                                                                      const ViewParams* __restrict__ view, int V,
-                                                                     int B, DetEntry* __restrict__ C) {
+                                                                     int B, DetEntry* __restrict__ C,
+                                                                     TailClear tc) {
+    {   // side job: clear the back projection's tail pixels, which its tail wavefronts add into
+        const int n0 = tc.nch * tc.ny * tc.w0, n1 = tc.nch * tc.h1 * tc.nx, nj = tc.nx * tc.ny;
+        for (int i = (blockIdx.y * gridDim.x + blockIdx.x) * kPrefixThreads + threadIdx.x; i < n0 + n1;
+             i += gridDim.x * gridDim.y * kPrefixThreads) {
+            if (i < n0) {                                      // row sweeps: columns [nx - w0, nx) of x
+                const int c = i / (tc.ny * tc.w0), r = i - c * tc.ny * tc.w0;
+                const int iy = r / tc.w0, ix = tc.nx - tc.w0 + (r - iy * tc.w0);
+                tc.x[(size_t)c * nj + (size_t)iy * tc.nx + ix] = 0.0f;
+            } else {                                           // column sweeps: rows [ny - h1, ny) of part
+                const int k = i - n0;
+                const int c = k / (tc.h1 * tc.nx), r = k - c * tc.h1 * tc.nx;
+                tc.part[(size_t)c * nj + (size_t)(tc.ny - tc.h1) * tc.nx + r] = 0.0f;
+            }
+        }
+    }
     const int slot = blockIdx.x, ch = blockIdx.y;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const float orient = view[slot].orient;
@@ -350,6 +406,99 @@ __global__ __launch_bounds__(kFwdWaves * 64) void k_dd_forward(const ViewParams*
 // resident waves.  Row sweeps write x; column sweeps write their partial image
 // to part in the image's own layout (scattered 4-byte stores, once per pixel),
 // which the caller adds -- the iteration does it inside the penalty kernel.
+// One (sweep line, view) at along-line position K: byte offset of the edge's
+// detector entry and the fraction of its bin.  m = {n, m, c, a}, g: the line's
+// map coefficients; span = back_shift(B) (the clamp, symmetric about the
+// detector centre), origin = span entries in bytes.
+__device__ __forceinline__ void back_locate(const float4& m, float g, float K, float span, int origin, int& off,
+                                            float& fr) {
+    const float den = fmaf(m.z, K, 1.0f);
+    const float num = fmaf(m.y, K, m.x);
+    const float bf = __builtin_amdgcn_fmed3f(floorf(num * fast_rcp(den)), -span, span);
+    off = (int)bf * (int)sizeof(DetEntry) + origin;          // entry in [0, B + 1]
+    fr = __builtin_amdgcn_fmed3f(fmaf(-bf, den, num) * fmaf(-g, bf, m.w), 0.0f, 1.0f);
+}
+
+// The tail of every sweep line (see back_tiling): lane l of tail wavefront tw
+// takes edge full*kPerWave + l mod E of line tw*LT + l / E, so each lane reads
+// its own line's coefficients (vector loads: LT distinct addresses per
+// wavefront).  Views [is0, is1) go in groups of UT with the next group's
+// coefficients in flight while this group's detector entries arrive, summed in
+// view order; the pixel values (FP64 differences of the lanes' sums, then FP32)
+// are added onto the tail pixels, which the detector-prefix launch clears: the
+// two halves of the views add once each, which gives the same result in either
+// order.
+template <int NCH>
+__device__ __forceinline__ void back_tail(const float4* __restrict__ line_tab, int tw, int is0, int is1, int slot0,
+                                          int Np, int Nq, int V, int B, int frame, int nx, int ny,
+                                          const __amdgpu_buffer_rsrc_t& tc, int row, float* __restrict__ dst) {
+    constexpr int UT = NCH <= 2 ? 4 : 2;   // keeps the tail within the main path's registers
+    if (is0 >= is1) return;                // no views in this half (uniform)
+    const BackTiling bt = back_tiling(Np);
+    const int E = bt.tail_edges, LT = bt.tail_lines;
+    const int lane = threadIdx.x & 63;
+    const int ql = lane / E, el = lane - ql * E;
+    const int q = tw * LT + ql;
+    const bool lane_ok = ql < LT && q < Nq;
+    const int pe = min(bt.full * kPerWave + el, Np);
+    const float K = (float)pe - 0.5f * (float)Np;
+    const float4* lt = line_tab + (size_t)min(q, Nq - 1) * V * 2;
+    const float* ltf = reinterpret_cast<const float*>(lt);
+    const int shift = back_shift(B);
+    const float span = (float)shift;
+    const int origin = shift * (int)sizeof(DetEntry);
+    double acc[NCH];
+    float accw[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        acc[c] = 0.0;
+        accw[c] = 0.0f;
+    }
+    float4 tm[UT];
+    float tg[UT];
+    auto fetch = [&](int is) {
+#pragma unroll
+        for (int u = 0; u < UT; ++u) {
+            const int slot = slot0 + min(is + u, is1 - 1);
+            tm[u] = lt[2 * slot];
+            tg[u] = ltf[4 * (2 * slot + 1)];
+        }
+    };
+    fetch(is0);
+    for (int is = is0; is < is1; is += UT) {                   // uniform
+        int off[UT];
+        float fr[UT];
+#pragma unroll
+        for (int u = 0; u < UT; ++u) back_locate(tm[u], tg[u], K, span, origin, off[u], fr[u]);
+        DetValue h[UT][NCH];
+#pragma unroll
+        for (int u = 0; u < UT; ++u)
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) h[u][c] = load_det(tc, off[u], (c * V + slot0 + min(is + u, is1 - 1)) * row);
+        fetch(is + UT);
+#pragma unroll
+        for (int u = 0; u < UT; ++u) {
+            if (is + u >= is1) break;                          // uniform
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                acc[c] += h[u][c].c;
+                accw[c] = fmaf(fr[u], h[u][c].d, accw[c]);
+                keep(h[u][c].pad);
+            }
+        }
+    }
+    const size_t img_stride = (size_t)nx * ny;
+    float val[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+        val[c] = (float)((next_lane(acc[c]) - acc[c]) + (double)(next_lane(accw[c]) - accw[c]));
+    if (lane_ok && el < E - 1) {                               // pixel pe, whose right edge is the next lane
+        const size_t pix = frame ? (size_t)pe * nx + q : (size_t)q * nx + pe;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) unsafeAtomicAdd(&dst[c * img_stride + pix], val[c]);
+    }
+}
+
 template <int NCH, int LPW, int U>
 __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__ line_tab, int nv0, int nv1,
                                                       FrameSplit fs, int nx, int ny, int V, int B,
@@ -359,7 +508,23 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
     if (!decode_block(fs, frame, item)) return;
     const int Nq = frame ? nx : ny;
     const int Np = frame ? ny : nx;
-    const int segs = (Np + kPerWave - 1) / kPerWave;
+    const int nv = frame ? nv1 : nv0;
+    const int slot0 = frame ? nv0 : 0;
+    const int row = det_row(B) * (int)sizeof(DetEntry);
+    const __amdgpu_buffer_rsrc_t tc = rsrc(C, (size_t)row * NCH * V);
+    // the tail items come first: their wavefronts are the longest, so they are
+    // dispatched before the main ones fill the machine
+    const int tail_items = back_tail_items(Np, Nq);
+    if (item < tail_items) {
+        const int tw = (item >> 1) * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        if (tw * back_tiling(Np).tail_lines >= Nq) return;      // whole wavefront past the last line
+        const int mid = nv >> 1;
+        back_tail<NCH>(line_tab, tw, (item & 1) ? mid : 0, (item & 1) ? nv : mid, slot0, Np, Nq, V, B, frame, nx,
+                       ny, tc, row, frame ? part : x);
+        return;
+    }
+    item -= tail_items;
+    const int segs = back_tiling(Np).full;
     const int seg = item % segs;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -367,14 +532,10 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
     if (q0 >= Nq) return;                          // whole wavefront outside the image
     const int pe = seg * kPerWave + lane;          // edge index; lanes past Np repeat edge Np
     const float K = (float)min(pe, Np) - 0.5f * (float)Np;
-    const int nv = frame ? nv1 : nv0;
-    const int slot0 = frame ? nv0 : 0;
     // first table entry of each line, kept in scalar registers
     int lt0[LPW];
 #pragma unroll
     for (int j = 0; j < LPW; ++j) lt0[j] = __builtin_amdgcn_readfirstlane(min(q0 + j, Nq - 1) * V * 2);
-    const int row = det_row(B) * (int)sizeof(DetEntry);
-    const __amdgpu_buffer_rsrc_t tc = rsrc(C, (size_t)row * NCH * V);
     const int shift = back_shift(B);
     const float span = (float)shift;               // bin index clamp, symmetric about the centre
     const int origin = shift * (int)sizeof(DetEntry);
@@ -387,14 +548,6 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
             acc[j][c] = 0.0;
             accw[j][c] = 0.0f;
         }
-    // one (line, view): byte offset of the edge's detector entry and its fraction
-    auto locate = [&](const float4& m, float g, int& off, float& fr) {
-        const float den = fmaf(m.z, K, 1.0f);
-        const float num = fmaf(m.y, K, m.x);
-        const float bf = __builtin_amdgcn_fmed3f(floorf(num * fast_rcp(den)), -span, span);
-        off = (int)bf * (int)sizeof(DetEntry) + origin;          // entry in [0, B + 1]
-        fr = __builtin_amdgcn_fmed3f(fmaf(-bf, den, num) * fmaf(-g, bf, m.w), 0.0f, 1.0f);
-    };
     // Software pipeline over groups of U views: the per-line tables of the next
     // group are requested (scalar loads) only after this group's values are in
     // registers -- scalar loads complete out of order, so a wait for one waits
@@ -421,7 +574,7 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int j = 0; j < LPW; ++j) locate(tm[u][j], tg[u][j], off[u][j], frs[u][j]);
+            for (int j = 0; j < LPW; ++j) back_locate(tm[u][j], tg[u][j], K, span, origin, off[u][j], frs[u][j]);
         DetValue h[U][LPW][NCH];
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -451,7 +604,7 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
         for (int j = 0; j < LPW; ++j) {
             int o;
             float fr;
-            locate(tm[u][j], tg[u][j], o, fr);
+            back_locate(tm[u][j], tg[u][j], K, span, origin, o, fr);
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
                 const DetValue h = load_det(tc, o, (c * V + slot0 + nfull + u) * row);
@@ -564,9 +717,8 @@ double back_cost(long long waves, int per_round, int lpw, int simds) {
 template <int NCH, int LPW, int U>
 void back_kernel_launch(const GeomTables& t, float* x, hipStream_t s) {
     const int nv0 = t.n_frame_views[0], nv1 = t.n_frame_views[1];
-    const int lines = kWaves * LPW;
-    const int u0 = nv0 ? ((t.nx + kPerWave - 1) / kPerWave) * ((t.ny + lines - 1) / lines) : 0;
-    const int u1 = nv1 ? ((t.ny + kPerWave - 1) / kPerWave) * ((t.nx + lines - 1) / lines) : 0;
+    const int u0 = nv0 ? back_main_items(t.nx, t.ny, LPW) + back_tail_items(t.nx, t.ny) : 0;
+    const int u1 = nv1 ? back_main_items(t.ny, t.nx, LPW) + back_tail_items(t.ny, t.nx) : 0;
     const FrameSplit fs = split(u0, u1);
     KernelTimer kt_("k_dd_back", s);
     hipLaunchKernelGGL((k_dd_back<NCH, LPW, U>), dim3(grid_blocks(fs)), dim3(kThreads), 0, s, t.back_line, nv0, nv1, fs,
@@ -578,14 +730,19 @@ void back_kernel_launch(const GeomTables& t, float* x, hipStream_t s) {
 // returns the column-sweep part, in image layout, or nullptr when there is none.
 template <int NCH>
 const float* back_launch(const GeomTables& t, const float* sino, float* x, hipStream_t s) {
-    {
-        KernelTimer kt_("k_detector_prefix", s);
-        hipLaunchKernelGGL(k_detector_prefix, dim3(t.V, NCH), dim3(kPrefixThreads), 0, s, sino, t.path, t.view,
-                           t.V, t.B, t.det_prefix);
-        kt_.stop();
-    }
-    MBMD_LAUNCHED();
     const int nv0 = t.n_frame_views[0], nv1 = t.n_frame_views[1];
+    // The detector prefix, which also clears the pixels the tail wavefronts add
+    // into, precedes every back projection kernel (the tuner's too).
+    auto prefix = [&]() {
+        KernelTimer kt_("k_detector_prefix", s);
+        const BackTiling b0 = back_tiling(t.nx), b1 = back_tiling(t.ny);
+        const TailClear clr{x, t.back_part, t.nx, t.ny, nv0 && b0.tail_lines ? t.nx - b0.full * kPerWave : 0,
+                            nv1 && b1.tail_lines ? t.ny - b1.full * kPerWave : 0, NCH};
+        hipLaunchKernelGGL(k_detector_prefix, dim3(t.V, NCH), dim3(kPrefixThreads), 0, s, sino, t.path, t.view,
+                           t.V, t.B, t.det_prefix, clr);
+        kt_.stop();
+        MBMD_LAUNCHED();
+    };
     if (!nv0) launch_fill(NCH * t.nx * t.ny, x, 0.0f, s);
     // Tile shape: lines per wavefront x views in flight.  The first back
     // projection of a geometry and channel count outside graph capture times
@@ -596,12 +753,16 @@ const float* back_launch(const GeomTables& t, const float* sino, float* x, hipSt
     constexpr int N2 = NCH <= 2 ? NCH : 1;
     const Launch cand[3] = {back_kernel_launch<NCH, 1, 2>, back_kernel_launch<NCH, 1, 4>,
                             back_kernel_launch<N2, 2, 2>};
+    auto run = [&](int v) {
+        prefix();
+        cand[v](t, x, s);
+        MBMD_LAUNCHED();
+    };
     const int n_cand = NCH <= 2 ? 3 : 2;
     int& choice = t.back_variant[NCH];
     const int forced = forced_back_variant();
     if (forced >= 0 && forced < n_cand) {           // testing hook: no tuning, nothing cached
-        cand[forced](t, x, s);
-        MBMD_LAUNCHED();
+        run(forced);
         return nv1 ? t.back_part : nullptr;
     }
     if (choice < 0) {
@@ -613,9 +774,9 @@ const float* back_launch(const GeomTables& t, const float* sino, float* x, hipSt
             MBMD_HIP(hipEventCreate(&ev[1]));
             float best = 1e30f;
             for (int v = 0; v < n_cand; ++v) {
-                cand[v](t, x, s);                      // warm-up
+                run(v);                                // warm-up
                 MBMD_HIP(hipEventRecord(ev[0], s));
-                for (int r = 0; r < 3; ++r) cand[v](t, x, s);
+                for (int r = 0; r < 3; ++r) run(v);     // the prefix is the same for every candidate
                 MBMD_HIP(hipEventRecord(ev[1], s));
                 MBMD_HIP(hipEventSynchronize(ev[1]));
                 float ms = 0.0f;
@@ -633,24 +794,21 @@ const float* back_launch(const GeomTables& t, const float* sino, float* x, hipSt
             MBMD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
             const int simds = 4 * (cus > 0 ? cus : 1);
             auto waves = [&](int lpw) {
-                const int lines = kWaves * lpw;
-                const long long u0 = nv0 ? (long long)((t.nx + kPerWave - 1) / kPerWave) * ((t.ny + lines - 1) / lines) : 0;
-                const long long u1 = nv1 ? (long long)((t.ny + kPerWave - 1) / kPerWave) * ((t.nx + lines - 1) / lines) : 0;
+                const long long u0 = nv0 ? (long long)back_main_items(t.nx, t.ny, lpw) + back_tail_items(t.nx, t.ny) : 0;
+                const long long u1 = nv1 ? (long long)back_main_items(t.ny, t.nx, lpw) + back_tail_items(t.ny, t.nx) : 0;
                 return (u0 + u1) * kWaves;
             };
             const double c1 = back_cost(waves(1), back_waves_per_round<NCH, 1>(), 1, simds);
             const double c2 = NCH <= 2 ? back_cost(waves(2), back_waves_per_round<N2, 2>(), 2, simds) : 1e300;
             const int pick = c2 < c1 ? 2 : 0;
             if (cap != hipStreamCaptureStatusNone) {
-                cand[pick](t, x, s);                   // not cached: tune on a later uncaptured call
-                MBMD_LAUNCHED();
+                run(pick);                             // not cached: tune on a later uncaptured call
                 return nv1 ? t.back_part : nullptr;
             }
             choice = pick;
         }
     }
-    cand[choice](t, x, s);
-    MBMD_LAUNCHED();
+    run(choice);
     return nv1 ? t.back_part : nullptr;
 }
 

@@ -94,6 +94,22 @@ def test_backproject_is_deterministic():
     assert torch.equal(a, b) and torch.equal(b, c)
 
 
+def test_projection_pair_is_deterministic_at_full_size():
+    """The forward adds two half-line sums per bin with atomics and the back
+    projector packs the line tails; both must still give bitwise-identical
+    results on repeated calls (two additions onto zero commute)."""
+    wl = C.make_c2(noise=False)
+    g = wl.geom
+    x = dev(wl.x_true)
+    s = dev(np.random.default_rng(7).normal(size=(1, g["n_views"], g["n_bins"])))
+    announce("determinism full size")
+    p = [mb.project(g, x) for _ in range(3)]
+    b = [mb.backproject(g, s) for _ in range(3)]
+    torch.cuda.synchronize()
+    assert torch.equal(p[0], p[1]) and torch.equal(p[1], p[2])
+    assert torch.equal(b[0], b[1]) and torch.equal(b[1], b[2])
+
+
 def test_identity_geometry_is_a_copy():
     g = C.identity_geometry(5, 7)
     x = np.random.default_rng(6).normal(size=(2, 5, 7))
