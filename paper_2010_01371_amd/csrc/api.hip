@@ -289,10 +289,14 @@ void plain_iteration(Problem& P, float* x, double* trace_slot, hipStream_t s) {
     launch_reduce_final(P.partials, counts, P.scal, trace_slot, 0, P.flags, s);
 }
 
-// One preconditioned iteration (l = A x must be current on entry and is kept current).
+// One preconditioned iteration.  On entry l = A x up to the step the previous
+// iteration left pending in alpha (zero when none), which this one applies first;
+// on exit its own step is pending.
 void precond_iteration(Problem& P, float* x, int kind, double* trace_slot, hipStream_t s) {
     int counts[kRegions] = {0};
-    counts[R_PHI_L] = launch_ray_grad(ray_args(P), P.l, P.u, nullptr, P.r, region(P, R_PHI_L), s);
+    // the previous iteration's step (x += alpha p, l += alpha q) is applied by this launch
+    const StepUpdate up{P.scal + S_ALPHA, P.q, P.l, x, P.p_img, P.K * P.nj};
+    counts[R_PHI_L] = launch_ray_grad(ray_args(P), P.l, P.u, nullptr, P.r, region(P, R_PHI_L), s, &up);
     const float* part = backproject_parts(P, P.u, P.g_img, P.K, s);   // summed by the penalty pass
     counts[R_PHI_R] = launch_penalty_grad(pen_args(P), x, P.g_img, nullptr, P.g_img, nullptr,
                                           region(P, R_PHI_R), s, part);
@@ -300,8 +304,15 @@ void precond_iteration(Problem& P, float* x, int kind, double* trace_slot, hipSt
     project(P, P.p_img, P.q, P.K, s);
     const PenaltyArgs pa = pen_args(P);
     launch_curvature(ray_args(P), P.l, P.r, P.q, P.has_penalty ? &pa : nullptr, x, P.p_img, P.partials, counts, s);
-    launch_reduce_final(P.partials, counts, P.scal, trace_slot, 1, P.flags, s);
+    launch_reduce_final(P.partials, counts, P.scal, trace_slot, 1, P.flags, s);   // alpha: applied next
+}
+
+// Applies a pending preconditioned step (x += alpha p, l += alpha q) and clears
+// alpha, which makes the next iteration's application a no-op; every run of
+// preconditioned iterations ends with this, and so does every refresh of l.
+void flush_step(Problem& P, float* x, hipStream_t s) {
     launch_axpy2_alpha(P.K * P.nj, x, P.p_img, P.K * P.ni, P.l, P.q, P.scal + S_ALPHA, s);
+    launch_fill_double(1, P.scal + S_ALPHA, 0.0, s);
 }
 
 void check_precond_ready(Problem& P, int precond) {
@@ -371,10 +382,14 @@ void sps_run(Problem& P, float* x, int precond, int n_iter, double* trace_host, 
         if (precond == MBMD_PRECOND_NONE) {
             plain_iteration(P, x, slot, s);
         } else {
-            if (n % kRefreshEvery == 0) project(P, x, P.l, P.K, s);
+            if (n % kRefreshEvery == 0) {
+                flush_step(P, x, s);
+                project(P, x, P.l, P.K, s);
+            }
             precond_iteration(P, x, precond, slot, s);
         }
     }
+    if (precond != MBMD_PRECOND_NONE) flush_step(P, x, s);
     if (trace_host) {
         if (n_iter - base == P.trace_cap) {
             MBMD_HIP(hipMemcpyAsync(trace_host + base, P.trace, sizeof(double) * P.trace_cap,
@@ -527,6 +542,10 @@ int mbmd_problem_create(const mbmd_geometry* geom, const mbmd_spectral* sp, cons
         else
             launch_inv_var(C * P->ni, P->y, P->w, s);
         launch_fill(4, reinterpret_cast<float*>(P->flags), 0.0f, s);
+        // no step pending: alpha = 0 (p and q finite)
+        launch_fill_double(kScalars, P->scal, 0.0, s);
+        launch_fill(P->K * P->nj, P->p_img, 0.0f, s);
+        launch_fill(P->K * P->ni, P->q, 0.0f, s);
         if (P->identity) {
             launch_fill(P->ni, P->gammaA, 1.0f, s);
         } else {
@@ -699,9 +718,16 @@ int mbmd_batch_sps_step(mbmd_batch* b, float* const* x_dev, int precond, int n_i
             if (precond == MBMD_PRECOND_NONE) {
                 plain_iteration(P, x_dev[k], nullptr, bs);
             } else {
-                if (refresh) project(P, x_dev[k], P.l, P.K, bs);
+                if (refresh) {
+                    flush_step(P, x_dev[k], bs);
+                    project(P, x_dev[k], P.l, P.K, bs);
+                }
                 precond_iteration(P, x_dev[k], precond, nullptr, bs);
             }
+        };
+        // the pending step of each slice, after its last iteration
+        auto finish = [&](size_t k, hipStream_t st) {
+            if (precond != MBMD_PRECOND_NONE) flush_step(*b->probs[k], x_dev[k], st);
         };
         auto fork = [&](hipStream_t from) {
             MBMD_HIP(hipEventRecord(b->fork, from));
@@ -718,6 +744,7 @@ int mbmd_batch_sps_step(mbmd_batch* b, float* const* x_dev, int precond, int n_i
             fork(s);
             for (int it = 0; it < n_iter; ++it)
                 for (size_t k = 0; k < n; ++k) slice_iter(k, it % kRefreshEvery == 0);
+            for (size_t k = 0; k < n; ++k) finish(k, b->branch[b->lane[k]]);
             join(s);
             return;
         }
@@ -762,6 +789,7 @@ int mbmd_batch_sps_step(mbmd_batch* b, float* const* x_dev, int precond, int n_i
             const bool refresh = precond != MBMD_PRECOND_NONE && it % kRefreshEvery == 0;
             MBMD_HIP(hipGraphLaunch(b->exec[refresh ? 1 : 0], s));
         }
+        for (size_t k = 0; k < n; ++k) finish(k, s);
     });
 }
 

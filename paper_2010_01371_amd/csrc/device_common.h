@@ -29,6 +29,68 @@ __device__ __forceinline__ float huber_omega(float t, float d) {
     return a <= d ? 1.0f : d / a;
 }
 
+__device__ __forceinline__ float huber_dpsi(float t, float d) { return fminf(fmaxf(t, -d), d); }
+__device__ __forceinline__ double huber_psi(double t, double d) {
+    const double a = fabs(t);
+    return a <= d ? 0.5 * t * t : d * a - 0.5 * d * d;
+}
+
+// Pixel j of the penalty: its gradient gr[k] per material, its separable SPS
+// curvature cur[k] (when cur is not NULL) and the share of R(x) charged to it
+// (the pairs (j, right) and (j, down)), which it returns.  Quadratic:
+// R = 1/2 x^T (beta (x) Gamma) x, curvature sum_k' |beta_kk'| 2 |N_j|; Huber (one
+// material): R = beta sum_pairs psi(x_j - x_j'), gradient beta sum psi'(.),
+// curvature 2 beta sum omega(.).
+__device__ __forceinline__ double penalty_grad_at(const PenaltyArgs& a, const float* __restrict__ x, int j,
+                                                  float* gr, float* cur) {
+    const int nj = a.nx * a.ny;
+    const int iy = j / a.nx, ix = j - iy * a.nx;
+    const bool L = ix > 0, R = ix + 1 < a.nx, U = iy > 0, D = iy + 1 < a.ny;
+    double phi = 0.0;
+    if (a.kind == MBMD_PENALTY_HUBER) {
+        const float xc = x[j];
+        float g = 0.0f, om = 0.0f;
+        if (L) { const float t = xc - x[j - 1]; g += huber_dpsi(t, a.delta); om += huber_omega(t, a.delta); }
+        if (R) { const float t = xc - x[j + 1]; g += huber_dpsi(t, a.delta); om += huber_omega(t, a.delta);
+                 phi += huber_psi((double)t, (double)a.delta); }
+        if (U) { const float t = xc - x[j - a.nx]; g += huber_dpsi(t, a.delta); om += huber_omega(t, a.delta); }
+        if (D) { const float t = xc - x[j + a.nx]; g += huber_dpsi(t, a.delta); om += huber_omega(t, a.delta);
+                 phi += huber_psi((double)t, (double)a.delta); }
+        const float b = a.beta[0];
+        gr[0] = b * g;
+        if (cur) cur[0] = 2.0f * b * om;
+        return phi * (double)b;
+    }
+    const float nn = (float)(L + R + U + D);
+    float lap[kMaxMat];
+#pragma unroll
+    for (int k = 0; k < kMaxMat; ++k) {
+        if (k >= a.K) break;
+        const float* xk = x + (size_t)k * nj;
+        float s = nn * xk[j];
+        if (L) s -= xk[j - 1];
+        if (R) s -= xk[j + 1];
+        if (U) s -= xk[j - a.nx];
+        if (D) s -= xk[j + a.nx];
+        lap[k] = s;
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxMat; ++k) {
+        if (k >= a.K) break;
+        float g = 0.0f, ab = 0.0f;
+#pragma unroll
+        for (int l2 = 0; l2 < kMaxMat; ++l2) {
+            if (l2 >= a.K) break;
+            g = fmaf(a.beta[k * a.K + l2], lap[l2], g);
+            ab += fabsf(a.beta[k * a.K + l2]);
+        }
+        gr[k] = g;
+        if (cur) cur[k] = ab * 2.0f * nn;
+        phi += 0.5 * (double)x[(size_t)k * nj + j] * (double)g;
+    }
+    return phi;
+}
+
 // Pixel j's share of p^T R''(x) p: the pairs (j, right) and (j, down).  Huber
 // (one material): beta sum omega(x_j - x_j') (p_j - p_j')^2; quadratic:
 // sum_kl beta_kl (p_k,j - p_k,j')(p_l,j - p_l,j').

@@ -29,11 +29,6 @@ using dev::block_sum;
 using dev::huber_omega;
 using dev::Counts;
 
-__device__ __forceinline__ float huber_dpsi(float t, float d) { return fminf(fmaxf(t, -d), d); }
-__device__ __forceinline__ double huber_psi(double t, double d) {
-    const double a = fabs(t);
-    return a <= d ? 0.5 * t * t : d * a - 0.5 * d * d;
-}
 
 // g = gL (+ gL2) + dR/dx, d = dL + d_R (d may be NULL), partials of R(x).
 // gL may alias g and dL may alias d (each element is read before it is written);
@@ -47,44 +42,15 @@ __global__ __launch_bounds__(kThreads) void k_penalty_grad(PenaltyArgs a, const 
     const int j = blockIdx.x * kThreads + threadIdx.x;
     double phi = 0.0;
     if (j < nj) {
-        const int iy = j / a.nx, ix = j - iy * a.nx;
-        const bool L = ix > 0, R = ix + 1 < a.nx, U = iy > 0, D = iy + 1 < a.ny;
-        if (a.kind == MBMD_PENALTY_HUBER) {
-            const float xc = x[j];
-            float gr = 0.0f, om = 0.0f;
-            if (L) { const float t = xc - x[j - 1]; gr += huber_dpsi(t, a.delta); om += huber_omega(t, a.delta); }
-            if (R) { const float t = xc - x[j + 1]; gr += huber_dpsi(t, a.delta); om += huber_omega(t, a.delta);
-                     phi += huber_psi((double)t, (double)a.delta); }
-            if (U) { const float t = xc - x[j - a.nx]; gr += huber_dpsi(t, a.delta); om += huber_omega(t, a.delta); }
-            if (D) { const float t = xc - x[j + a.nx]; gr += huber_dpsi(t, a.delta); om += huber_omega(t, a.delta);
-                     phi += huber_psi((double)t, (double)a.delta); }
-            const float b = a.beta[0];
-            g[j] = (gL2 ? gL[j] + gL2[j] : gL[j]) + b * gr;
-            if (d) d[j] = dL[j] + 2.0f * b * om;
-            phi *= (double)b;
-        } else {
-            const float nn = (float)(L + R + U + D);
-            float lap[kMaxMat];
-            for (int k = 0; k < a.K; ++k) {
-                const float* xk = x + (size_t)k * nj;
-                float s = nn * xk[j];
-                if (L) s -= xk[j - 1];
-                if (R) s -= xk[j + 1];
-                if (U) s -= xk[j - a.nx];
-                if (D) s -= xk[j + a.nx];
-                lap[k] = s;
-            }
-            for (int k = 0; k < a.K; ++k) {
-                float gr = 0.0f, ab = 0.0f;
-                for (int l2 = 0; l2 < a.K; ++l2) {
-                    gr = fmaf(a.beta[k * a.K + l2], lap[l2], gr);
-                    ab += fabsf(a.beta[k * a.K + l2]);
-                }
-                const size_t jk = (size_t)k * nj + j;
-                g[jk] = (gL2 ? gL[jk] + gL2[jk] : gL[jk]) + gr;
-                if (d) d[(size_t)k * nj + j] = dL[(size_t)k * nj + j] + ab * 2.0f * nn;
-                phi += 0.5 * (double)x[(size_t)k * nj + j] * (double)gr;
-            }
+        float gr[kMaxMat], cur[kMaxMat];
+        phi = dev::penalty_grad_at(a, x, j, gr, d ? cur : nullptr);
+        const int K = a.kind == MBMD_PENALTY_HUBER ? 1 : a.K;
+#pragma unroll
+        for (int k = 0; k < kMaxMat; ++k) {
+            if (k >= K) break;
+            const size_t jk = (size_t)k * nj + j;
+            g[jk] = (gL2 ? gL[jk] + gL2[jk] : gL[jk]) + gr[k];
+            if (d) d[jk] = dL[jk] + cur[k];
         }
     }
     const double tot = block_sum(phi, sh);

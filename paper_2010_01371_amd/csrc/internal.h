@@ -283,8 +283,20 @@ struct PenaltyArgs {
     const float* beta;     // device [K][K]
     float delta;
 };
+// The previous preconditioned step, applied at the start of the next ray
+// gradient launch: l += alpha q (in place, before l is used) and, in extra
+// blocks of the same launch, x += alpha p (n_img floats); alpha is read on the
+// device, and a zero alpha (with finite p and q) makes it a no-op.
+struct StepUpdate {
+    const double* alpha;
+    const float* q;
+    float* l;
+    float* x;
+    const float* p;
+    int n_img;
+};
 int launch_ray_grad(const RayArgs& a, const float* l, float* u, float* v, float* r,
-                    double* phi_partials, hipStream_t s);
+                    double* phi_partials, hipStream_t s, const StepUpdate* up = nullptr);
 int launch_ray_curv(const RayArgs& a, const float* l, const float* r, const float* q,
                     double* partials, hipStream_t s);
 // Curvature along the direction in one launch: the rays' c q^2 into region CQ2

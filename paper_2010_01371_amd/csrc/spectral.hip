@@ -76,16 +76,30 @@ __global__ __launch_bounds__(kRayThreads) void k_ray_grad(RayModel m, int ni, co
                                                           const float* __restrict__ gammaA,
                                                           float* __restrict__ u, float* __restrict__ v,
                                                           float* __restrict__ r_out,
-                                                          double* __restrict__ partials) {
+                                                          double* __restrict__ partials, StepUpdate up, int nb_ray) {
     __shared__ double sh[kRayThreads / 64];
     __shared__ SharedModel sm;
+    if (up.alpha && (int)blockIdx.x >= nb_ray) {           // the image part of the step: x += alpha p
+        const float a = (float)*up.alpha;
+        const int i = ((int)blockIdx.x - nb_ray) * kRayThreads + threadIdx.x;
+        if (a != 0.0f && i < up.n_img) up.x[i] = fmaf(a, up.p[i], up.x[i]);
+        return;
+    }
     stage_model<KT, CT>(m, sm);
     const int K = KT ? KT : m.K, C = CT ? CT : m.C;
     const int i = blockIdx.x * kRayThreads + threadIdx.x;
     double phi = 0.0;
     if (i < ni) {
         float lk[kMaxMat], ybar[kMaxChan], rc[kMaxChan], sig[kMaxChan];
-        for (int k = 0; k < K; ++k) lk[k] = l[(size_t)k * ni + i];
+        const float a = up.alpha ? (float)*up.alpha : 0.0f;
+        if (a != 0.0f) {                                   // l += alpha q, then use it
+            for (int k = 0; k < K; ++k) {
+                lk[k] = fmaf(a, up.q[(size_t)k * ni + i], up.l[(size_t)k * ni + i]);
+                up.l[(size_t)k * ni + i] = lk[k];
+            }
+        } else {
+            for (int k = 0; k < K; ++k) lk[k] = l[(size_t)k * ni + i];
+        }
         channel_means<KT, CT>(m, sm, lk, ybar);
         for (int c = 0; c < C; ++c) {
             const float yc = y[(size_t)c * ni + i], wc = w[(size_t)c * ni + i];
@@ -453,13 +467,16 @@ int blocks_for(int n) { return (n + kRayThreads - 1) / kRayThreads; }
 }  // namespace
 
 int launch_ray_grad(const RayArgs& a, const float* l, float* u, float* v, float* r, double* phi_partials,
-                    hipStream_t s) {
+                    hipStream_t s, const StepUpdate* up) {
     const int nb = blocks_for(a.ni);
     MBMD_REQUIRE(nb <= kMaxPartials, MBMD_ERR_SHAPE, "too many rays for the partial-sum buffer");
+    const StepUpdate upd = up ? *up : StepUpdate{nullptr, nullptr, nullptr, nullptr, nullptr, 0};
+    MBMD_REQUIRE(!up || up->l == l, MBMD_ERR_ARG, "the step update must update the l it reads");
+    const int nb_img = up ? blocks_for(up->n_img) : 0;
     {
         KernelTimer kt_("k_ray_grad", s);
-#define L_(KT, CT) hipLaunchKernelGGL((k_ray_grad<KT, CT>), dim3(nb), dim3(kRayThreads), 0, s, model_of(a), a.ni, \
-                                   l, a.y, a.w, a.gammaA, u, v, r, phi_partials)
+#define L_(KT, CT) hipLaunchKernelGGL((k_ray_grad<KT, CT>), dim3(nb + nb_img), dim3(kRayThreads), 0, s, model_of(a), \
+                                   a.ni, l, a.y, a.w, a.gammaA, u, v, r, phi_partials, upd, nb)
         MBMD_RAY_DISPATCH(a.K, a.C, L_);
 #undef L_
         kt_.stop();
