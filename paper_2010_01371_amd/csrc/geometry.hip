@@ -170,18 +170,23 @@ void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int b
         // the line).  Numerator and denominator are divided by D, so that the
         // denominator is 1 + c K, and the bin origin moves to the detector centre,
         // which bounds the in-range FP32 map values by half the detector and makes
-        // the clamp of the bin index symmetric.
+        // the clamp of the bin index symmetric.  For a view whose bins run along -K
+        // the map is of the reversed index B - beta (numerator B (D + dK K) -
+        // (N + nK K)), matching its detector row, which the back projector stores
+        // from the last bin: every row then runs along +K.
         const int Nq = frame == 0 ? g.ny : g.nx;
         const double sh = (double)back_shift(B);
         for (int q = 0; q < Nq; ++q) {
             const double qq = q - 0.5 * (Nq - 1);
-            const double N = n0 + nq * qq, D = d0 + dqq * qq;
-            const double delta = D * nK - N * dK;
+            const double D = d0 + dqq * qq;
+            const double N = n_neg ? B * D - (n0 + nq * qq) : n0 + nq * qq;
+            const double nKl = n_neg ? B * dK - nK : nK;
+            const double delta = D * nKl - N * dK;
             MBMD_REQUIRE(std::fabs(delta) > 0.0 && D > 0.0, MBMD_ERR_SHAPE,
                          "degenerate bin map on a sweep line (source too close)");
             float4* L = &line[((size_t)q * V + slot) * 2];
-            L[0] = make_float4((float)((N - sh * D) / D), (float)((nK - sh * dK) / D), (float)(dK / D),
-                               (float)(D * (nK - (sh + 1.0) * dK) / delta));
+            L[0] = make_float4((float)((N - sh * D) / D), (float)((nKl - sh * dK) / D), (float)(dK / D),
+                               (float)(D * (nKl - (sh + 1.0) * dK) / delta));
             L[1] = make_float4((float)(D * dK / delta), 0.0f, 0.0f, 0.0f);
         }
         p.orient = n_neg == 0 ? 1.0f : -1.0f;

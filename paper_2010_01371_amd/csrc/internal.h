@@ -97,12 +97,13 @@ struct ViewParams {
 __host__ __device__ inline int vp_view(const ViewParams& p) { return p.view_frame & 0xffff; }
 __host__ __device__ inline int vp_frame(const ViewParams& p) { return p.view_frame >> 16; }
 
-// One detector cell of the back projector's cumulative integral: C[b] in FP64
-// and the width C[b+1] - C[b] of the bin in FP32 (16 bytes, one vector load).
+// One detector cell b of the back projector's cumulative integral: C[b+1] in
+// FP64, the width C[b+1] - C[b] of the bin and the width of the next bin in
+// FP32 (16 bytes, one vector load, which serves both pixel edges of a lane).
 struct alignas(16) DetEntry {
     double c;
     float d;
-    float pad;
+    float dn;
 };
 
 // Per-view tables are in slot order (views of frame 0, then of frame 1).
@@ -128,8 +129,9 @@ struct GeomTables {
     // [max(nx,ny)][slot][2]: per sweep line q of the slot's frame, the fractional
     // bin index counted from the detector centre, beta - back_shift(B) =
     // (n + m K) / (1 + c K), as {n, m, c, a} and {g, 0, 0, 0}: with
-    // f = floor(beta - back_shift(B)), (a - g f) scales (n + m K) - f (1 + c K)
-    // to the fraction (K - K_b) / (K_b+1 - K_b) of bin b
+    // f = b - back_shift(B) for any bin b, (a - g f) scales (n + m K) - f (1 + c K)
+    // to the fraction (K - K_b) / (K_b+1 - K_b) of bin b.  beta increases with K:
+    // for views with orient < 0 it counts bins from the last one
     float4* back_line = nullptr;
     int back_line_q = 0;             // max(nx, ny)
     DetEntry* det_prefix = nullptr;  // scratch: [back_ch][V][det_row(B)] detector entries
@@ -146,10 +148,11 @@ struct GeomTables {
 // entries (a 16-byte read at any k <= Np stays in the row) rounded up to a
 // multiple of 4, so that rows start 16-byte aligned.
 __host__ __device__ inline int prefix_row(int Np) { return (Np + 4 + 3) & ~3; }
-// Detector rows of the back projector: entries 0 .. B-1 are the bins, B and
-// B+1 repeat the total with zero width, so that the bin index clamped to the
-// symmetric range [-back_shift(B), back_shift(B)] around the detector centre
-// (shifted by back_shift(B)) always lands inside the row.
+// Detector rows of the back projector: entries 0 .. B-1 are the bins (from the
+// last bin for views with orient < 0), B and B+1 repeat the total with zero
+// widths, so that the bin index clamped to the symmetric range
+// [-back_shift(B), back_shift(B)] around the detector centre (shifted by
+// back_shift(B)) always lands inside the row.
 __host__ __device__ inline int det_row(int B) { return B + 2; }
 
 // Forward projection tiling: wavefronts of two bin boundaries per lane (127 bins),

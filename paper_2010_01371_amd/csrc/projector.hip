@@ -55,7 +55,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr int kPerWave = 63;                 // pixels per wavefront (back projection)
+constexpr int kPerWave = 127;                // pixels per wavefront of the back projection (two edges per lane)
 
 // Back projection tiling of a sweep line of Np pixels (Np + 1 edges): full
 // segments of kPerWave pixels, then the pixels left over (Np mod kPerWave) as a
@@ -115,13 +115,14 @@ __device__ __forceinline__ float2 load_f2(__amdgpu_buffer_rsrc_t r, int voff, in
 __device__ __forceinline__ float4 load_f4(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
     return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
-// One detector entry as loaded: C[b], the width, and the pad word, which is
-// kept live until the entry is consumed (see keep()), since otherwise the
-// compiler reuses its register as a temporary and must wait for the load.
+// One detector entry as loaded: C[b+1] and the widths of bins b and b + 1.  A word
+// that the reader does not use is kept live until the entry is consumed (see
+// keep()), since otherwise the compiler reuses its register as a temporary and
+// must wait for the load.
 struct DetValue {
     double c;
     float d;
-    float pad;
+    float dn;
 };
 __device__ __forceinline__ DetValue load_det(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
     return __builtin_bit_cast(DetValue, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
@@ -180,17 +181,18 @@ __global__ __launch_bounds__(kScanThreads) void k_line_prefix(const float* __res
     if (threadIdx.x < 4) dst[Np + threadIdx.x] = (float)part[kScanThreads - 1];
 }
 
-// Per slot and channel, the row of detector entries (C[b], C[b+1] - C[b]) with
-// C[b] = orient * sum_{b'<b} sino[b'] path[b'] (FP64 sums of the FP32 widths,
-// so that C[b] + width reaches C[b+1] up to FP64 rounding), and the total with
-// zero width at entries B and B+1; the view's orientation sign makes
-// H(K+1) - H(K) the pixel value.  One workgroup per (slot, channel); each lane
-// takes a contiguous run of bins, an FP64 shuffle scan combines the lanes of a
-// wavefront and one barrier the wavefronts.
+// Per slot and channel, the row of detector entries (C[b+1], w[b], w[b+1]) with
+// widths w[b] = sino[b'] path[b'] of the bins in increasing-K order (b' = b, or
+// B - 1 - b for views with orient < 0) and C[b] = sum_{b''<b} w[b''] (FP64 sums
+// of the FP32 widths, so that C[b+1] - w[b] gives C[b] up to FP64 rounding),
+// w[B] = 0, and the total with zero widths at entries B and B+1.  One workgroup
+// per (slot, channel); each lane takes a contiguous run of bins, an FP64
+// shuffle scan combines the lanes of a wavefront and one barrier the wavefronts.
 constexpr int kPrefixThreads = 256;
-// Pixels that the back projection's tail wavefronts add into (see back_tiling):
-// the last w0 columns of x (row sweeps) and the last h1 rows of part (column
-// sweeps), nch channels each; zero sizes when there is no such tail.
+// Pixels that the back projection adds into: the last w0 columns of x (row
+// sweeps) and the last h1 rows of part (column sweeps), nch channels each --
+// the tail pixels (see back_tiling), or every pixel when the main wavefronts'
+// views are split in two as well; zero sizes when there is none.
 struct TailClear {
     float* x;
     float* part;
@@ -218,17 +220,21 @@ __global__ __launch_bounds__(kPrefixThreads) void k_detector_prefix(const float*
     }
     const int slot = blockIdx.x, ch = blockIdx.y;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const float orient = view[slot].orient;
+    const bool rev = view[slot].orient < 0.0f;
     const float* s = sino + ((size_t)ch * V + vp_view(view[slot])) * B;
     const float* pa = path + (size_t)slot * B;
     DetEntry* dst = C + ((size_t)ch * V + slot) * det_row(B);
+    auto width = [&](int b) {                                     // b in row order, < B
+        const int k = rev ? B - 1 - b : b;
+        return (float)((double)s[k] * (double)pa[k]);
+    };
     __shared__ double wave_total[kPrefixThreads / 64];
     const int per = (B + kPrefixThreads - 1) / kPrefixThreads;
     const int b0 = threadIdx.x * per;
     double acc = 0.0;
     for (int i = 0; i < per; ++i) {
         const int b = b0 + i;
-        if (b < B) acc += (double)(orient * (float)((double)s[b] * (double)pa[b]));
+        if (b < B) acc += (double)width(b);
     }
     double inc = acc;                                             // inclusive scan over the wavefront
     for (int off = 1; off < 64; off <<= 1) {
@@ -239,12 +245,14 @@ __global__ __launch_bounds__(kPrefixThreads) void k_detector_prefix(const float*
     __syncthreads();
     double run = inc - acc;
     for (int w = 0; w < wave; ++w) run += wave_total[w];          // fixed order
+    float d = b0 < B ? width(b0) : 0.0f;
     for (int i = 0; i < per; ++i) {
         const int b = b0 + i;
         if (b < B) {
-            const float d = orient * (float)((double)s[b] * (double)pa[b]);
-            dst[b] = DetEntry{run, d, 0.0f};
+            const float dn = b + 1 < B ? width(b + 1) : 0.0f;
             run += (double)d;
+            dst[b] = DetEntry{run, d, dn};
+            d = dn;
         }
     }
     if (threadIdx.x == kPrefixThreads - 1) {                      // holds the total after its run
@@ -399,13 +407,6 @@ __global__ __launch_bounds__(kFwdWaves * 64) void k_dd_forward(const ViewParams*
     }
 }
 
-// One block: kWaves wavefronts x LPW adjacent sweep lines each, one segment of
-// 63 pixel edges; every wavefront walks all views of its frame.  Several lines
-// per wavefront give each wave LPW independent load chains per view, which is
-// what hides the memory latency, and let the whole launch fit in one round of
-// resident waves.  Row sweeps write x; column sweeps write their partial image
-// to part in the image's own layout (scattered 4-byte stores, once per pixel),
-// which the caller adds -- the iteration does it inside the penalty kernel.
 // One (sweep line, view) at along-line position K: byte offset of the edge's
 // detector entry and the fraction of its bin.  m = {n, m, c, a}, g: the line's
 // map coefficients; span = back_shift(B) (the clamp, symmetric about the
@@ -417,6 +418,34 @@ __device__ __forceinline__ void back_locate(const float4& m, float g, float K, f
     const float bf = __builtin_amdgcn_fmed3f(floorf(num * fast_rcp(den)), -span, span);
     off = (int)bf * (int)sizeof(DetEntry) + origin;          // entry in [0, B + 1]
     fr = __builtin_amdgcn_fmed3f(fmaf(-bf, den, num) * fmaf(-g, bf, m.w), 0.0f, 1.0f);
+}
+
+// Both edges of a lane on one (sweep line, view): edge A at K, edge B at K + 1.
+// The map increases with K, so edge B's bin is at least edge A's bin b0, and
+//   H(A) = C[b0+1] + (frA - 1) w[b0],
+//   H(B) = C[b0+1] + (f0 - 1) w[b0] + f1 w[b0+1]
+// with f0, f1 the clamped fractions of bins b0 and b0 + 1 covered up to edge B
+// (the projective fraction formula holds for any bin, so no second division);
+// one entry (C[b0+1], w[b0], w[b0+1]) serves both edges, and both FP32 parts
+// stay within one bin width.  When edge B lies past bin b0 + 1 (f1 reaches 1),
+// it is wide and takes its own entry.
+struct EdgePair {
+    int off;            // byte offset of the entry of b0
+    float frA, f0, f1;
+};
+__device__ __forceinline__ EdgePair back_pair(const float4& m, float g, float K, float span, int origin) {
+    EdgePair e;
+    const float den = fmaf(m.z, K, 1.0f);
+    const float num = fmaf(m.y, K, m.x);
+    const float bf = __builtin_amdgcn_fmed3f(floorf(num * fast_rcp(den)), -span, span);
+    e.off = (int)bf * (int)sizeof(DetEntry) + origin;
+    const float qa = fmaf(-g, bf, m.w);                        // bin b0's scale
+    e.frA = __builtin_amdgcn_fmed3f(fmaf(-bf, den, num) * qa, 0.0f, 1.0f);
+    const float denB = den + m.z, numB = num + m.y;             // at K + 1
+    const float n0 = fmaf(-bf, denB, numB);
+    e.f0 = __builtin_amdgcn_fmed3f(n0 * qa, 0.0f, 1.0f);
+    e.f1 = __builtin_amdgcn_fmed3f((n0 - denB) * (qa - g), 0.0f, 1.0f);
+    return e;
 }
 
 // The tail of every sweep line (see back_tiling): lane l of tail wavefront tw
@@ -481,9 +510,9 @@ __device__ __forceinline__ void back_tail(const float4* __restrict__ line_tab, i
             if (is + u >= is1) break;                          // uniform
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
-                acc[c] += h[u][c].c;
-                accw[c] = fmaf(fr[u], h[u][c].d, accw[c]);
-                keep(h[u][c].pad);
+                acc[c] += h[u][c].c;                           // C[b+1]
+                accw[c] += fmaf(fr[u], h[u][c].d, -h[u][c].d);  // (fr - 1) w[b]
+                keep(h[u][c].dn);
             }
         }
     }
@@ -499,11 +528,22 @@ __device__ __forceinline__ void back_tail(const float4* __restrict__ line_tab, i
     }
 }
 
+// One block: kWaves wavefronts x LPW adjacent sweep lines each, one segment of
+// kPerWave pixels (two edges per lane); every wavefront walks all views of its
+// frame.  Several lines per wavefront give each wave LPW independent load
+// chains per view, which is what hides the memory latency, and let the whole
+// launch fit in one round of resident waves.  Per lane, line and channel: the
+// FP64 sum over views of C[b0+1] and the FP32 sums of H(A) - C[b0+1] and
+// H(B) - C[b0+1]; the pixel between the lane's edges is the difference of the
+// two FP32 sums, the pixel after edge B takes the next lane's sums.  Row sweeps
+// write x; column sweeps write their partial image to part in the image's own
+// layout (scattered 4-byte stores, once per pixel), which the caller adds --
+// the iteration does it inside the penalty kernel.
 template <int NCH, int LPW, int U>
 __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__ line_tab, int nv0, int nv1,
                                                       FrameSplit fs, int nx, int ny, int V, int B,
                                                       const DetEntry* __restrict__ C, float* __restrict__ x,
-                                                      float* __restrict__ part) {
+                                                      float* __restrict__ part, int vsplit) {
     int frame, item;
     if (!decode_block(fs, frame, item)) return;
     const int Nq = frame ? nx : ny;
@@ -524,13 +564,19 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
         return;
     }
     item -= tail_items;
+    // with split views, items 2 i and 2 i + 1 take the two halves of item i
+    const int half = vsplit == 2 ? item & 1 : 0;
+    if (vsplit == 2) item >>= 1;
+    const int iv0 = half ? nv >> 1 : 0, iv1 = vsplit == 2 && !half ? nv >> 1 : nv;
+    if (iv0 >= iv1) return;                        // no views in this half (uniform)
+    const int sl0 = slot0 + iv0, nvh = iv1 - iv0;  // first slot and number of views taken
     const int segs = back_tiling(Np).full;
     const int seg = item % segs;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int q0 = ((item / segs) * kWaves + wave) * LPW;
     if (q0 >= Nq) return;                          // whole wavefront outside the image
-    const int pe = seg * kPerWave + lane;          // edge index; lanes past Np repeat edge Np
+    const int pe = seg * kPerWave + 2 * lane;      // edge A; lanes past Np repeat edge Np
     const float K = (float)min(pe, Np) - 0.5f * (float)Np;
     // first table entry of each line, kept in scalar registers
     int lt0[LPW];
@@ -539,14 +585,17 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
     const int shift = back_shift(B);
     const float span = (float)shift;               // bin index clamp, symmetric about the centre
     const int origin = shift * (int)sizeof(DetEntry);
-    double acc[LPW][NCH];                           // sum over views of C[b]
-    float accw[LPW][NCH];                           // sum over views of fraction x width
+    double acc[LPW][NCH];                           // sum over views of C[b0+1]
+    float wa[LPW][NCH], wb[LPW][NCH];               // sums over views of H(A) - C[b0+1], H(B) - C[b0+1]
+    double accw64[LPW][NCH];                        // the part of the latter from wide lanes' C[bB+1] - C[b0+1]
 #pragma unroll
     for (int j = 0; j < LPW; ++j)
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             acc[j][c] = 0.0;
-            accw[j][c] = 0.0f;
+            accw64[j][c] = 0.0;
+            wa[j][c] = 0.0f;
+            wb[j][c] = 0.0f;
         }
     // Software pipeline over groups of U views: the per-line tables of the next
     // group are requested (scalar loads) only after this group's values are in
@@ -557,7 +606,7 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
     auto fetch = [&](int is) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int slot = slot0 + min(is + u, nv - 1);
+            const int slot = sl0 + min(is + u, nvh - 1);
 #pragma unroll
             for (int j = 0; j < LPW; ++j) {
                 tm[u][j] = line_tab[lt0[j] + 2 * slot];                                          // {n, m, c, a}
@@ -565,23 +614,59 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
             }
         }
     };
+    // One view's contribution from its edge pair, the entry h of b0 and, for a
+    // wide lane, edge B's own entry hw (of bin bB) and fraction frw: H(B) -
+    // C[b0+1] is then (C[bB+1] - C[b0+1]) + (frw - 1) w[bB] instead of the two
+    // pieces, the difference of cumulative values summed in FP64 on its own.
+    // any_wide (uniform) skips the correction in wavefronts without wide lanes.
+    auto add_view = [&](int j, int c, const EdgePair& e, const DetValue& h, bool any_wide, bool wide,
+                        const DetValue& hw, float frw) {
+        acc[j][c] += h.c;
+        wa[j][c] += fmaf(e.frA, h.d, -h.d);
+        float tb = fmaf(e.f1, h.dn, fmaf(e.f0, h.d, -h.d));
+        if (any_wide) {
+            if (wide) {
+                tb = fmaf(frw, hw.d, -hw.d);
+                accw64[j][c] += hw.c - h.c;
+            }
+            keep(hw.dn);
+        }
+        wb[j][c] += tb;
+    };
     fetch(0);
-    const int nfull = nv - nv % U;
+    const int nfull = nvh - nvh % U;
     int is = 0;
     for (; is < nfull; is += U) {          // trip counts are uniform over the wavefront
-        int off[U][LPW];
-        float frs[U][LPW];
+        EdgePair ep[U][LPW];
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int j = 0; j < LPW; ++j) back_locate(tm[u][j], tg[u][j], K, span, origin, off[u][j], frs[u][j]);
+            for (int j = 0; j < LPW; ++j) ep[u][j] = back_pair(tm[u][j], tg[u][j], K, span, origin);
         DetValue h[U][LPW][NCH];
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int j = 0; j < LPW; ++j)
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) h[u][j][c] = load_det(tc, off[u][j], (c * V + slot0 + is + u) * row);
+                for (int c = 0; c < NCH; ++c) h[u][j][c] = load_det(tc, ep[u][j].off, (c * V + sl0 + is + u) * row);
+        // wide lanes: edge B's own bin, entry and fraction (skipped by wavefronts without any)
+        bool wide[U][LPW], any_wide[U][LPW];
+        DetValue hw[U][LPW][NCH];
+        float frw[U][LPW];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < LPW; ++j) {
+                wide[u][j] = ep[u][j].f1 >= 1.0f;
+                any_wide[u][j] = __builtin_amdgcn_ballot_w64(wide[u][j]) != 0;
+                frw[u][j] = 0.0f;
+                if (wide[u][j]) {
+                    int o;
+                    back_locate(tm[u][j], tg[u][j], K + 1.0f, span, origin, o, frw[u][j]);
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c) hw[u][j][c] = load_det(tc, o, (c * V + sl0 + is + u) * row);
+                }
+            }
         __builtin_amdgcn_sched_barrier(0);
         fetch(is + U);
         __builtin_amdgcn_sched_barrier(0);
@@ -590,26 +675,27 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
 #pragma unroll
             for (int j = 0; j < LPW; ++j)
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) {
-                    acc[j][c] += h[u][j][c].c;
-                    accw[j][c] = fmaf(frs[u][j], h[u][j][c].d, accw[j][c]);
-                    keep(h[u][j][c].pad);
-                }
+                for (int c = 0; c < NCH; ++c)
+                    add_view(j, c, ep[u][j], h[u][j][c], any_wide[u][j], wide[u][j], hw[u][j][c], frw[u][j]);
     }
     // the remaining views (fewer than U); their tables were fetched into slots 0..
 #pragma unroll
     for (int u = 0; u < U - 1; ++u) {
-        if (nfull + u >= nv) break;        // uniform
+        if (nfull + u >= nvh) break;       // uniform
 #pragma unroll
         for (int j = 0; j < LPW; ++j) {
-            int o;
-            float fr;
-            back_locate(tm[u][j], tg[u][j], K, span, origin, o, fr);
+            const EdgePair e = back_pair(tm[u][j], tg[u][j], K, span, origin);
+            const bool wd = e.f1 >= 1.0f;
+            int o = 0;
+            float frw = 0.0f;
+            if (wd) back_locate(tm[u][j], tg[u][j], K + 1.0f, span, origin, o, frw);
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
-                const DetValue h = load_det(tc, o, (c * V + slot0 + nfull + u) * row);
-                acc[j][c] += h.c;
-                accw[j][c] = fmaf(fr, h.d, accw[j][c]);
+                const int rc = (c * V + sl0 + nfull + u) * row;
+                const DetValue h = load_det(tc, e.off, rc);
+                DetValue hw = h;
+                if (wd) hw = load_det(tc, o, rc);
+                add_view(j, c, e, h, true, wd, hw, frw);
             }
         }
     }
@@ -617,15 +703,35 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
     float* dst = frame ? part : x;
 #pragma unroll
     for (int j = 0; j < LPW; ++j) {
-        float val[NCH];
+        if (q0 + j >= Nq) break;           // uniform
+        float va[NCH], vb[NCH];
 #pragma unroll
-        for (int c = 0; c < NCH; ++c)
-            val[c] = (float)((next_lane(acc[j][c]) - acc[j][c]) + (double)(next_lane(accw[j][c]) - accw[j][c]));
-        if (lane < kPerWave && pe < Np && q0 + j < Nq) {
-            // image layout: rows sweep (iy = q, ix = pe), columns sweep (iy = pe, ix = q)
-            const size_t pix = frame ? (size_t)pe * nx + (q0 + j) : (size_t)(q0 + j) * nx + pe;
+        for (int c = 0; c < NCH; ++c) {
+            va[c] = (float)(accw64[j][c] + (double)(wb[j][c] - wa[j][c]));
+            vb[c] = (float)(((next_lane(acc[j][c]) - acc[j][c]) - accw64[j][c]) +
+                            (double)(next_lane(wa[j][c]) - wb[j][c]));
+        }
+        // image layout: rows sweep (iy = q, ix = p), columns sweep (iy = p, ix = q)
+        const size_t pix_a = frame ? (size_t)pe * nx + (q0 + j) : (size_t)(q0 + j) * nx + pe;
+        const size_t step = frame ? (size_t)nx : 1;
+        if (vsplit == 2) {                 // onto the cleared image (uniform)
+            if (pe < Np) {
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) dst[c * img_stride + pix] = val[c];
+                for (int c = 0; c < NCH; ++c) unsafeAtomicAdd(&dst[c * img_stride + pix_a], va[c]);
+            }
+            if (lane < 63 && pe + 1 < Np) {
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) unsafeAtomicAdd(&dst[c * img_stride + pix_a + step], vb[c]);
+            }
+        } else {
+            if (pe < Np) {
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) dst[c * img_stride + pix_a] = va[c];
+            }
+            if (lane < 63 && pe + 1 < Np) {
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) dst[c * img_stride + pix_a + step] = vb[c];
+            }
         }
     }
 }
@@ -715,14 +821,14 @@ double back_cost(long long waves, int per_round, int lpw, int simds) {
 }
 
 template <int NCH, int LPW, int U>
-void back_kernel_launch(const GeomTables& t, float* x, hipStream_t s) {
+void back_kernel_launch(const GeomTables& t, float* x, hipStream_t s, int vsplit) {
     const int nv0 = t.n_frame_views[0], nv1 = t.n_frame_views[1];
-    const int u0 = nv0 ? back_main_items(t.nx, t.ny, LPW) + back_tail_items(t.nx, t.ny) : 0;
-    const int u1 = nv1 ? back_main_items(t.ny, t.nx, LPW) + back_tail_items(t.ny, t.nx) : 0;
+    const int u0 = nv0 ? vsplit * back_main_items(t.nx, t.ny, LPW) + back_tail_items(t.nx, t.ny) : 0;
+    const int u1 = nv1 ? vsplit * back_main_items(t.ny, t.nx, LPW) + back_tail_items(t.ny, t.nx) : 0;
     const FrameSplit fs = split(u0, u1);
     KernelTimer kt_("k_dd_back", s);
     hipLaunchKernelGGL((k_dd_back<NCH, LPW, U>), dim3(grid_blocks(fs)), dim3(kThreads), 0, s, t.back_line, nv0, nv1, fs,
-                       t.nx, t.ny, t.V, t.B, t.det_prefix, x, t.back_part);
+                       t.nx, t.ny, t.V, t.B, t.det_prefix, x, t.back_part, vsplit);
     kt_.stop();
 }
 
@@ -731,34 +837,45 @@ void back_kernel_launch(const GeomTables& t, float* x, hipStream_t s) {
 template <int NCH>
 const float* back_launch(const GeomTables& t, const float* sino, float* x, hipStream_t s) {
     const int nv0 = t.n_frame_views[0], nv1 = t.n_frame_views[1];
-    // The detector prefix, which also clears the pixels the tail wavefronts add
-    // into, precedes every back projection kernel (the tuner's too).
-    auto prefix = [&]() {
+    // The detector prefix, which also clears the pixels the kernel adds into
+    // (the tail's, or all with split views), precedes every back projection
+    // kernel (the tuner's too).
+    auto prefix = [&](int vsplit) {
         KernelTimer kt_("k_detector_prefix", s);
         const BackTiling b0 = back_tiling(t.nx), b1 = back_tiling(t.ny);
-        const TailClear clr{x, t.back_part, t.nx, t.ny, nv0 && b0.tail_lines ? t.nx - b0.full * kPerWave : 0,
-                            nv1 && b1.tail_lines ? t.ny - b1.full * kPerWave : 0, NCH};
+        const int w0 = !nv0 ? 0 : vsplit == 2 ? t.nx : b0.tail_lines ? t.nx - b0.full * kPerWave : 0;
+        const int h1 = !nv1 ? 0 : vsplit == 2 ? t.ny : b1.tail_lines ? t.ny - b1.full * kPerWave : 0;
+        const TailClear clr{x, t.back_part, t.nx, t.ny, w0, h1, NCH};
         hipLaunchKernelGGL(k_detector_prefix, dim3(t.V, NCH), dim3(kPrefixThreads), 0, s, sino, t.path, t.view,
                            t.V, t.B, t.det_prefix, clr);
         kt_.stop();
         MBMD_LAUNCHED();
     };
     if (!nv0) launch_fill(NCH * t.nx * t.ny, x, 0.0f, s);
-    // Tile shape: lines per wavefront x views in flight.  The first back
-    // projection of a geometry and channel count outside graph capture times
-    // the candidates on its own inputs (they give bit-identical results: the
-    // order of the sums over views is the same) and keeps the fastest; under
-    // capture, or when tuning is switched off, a round-count cost model picks.
-    using Launch = void (*)(const GeomTables&, float*, hipStream_t);
+    // Tile shape: lines per wavefront x views in flight, and whether each
+    // wavefront's views are split in two halves (twice the wavefronts, each
+    // half added onto the cleared image: two additions onto zero give the same
+    // result in either order).  Shapes with the same split give bit-identical
+    // results (the order of the sums over views is the same); split and
+    // unsplit ones agree up to rounding.  The first back projection of a
+    // geometry and channel count outside graph capture times the candidates on
+    // its own inputs and keeps the fastest; under capture, or when tuning is
+    // switched off, a round-count cost model picks between unsplit shapes.
+    using Launch = void (*)(const GeomTables&, float*, hipStream_t, int);
+    struct Cand {
+        Launch fn;
+        int vsplit;
+    };
     constexpr int N2 = NCH <= 2 ? NCH : 1;
-    const Launch cand[3] = {back_kernel_launch<NCH, 1, 2>, back_kernel_launch<NCH, 1, 4>,
-                            back_kernel_launch<N2, 2, 2>};
+    const Cand cand[5] = {{back_kernel_launch<NCH, 1, 2>, 1}, {back_kernel_launch<NCH, 1, 4>, 1},
+                          {back_kernel_launch<N2, 2, 2>, 1},  {back_kernel_launch<NCH, 1, 2>, 2},
+                          {back_kernel_launch<N2, 1, 4>, 2}};
     auto run = [&](int v) {
-        prefix();
-        cand[v](t, x, s);
+        prefix(cand[v].vsplit);
+        cand[v].fn(t, x, s, cand[v].vsplit);
         MBMD_LAUNCHED();
     };
-    const int n_cand = NCH <= 2 ? 3 : 2;
+    const int n_cand = NCH <= 2 ? 5 : 2;
     int& choice = t.back_variant[NCH];
     const int forced = forced_back_variant();
     if (forced >= 0 && forced < n_cand) {           // testing hook: no tuning, nothing cached
@@ -772,20 +889,24 @@ const float* back_launch(const GeomTables& t, const float* sino, float* x, hipSt
             hipEvent_t ev[2];
             MBMD_HIP(hipEventCreate(&ev[0]));
             MBMD_HIP(hipEventCreate(&ev[1]));
-            float best = 1e30f;
-            for (int v = 0; v < n_cand; ++v) {
-                run(v);                                // warm-up
-                MBMD_HIP(hipEventRecord(ev[0], s));
-                for (int r = 0; r < 3; ++r) run(v);     // the prefix is the same for every candidate
-                MBMD_HIP(hipEventRecord(ev[1], s));
-                MBMD_HIP(hipEventSynchronize(ev[1]));
-                float ms = 0.0f;
-                MBMD_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
-                if (ms < best) {
-                    best = ms;
-                    choice = v;
+            // Candidates interleaved over several rounds, each keeping its best
+            // round: the shapes are often within a few per cent of each other,
+            // closer than the spread of back-to-back launches.
+            float best[5] = {1e30f, 1e30f, 1e30f, 1e30f, 1e30f};
+            for (int v = 0; v < n_cand; ++v) run(v);  // warm-up
+            for (int round = 0; round < 4; ++round)
+                for (int v = 0; v < n_cand; ++v) {
+                    MBMD_HIP(hipEventRecord(ev[0], s));
+                    for (int r = 0; r < 2; ++r) run(v);  // the prefix is the same for every candidate
+                    MBMD_HIP(hipEventRecord(ev[1], s));
+                    MBMD_HIP(hipEventSynchronize(ev[1]));
+                    float ms = 0.0f;
+                    MBMD_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+                    if (ms < best[v]) best[v] = ms;
                 }
-            }
+            choice = 0;
+            for (int v = 1; v < n_cand; ++v)
+                if (best[v] < best[choice]) choice = v;
             (void)hipEventDestroy(ev[0]);
             (void)hipEventDestroy(ev[1]);
         } else {

@@ -156,20 +156,31 @@ def test_nonzero_count_matches_oracle(name):
     assert abs(got - want) <= 5e-3 * want, (got, want)
 
 
+# Tile shapes the autotuner may pick, by channel count: whether each shape
+# splits its wavefronts' views in two halves (the halves are added onto a
+# cleared image).
+SPLIT_OF_SHAPE = {True: [False, False, False, True, True], False: [False, False]}
+
+
 @pytest.mark.parametrize("nch", [1, 2, 3])
 def test_back_projector_tile_shapes_agree(nch, monkeypatch):
-    """Every tile shape the autotuner may pick (lines per wavefront x views in
-    flight) sums each pixel's views in the same order, so their outputs are
-    bitwise equal; and they match the oracle."""
+    """Tile shapes with the same view split (lines per wavefront x views in
+    flight) sum each pixel's views in the same order, so their outputs are
+    bitwise equal; every shape matches the oracle."""
     g = GEOMS["fan_ragged"]
     s = np.random.default_rng(7).uniform(size=(nch, g["n_views"], g["n_bins"]))
     sd = dev(s)
+    want = OP.backproject(g, s)
+    splits = SPLIT_OF_SHAPE[nch <= 2]
     outs = []
-    for v in range(3 if nch <= 2 else 2):
+    for v in range(len(splits)):
         monkeypatch.setenv("MBMD_BACK_VARIANT", str(v))
         announce("back tile shape", nch, v)
         outs.append(host(mb.backproject(g, sd)))
     monkeypatch.delenv("MBMD_BACK_VARIANT")
-    for o in outs[1:]:
-        np.testing.assert_array_equal(o, outs[0])
-    assert maxrel(outs[0], OP.backproject(g, s)) <= TOL_PROJ
+    for sp in (False, True):
+        group = [o for o, f in zip(outs, splits) if f == sp]
+        for o in group[1:]:
+            np.testing.assert_array_equal(o, group[0])
+    for o in outs:
+        assert maxrel(o, want) <= TOL_PROJ
