@@ -55,20 +55,22 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr int kPerWave = 127;                // pixels per wavefront of the back projection (two edges per lane)
+// Pixels per wavefront of the back projection's main path: 63 with one pixel
+// edge per lane, 127 with two.
+__host__ __device__ constexpr int back_ppw(int epl) { return epl == 2 ? 127 : 63; }
 
 // Back projection tiling of a sweep line of Np pixels (Np + 1 edges): full
-// segments of kPerWave pixels, then the pixels left over (Np mod kPerWave) as a
-// tail of tail_edges edges, packed tail_lines lines per wavefront -- one
-// wavefront per line there would spend a whole wavefront's time on a handful of
-// lanes.  A tail that would not fit two lines per wavefront is an ordinary
-// partial segment instead (counted in full; lanes past the last edge repeat it).
+// segments of ppw pixels, then the pixels left over (Np mod ppw) as a tail of
+// tail_edges edges, packed tail_lines lines per wavefront -- one wavefront per
+// line there would spend a whole wavefront's time on a handful of lanes.  A
+// tail that would not fit two lines per wavefront is an ordinary partial
+// segment instead (counted in full; lanes past the last edge repeat it).
 struct BackTiling {
     int full, tail_edges, tail_lines;
 };
-__host__ __device__ inline BackTiling back_tiling(int Np) {
-    BackTiling b{Np / kPerWave, 0, 0};
-    const int rem = Np - b.full * kPerWave;
+__host__ __device__ inline BackTiling back_tiling(int Np, int ppw) {
+    BackTiling b{Np / ppw, 0, 0};
+    const int rem = Np - b.full * ppw;
     if (rem > 0) {
         b.tail_edges = rem + 1;
         b.tail_lines = 64 / b.tail_edges;
@@ -77,13 +79,13 @@ __host__ __device__ inline BackTiling back_tiling(int Np) {
     return b;
 }
 // Blocks (kWaves wavefronts) of one sweep frame: the tail, then segments x line groups.
-__host__ __device__ inline int back_main_items(int Np, int Nq, int lpw) {
-    return back_tiling(Np).full * ((Nq + kWaves * lpw - 1) / (kWaves * lpw));
+__host__ __device__ inline int back_main_items(int Np, int Nq, int lpw, int ppw) {
+    return back_tiling(Np, ppw).full * ((Nq + kWaves * lpw - 1) / (kWaves * lpw));
 }
 // Tail blocks: each tail wavefront's views are split into two halves (items
 // 2 i and 2 i + 1), whose pixel values are added onto the cleared tail pixels.
-__host__ __device__ inline int back_tail_items(int Np, int Nq) {
-    const BackTiling b = back_tiling(Np);
+__host__ __device__ inline int back_tail_items(int Np, int Nq, int ppw) {
+    const BackTiling b = back_tiling(Np, ppw);
     if (!b.tail_lines) return 0;
     const int waves = (Nq + b.tail_lines - 1) / b.tail_lines;
     return 2 * ((waves + kWaves - 1) / kWaves);
@@ -449,7 +451,7 @@ __device__ __forceinline__ EdgePair back_pair(const float4& m, float g, float K,
 }
 
 // The tail of every sweep line (see back_tiling): lane l of tail wavefront tw
-// takes edge full*kPerWave + l mod E of line tw*LT + l / E, so each lane reads
+// takes edge full*ppw + l mod E of line tw*LT + l / E, so each lane reads
 // its own line's coefficients (vector loads: LT distinct addresses per
 // wavefront).  Views [is0, is1) go in groups of UT with the next group's
 // coefficients in flight while this group's detector entries arrive, summed in
@@ -459,17 +461,17 @@ __device__ __forceinline__ EdgePair back_pair(const float4& m, float g, float K,
 // order.
 template <int NCH>
 __device__ __forceinline__ void back_tail(const float4* __restrict__ line_tab, int tw, int is0, int is1, int slot0,
-                                          int Np, int Nq, int V, int B, int frame, int nx, int ny,
+                                          int Np, int Nq, int V, int B, int frame, int nx, int ny, int ppw,
                                           const __amdgpu_buffer_rsrc_t& tc, int row, float* __restrict__ dst) {
     constexpr int UT = NCH <= 2 ? 4 : 2;   // keeps the tail within the main path's registers
     if (is0 >= is1) return;                // no views in this half (uniform)
-    const BackTiling bt = back_tiling(Np);
+    const BackTiling bt = back_tiling(Np, ppw);
     const int E = bt.tail_edges, LT = bt.tail_lines;
     const int lane = threadIdx.x & 63;
     const int ql = lane / E, el = lane - ql * E;
     const int q = tw * LT + ql;
     const bool lane_ok = ql < LT && q < Nq;
-    const int pe = min(bt.full * kPerWave + el, Np);
+    const int pe = min(bt.full * ppw + el, Np);
     const float K = (float)pe - 0.5f * (float)Np;
     const float4* lt = line_tab + (size_t)min(q, Nq - 1) * V * 2;
     const float* ltf = reinterpret_cast<const float*>(lt);
@@ -529,17 +531,21 @@ __device__ __forceinline__ void back_tail(const float4* __restrict__ line_tab, i
 }
 
 // One block: kWaves wavefronts x LPW adjacent sweep lines each, one segment of
-// kPerWave pixels (two edges per lane); every wavefront walks all views of its
-// frame.  Several lines per wavefront give each wave LPW independent load
-// chains per view, which is what hides the memory latency, and let the whole
-// launch fit in one round of resident waves.  Per lane, line and channel: the
-// FP64 sum over views of C[b0+1] and the FP32 sums of H(A) - C[b0+1] and
-// H(B) - C[b0+1]; the pixel between the lane's edges is the difference of the
-// two FP32 sums, the pixel after edge B takes the next lane's sums.  Row sweeps
-// write x; column sweeps write their partial image to part in the image's own
-// layout (scattered 4-byte stores, once per pixel), which the caller adds --
-// the iteration does it inside the penalty kernel.
-template <int NCH, int LPW, int U>
+// back_ppw(EPL) pixels (EPL edges per lane); every wavefront walks all views of
+// its frame, or one half of them.  Several lines per wavefront give each wave
+// LPW independent load chains per view, which is what hides the memory
+// latency.  EPL = 1: per lane, line and channel, the FP64 sum over views of
+// C[b+1] and the FP32 sum of (fr - 1) w[b] at the lane's edge; the pixel is the
+// difference of the next lane's sums and its own.  EPL = 2: the FP64 sum over
+// views of C[b0+1] and the FP32 sums of H(A) - C[b0+1] and H(B) - C[b0+1]; the
+// pixel between the lane's edges is the difference of the two FP32 sums, the
+// pixel after edge B takes the next lane's sums.  Two edges per lane halve the
+// gathers and the locate work of edge B; one edge per lane gives twice the
+// wavefronts and fewer registers, which small images with several channels
+// need.  Row sweeps write x; column sweeps write their partial image to part in
+// the image's own layout (scattered 4-byte stores, once per pixel), which the
+// caller adds -- the iteration does it inside the penalty kernel.
+template <int NCH, int LPW, int U, int EPL>
 __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__ line_tab, int nv0, int nv1,
                                                       FrameSplit fs, int nx, int ny, int V, int B,
                                                       const DetEntry* __restrict__ C, float* __restrict__ x,
@@ -554,13 +560,14 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
     const __amdgpu_buffer_rsrc_t tc = rsrc(C, (size_t)row * NCH * V);
     // the tail items come first: their wavefronts are the longest, so they are
     // dispatched before the main ones fill the machine
-    const int tail_items = back_tail_items(Np, Nq);
+    constexpr int PPW = back_ppw(EPL);
+    const int tail_items = back_tail_items(Np, Nq, PPW);
     if (item < tail_items) {
         const int tw = (item >> 1) * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        if (tw * back_tiling(Np).tail_lines >= Nq) return;      // whole wavefront past the last line
+        if (tw * back_tiling(Np, PPW).tail_lines >= Nq) return;      // whole wavefront past the last line
         const int mid = nv >> 1;
         back_tail<NCH>(line_tab, tw, (item & 1) ? mid : 0, (item & 1) ? nv : mid, slot0, Np, Nq, V, B, frame, nx,
-                       ny, tc, row, frame ? part : x);
+                       ny, PPW, tc, row, frame ? part : x);
         return;
     }
     item -= tail_items;
@@ -570,13 +577,13 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
     const int iv0 = half ? nv >> 1 : 0, iv1 = vsplit == 2 && !half ? nv >> 1 : nv;
     if (iv0 >= iv1) return;                        // no views in this half (uniform)
     const int sl0 = slot0 + iv0, nvh = iv1 - iv0;  // first slot and number of views taken
-    const int segs = back_tiling(Np).full;
+    const int segs = back_tiling(Np, PPW).full;
     const int seg = item % segs;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int q0 = ((item / segs) * kWaves + wave) * LPW;
     if (q0 >= Nq) return;                          // whole wavefront outside the image
-    const int pe = seg * kPerWave + 2 * lane;      // edge A; lanes past Np repeat edge Np
+    const int pe = seg * PPW + EPL * lane;         // (first) edge; lanes past Np repeat edge Np
     const float K = (float)min(pe, Np) - 0.5f * (float)Np;
     // first table entry of each line, kept in scalar registers
     int lt0[LPW];
@@ -585,18 +592,8 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
     const int shift = back_shift(B);
     const float span = (float)shift;               // bin index clamp, symmetric about the centre
     const int origin = shift * (int)sizeof(DetEntry);
-    double acc[LPW][NCH];                           // sum over views of C[b0+1]
-    float wa[LPW][NCH], wb[LPW][NCH];               // sums over views of H(A) - C[b0+1], H(B) - C[b0+1]
-    double accw64[LPW][NCH];                        // the part of the latter from wide lanes' C[bB+1] - C[b0+1]
-#pragma unroll
-    for (int j = 0; j < LPW; ++j)
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            acc[j][c] = 0.0;
-            accw64[j][c] = 0.0;
-            wa[j][c] = 0.0f;
-            wb[j][c] = 0.0f;
-        }
+    const size_t img_stride = (size_t)nx * ny;
+    float* dst = frame ? part : x;
     // Software pipeline over groups of U views: the per-line tables of the next
     // group are requested (scalar loads) only after this group's values are in
     // registers -- scalar loads complete out of order, so a wait for one waits
@@ -614,6 +611,96 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
             }
         }
     };
+    const int nfull = nvh - nvh % U;
+    if constexpr (EPL == 1) {
+        double acc[LPW][NCH];                       // sum over views of C[b+1]
+        float accw[LPW][NCH];                       // sum over views of (fr - 1) w[b]
+#pragma unroll
+        for (int j = 0; j < LPW; ++j)
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                acc[j][c] = 0.0;
+                accw[j][c] = 0.0f;
+            }
+        fetch(0);
+        for (int is = 0; is < nfull; is += U) {   // trip counts are uniform over the wavefront
+            int off[U][LPW];
+            float frs[U][LPW];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int j = 0; j < LPW; ++j) back_locate(tm[u][j], tg[u][j], K, span, origin, off[u][j], frs[u][j]);
+            DetValue h[U][LPW][NCH];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int j = 0; j < LPW; ++j)
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c) h[u][j][c] = load_det(tc, off[u][j], (c * V + sl0 + is + u) * row);
+            __builtin_amdgcn_sched_barrier(0);
+            fetch(is + U);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int j = 0; j < LPW; ++j)
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c) {
+                        acc[j][c] += h[u][j][c].c;
+                        accw[j][c] += fmaf(frs[u][j], h[u][j][c].d, -h[u][j][c].d);
+                        keep(h[u][j][c].dn);
+                    }
+        }
+        // the remaining views (fewer than U); their tables were fetched into slots 0..
+#pragma unroll
+        for (int u = 0; u < U - 1; ++u) {
+            if (nfull + u >= nvh) break;   // uniform
+#pragma unroll
+            for (int j = 0; j < LPW; ++j) {
+                int o;
+                float fr;
+                back_locate(tm[u][j], tg[u][j], K, span, origin, o, fr);
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    const DetValue h = load_det(tc, o, (c * V + sl0 + nfull + u) * row);
+                    acc[j][c] += h.c;
+                    accw[j][c] += fmaf(fr, h.d, -h.d);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < LPW; ++j) {
+            if (q0 + j >= Nq) break;       // uniform
+            float val[NCH];
+#pragma unroll
+            for (int c = 0; c < NCH; ++c)
+                val[c] = (float)((next_lane(acc[j][c]) - acc[j][c]) + (double)(next_lane(accw[j][c]) - accw[j][c]));
+            if (lane < 63 && pe < Np) {
+                // image layout: rows sweep (iy = q, ix = p), columns sweep (iy = p, ix = q)
+                const size_t pix = frame ? (size_t)pe * nx + (q0 + j) : (size_t)(q0 + j) * nx + pe;
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    if (vsplit == 2)
+                        unsafeAtomicAdd(&dst[c * img_stride + pix], val[c]);
+                    else
+                        dst[c * img_stride + pix] = val[c];
+                }
+            }
+        }
+        return;
+    }
+    double acc[LPW][NCH];                           // sum over views of C[b0+1]
+    float wa[LPW][NCH], wb[LPW][NCH];               // sums over views of H(A) - C[b0+1], H(B) - C[b0+1]
+    double accw64[LPW][NCH];                        // the part of the latter from wide lanes' C[bB+1] - C[b0+1]
+#pragma unroll
+    for (int j = 0; j < LPW; ++j)
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            acc[j][c] = 0.0;
+            accw64[j][c] = 0.0;
+            wa[j][c] = 0.0f;
+            wb[j][c] = 0.0f;
+        }
     // One view's contribution from its edge pair, the entry h of b0 and, for a
     // wide lane, edge B's own entry hw (of bin bB) and fraction frw: H(B) -
     // C[b0+1] is then (C[bB+1] - C[b0+1]) + (frw - 1) w[bB] instead of the two
@@ -634,9 +721,7 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
         wb[j][c] += tb;
     };
     fetch(0);
-    const int nfull = nvh - nvh % U;
-    int is = 0;
-    for (; is < nfull; is += U) {          // trip counts are uniform over the wavefront
+    for (int is = 0; is < nfull; is += U) {   // trip counts are uniform over the wavefront
         EdgePair ep[U][LPW];
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -699,8 +784,6 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
             }
         }
     }
-    const size_t img_stride = (size_t)nx * ny;
-    float* dst = frame ? part : x;
 #pragma unroll
     for (int j = 0; j < LPW; ++j) {
         if (q0 + j >= Nq) break;           // uniform
@@ -771,7 +854,7 @@ void fwd_launch(const GeomTables& t, float* sino, hipStream_t s) {
     MBMD_LAUNCHED();
 }
 
-// Wavefronts of k_dd_back<NCH, LPW, 2> resident on the whole device at once.
+// Wavefronts of k_dd_back<NCH, LPW, 2, 2> resident on the whole device at once.
 template <int NCH, int LPW>
 int back_waves_per_round() {
     static int cached[kMaxGpus] = {};
@@ -781,7 +864,7 @@ int back_waves_per_round() {
     if (!cached[dev]) {
         int cus = 0, occ = 0;
         MBMD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        MBMD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_dd_back<NCH, LPW, 2>, kThreads, 0));
+        MBMD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_dd_back<NCH, LPW, 2, 2>, kThreads, 0));
         cached[dev] = (cus > 0 ? cus : 1) * (occ > 0 ? occ : 1) * kWaves;
     }
     return cached[dev];
@@ -820,15 +903,16 @@ double back_cost(long long waves, int per_round, int lpw, int simds) {
     return t;
 }
 
-template <int NCH, int LPW, int U>
+template <int NCH, int LPW, int U, int EPL>
 void back_kernel_launch(const GeomTables& t, float* x, hipStream_t s, int vsplit) {
     const int nv0 = t.n_frame_views[0], nv1 = t.n_frame_views[1];
-    const int u0 = nv0 ? vsplit * back_main_items(t.nx, t.ny, LPW) + back_tail_items(t.nx, t.ny) : 0;
-    const int u1 = nv1 ? vsplit * back_main_items(t.ny, t.nx, LPW) + back_tail_items(t.ny, t.nx) : 0;
+    constexpr int ppw = back_ppw(EPL);
+    const int u0 = nv0 ? vsplit * back_main_items(t.nx, t.ny, LPW, ppw) + back_tail_items(t.nx, t.ny, ppw) : 0;
+    const int u1 = nv1 ? vsplit * back_main_items(t.ny, t.nx, LPW, ppw) + back_tail_items(t.ny, t.nx, ppw) : 0;
     const FrameSplit fs = split(u0, u1);
     KernelTimer kt_("k_dd_back", s);
-    hipLaunchKernelGGL((k_dd_back<NCH, LPW, U>), dim3(grid_blocks(fs)), dim3(kThreads), 0, s, t.back_line, nv0, nv1, fs,
-                       t.nx, t.ny, t.V, t.B, t.det_prefix, x, t.back_part, vsplit);
+    hipLaunchKernelGGL((k_dd_back<NCH, LPW, U, EPL>), dim3(grid_blocks(fs)), dim3(kThreads), 0, s, t.back_line, nv0,
+                       nv1, fs, t.nx, t.ny, t.V, t.B, t.det_prefix, x, t.back_part, vsplit);
     kt_.stop();
 }
 
@@ -840,11 +924,11 @@ const float* back_launch(const GeomTables& t, const float* sino, float* x, hipSt
     // The detector prefix, which also clears the pixels the kernel adds into
     // (the tail's, or all with split views), precedes every back projection
     // kernel (the tuner's too).
-    auto prefix = [&](int vsplit) {
+    auto prefix = [&](int vsplit, int ppw) {
         KernelTimer kt_("k_detector_prefix", s);
-        const BackTiling b0 = back_tiling(t.nx), b1 = back_tiling(t.ny);
-        const int w0 = !nv0 ? 0 : vsplit == 2 ? t.nx : b0.tail_lines ? t.nx - b0.full * kPerWave : 0;
-        const int h1 = !nv1 ? 0 : vsplit == 2 ? t.ny : b1.tail_lines ? t.ny - b1.full * kPerWave : 0;
+        const BackTiling b0 = back_tiling(t.nx, ppw), b1 = back_tiling(t.ny, ppw);
+        const int w0 = !nv0 ? 0 : vsplit == 2 ? t.nx : b0.tail_lines ? t.nx - b0.full * ppw : 0;
+        const int h1 = !nv1 ? 0 : vsplit == 2 ? t.ny : b1.tail_lines ? t.ny - b1.full * ppw : 0;
         const TailClear clr{x, t.back_part, t.nx, t.ny, w0, h1, NCH};
         hipLaunchKernelGGL(k_detector_prefix, dim3(t.V, NCH), dim3(kPrefixThreads), 0, s, sino, t.path, t.view,
                            t.V, t.B, t.det_prefix, clr);
@@ -852,30 +936,42 @@ const float* back_launch(const GeomTables& t, const float* sino, float* x, hipSt
         MBMD_LAUNCHED();
     };
     if (!nv0) launch_fill(NCH * t.nx * t.ny, x, 0.0f, s);
-    // Tile shape: lines per wavefront x views in flight, and whether each
-    // wavefront's views are split in two halves (twice the wavefronts, each
-    // half added onto the cleared image: two additions onto zero give the same
-    // result in either order).  Shapes with the same split give bit-identical
-    // results (the order of the sums over views is the same); split and
-    // unsplit ones agree up to rounding.  The first back projection of a
-    // geometry and channel count outside graph capture times the candidates on
-    // its own inputs and keeps the fastest; under capture, or when tuning is
-    // switched off, a round-count cost model picks between unsplit shapes.
+    // Tile shape: edges per lane, lines per wavefront x views in flight, and
+    // whether each wavefront's views are split in two halves (twice the
+    // wavefronts, each half added onto the cleared image: two additions onto
+    // zero give the same result in either order).  Shapes with the same edges
+    // per lane and split give bit-identical results (the order of the sums over
+    // views is the same); the others agree up to rounding.  The first back
+    // projection of a geometry and channel count outside graph capture times
+    // the candidates on its own inputs and keeps the fastest; under capture, or
+    // when tuning is switched off, a round-count cost model picks between
+    // unsplit two-edge shapes.
     using Launch = void (*)(const GeomTables&, float*, hipStream_t, int);
     struct Cand {
         Launch fn;
-        int vsplit;
+        int vsplit, ppw;
     };
-    constexpr int N2 = NCH <= 2 ? NCH : 1;
-    const Cand cand[5] = {{back_kernel_launch<NCH, 1, 2>, 1}, {back_kernel_launch<NCH, 1, 4>, 1},
-                          {back_kernel_launch<N2, 2, 2>, 1},  {back_kernel_launch<NCH, 1, 2>, 2},
-                          {back_kernel_launch<N2, 1, 4>, 2}};
+    Cand cand[7];
+    int n_cand = 0;
+    if constexpr (NCH <= 2) {
+        // two edges per lane: 1 or 2 lines x 2 or 4 views, unsplit and split;
+        // one edge per lane, unsplit
+        const Cand c[7] = {{back_kernel_launch<NCH, 1, 2, 2>, 1, 127}, {back_kernel_launch<NCH, 1, 4, 2>, 1, 127},
+                           {back_kernel_launch<NCH, 2, 2, 2>, 1, 127}, {back_kernel_launch<NCH, 1, 2, 2>, 2, 127},
+                           {back_kernel_launch<NCH, 1, 4, 2>, 2, 127}, {back_kernel_launch<NCH, 1, 2, 1>, 1, 63},
+                           {back_kernel_launch<NCH, 1, 4, 1>, 1, 63}};
+        for (const Cand& e : c) cand[n_cand++] = e;
+    } else {
+        // more channels (one line per wavefront: two would not fit the registers)
+        const Cand c[4] = {{back_kernel_launch<NCH, 1, 2, 2>, 1, 127}, {back_kernel_launch<NCH, 1, 2, 2>, 2, 127},
+                           {back_kernel_launch<NCH, 1, 2, 1>, 1, 63}, {back_kernel_launch<NCH, 1, 4, 1>, 1, 63}};
+        for (const Cand& e : c) cand[n_cand++] = e;
+    }
     auto run = [&](int v) {
-        prefix(cand[v].vsplit);
+        prefix(cand[v].vsplit, cand[v].ppw);
         cand[v].fn(t, x, s, cand[v].vsplit);
         MBMD_LAUNCHED();
     };
-    const int n_cand = NCH <= 2 ? 5 : 2;
     int& choice = t.back_variant[NCH];
     const int forced = forced_back_variant();
     if (forced >= 0 && forced < n_cand) {           // testing hook: no tuning, nothing cached
@@ -892,7 +988,7 @@ const float* back_launch(const GeomTables& t, const float* sino, float* x, hipSt
             // Candidates interleaved over several rounds, each keeping its best
             // round: the shapes are often within a few per cent of each other,
             // closer than the spread of back-to-back launches.
-            float best[5] = {1e30f, 1e30f, 1e30f, 1e30f, 1e30f};
+            float best[7] = {1e30f, 1e30f, 1e30f, 1e30f, 1e30f, 1e30f, 1e30f};
             for (int v = 0; v < n_cand; ++v) run(v);  // warm-up
             for (int round = 0; round < 4; ++round)
                 for (int v = 0; v < n_cand; ++v) {
@@ -915,11 +1011,14 @@ const float* back_launch(const GeomTables& t, const float* sino, float* x, hipSt
             MBMD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
             const int simds = 4 * (cus > 0 ? cus : 1);
             auto waves = [&](int lpw) {
-                const long long u0 = nv0 ? (long long)back_main_items(t.nx, t.ny, lpw) + back_tail_items(t.nx, t.ny) : 0;
-                const long long u1 = nv1 ? (long long)back_main_items(t.ny, t.nx, lpw) + back_tail_items(t.ny, t.nx) : 0;
+                const long long u0 =
+                    nv0 ? (long long)back_main_items(t.nx, t.ny, lpw, 127) + back_tail_items(t.nx, t.ny, 127) : 0;
+                const long long u1 =
+                    nv1 ? (long long)back_main_items(t.ny, t.nx, lpw, 127) + back_tail_items(t.ny, t.nx, 127) : 0;
                 return (u0 + u1) * kWaves;
             };
             const double c1 = back_cost(waves(1), back_waves_per_round<NCH, 1>(), 1, simds);
+            constexpr int N2 = NCH <= 2 ? NCH : 1;
             const double c2 = NCH <= 2 ? back_cost(waves(2), back_waves_per_round<N2, 2>(), 2, simds) : 1e300;
             const int pick = c2 < c1 ? 2 : 0;
             if (cap != hipStreamCaptureStatusNone) {

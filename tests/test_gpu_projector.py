@@ -156,30 +156,33 @@ def test_nonzero_count_matches_oracle(name):
     assert abs(got - want) <= 5e-3 * want, (got, want)
 
 
-# Tile shapes the autotuner may pick, by channel count: whether each shape
-# splits its wavefronts' views in two halves (the halves are added onto a
-# cleared image).
-SPLIT_OF_SHAPE = {True: [False, False, False, True, True], False: [False, False]}
+# Tile shapes the autotuner may pick, by channel count (one or two, or more):
+# (pixel edges per lane, views split in two halves added onto a cleared image).
+SHAPE_CLASSES = {
+    True: [(2, False), (2, False), (2, False), (2, True), (2, True), (1, False), (1, False)],
+    False: [(2, False), (2, True), (1, False), (1, False)],
+}
 
 
 @pytest.mark.parametrize("nch", [1, 2, 3])
 def test_back_projector_tile_shapes_agree(nch, monkeypatch):
-    """Tile shapes with the same view split (lines per wavefront x views in
-    flight) sum each pixel's views in the same order, so their outputs are
-    bitwise equal; every shape matches the oracle."""
+    """Tile shapes of one class (edges per lane, view split) differ only in
+    lines per wavefront and views in flight and sum each pixel's views in the
+    same order, so their outputs are bitwise equal; every shape matches the
+    oracle."""
     g = GEOMS["fan_ragged"]
     s = np.random.default_rng(7).uniform(size=(nch, g["n_views"], g["n_bins"]))
     sd = dev(s)
     want = OP.backproject(g, s)
-    splits = SPLIT_OF_SHAPE[nch <= 2]
+    classes = SHAPE_CLASSES[nch <= 2]
     outs = []
-    for v in range(len(splits)):
+    for v in range(len(classes)):
         monkeypatch.setenv("MBMD_BACK_VARIANT", str(v))
         announce("back tile shape", nch, v)
         outs.append(host(mb.backproject(g, sd)))
     monkeypatch.delenv("MBMD_BACK_VARIANT")
-    for sp in (False, True):
-        group = [o for o, f in zip(outs, splits) if f == sp]
+    for cl in set(classes):
+        group = [o for o, c in zip(outs, classes) if c == cl]
         for o in group[1:]:
             np.testing.assert_array_equal(o, group[0])
     for o in outs:
