@@ -439,12 +439,13 @@ __device__ __forceinline__ EdgePair back_pair(const float4& m, float g, float K,
     EdgePair e;
     const float den = fmaf(m.z, K, 1.0f);
     const float num = fmaf(m.y, K, m.x);
-    const float bf = __builtin_amdgcn_fmed3f(floorf(num * fast_rcp(den)), -span, span);
-    e.off = (int)bf * (int)sizeof(DetEntry) + origin;
-    const float qa = fmaf(-g, bf, m.w);                        // bin b0's scale
-    e.frA = __builtin_amdgcn_fmed3f(fmaf(-bf, den, num) * qa, 0.0f, 1.0f);
+    // -b0 (the clamp is symmetric), so that every use below is a plain FMA
+    const float nbf = __builtin_amdgcn_fmed3f(-floorf(num * fast_rcp(den)), -span, span);
+    e.off = (int)(-nbf) * (int)sizeof(DetEntry) + origin;
+    const float qa = fmaf(g, nbf, m.w);                         // bin b0's scale
+    e.frA = __builtin_amdgcn_fmed3f(fmaf(nbf, den, num) * qa, 0.0f, 1.0f);
     const float denB = den + m.z, numB = num + m.y;             // at K + 1
-    const float n0 = fmaf(-bf, denB, numB);
+    const float n0 = fmaf(nbf, denB, numB);
     e.f0 = __builtin_amdgcn_fmed3f(n0 * qa, 0.0f, 1.0f);
     e.f1 = __builtin_amdgcn_fmed3f((n0 - denB) * (qa - g), 0.0f, 1.0f);
     return e;
@@ -513,7 +514,7 @@ __device__ __forceinline__ void back_tail(const float4* __restrict__ line_tab, i
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
                 acc[c] += h[u][c].c;                           // C[b+1]
-                accw[c] += fmaf(fr[u], h[u][c].d, -h[u][c].d);  // (fr - 1) w[b]
+                accw[c] = fmaf(fr[u], h[u][c].d, accw[c] - h[u][c].d);  // + (fr - 1) w[b]
                 keep(h[u][c].dn);
             }
         }
@@ -571,12 +572,13 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
         return;
     }
     item -= tail_items;
-    // with split views, items 2 i and 2 i + 1 take the two halves of item i
+    // Every pixel value is the sum of two half values, views [0, nv/2) and
+    // [nv/2, nv), added onto zero in that order: with split views items 2 i and
+    // 2 i + 1 each add one half onto the cleared image (two additions onto zero
+    // give the same result in either order); unsplit, a wavefront does both
+    // halves itself.  Both schedules give the same bits.
     const int half = vsplit == 2 ? item & 1 : 0;
     if (vsplit == 2) item >>= 1;
-    const int iv0 = half ? nv >> 1 : 0, iv1 = vsplit == 2 && !half ? nv >> 1 : nv;
-    if (iv0 >= iv1) return;                        // no views in this half (uniform)
-    const int sl0 = slot0 + iv0, nvh = iv1 - iv0;  // first slot and number of views taken
     const int segs = back_tiling(Np, PPW).full;
     const int seg = item % segs;
     const int lane = threadIdx.x & 63;
@@ -594,6 +596,13 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
     const int origin = shift * (int)sizeof(DetEntry);
     const size_t img_stride = (size_t)nx * ny;
     float* dst = frame ? part : x;
+    // pixel values summed over the halves taken (EPL = 2: pixels pe and pe + 1)
+    float outa[LPW][NCH], outb[LPW][NCH];
+#pragma unroll
+    for (int j = 0; j < LPW; ++j)
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) outa[j][c] = outb[j][c] = 0.0f;
+    int sl0 = 0, nvh = 0;                          // first slot and number of views of the half
     // Software pipeline over groups of U views: the per-line tables of the next
     // group are requested (scalar loads) only after this group's values are in
     // registers -- scalar loads complete out of order, so a wait for one waits
@@ -611,209 +620,202 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
             }
         }
     };
-    const int nfull = nvh - nvh % U;
-    if constexpr (EPL == 1) {
-        double acc[LPW][NCH];                       // sum over views of C[b+1]
-        float accw[LPW][NCH];                       // sum over views of (fr - 1) w[b]
-#pragma unroll
-        for (int j = 0; j < LPW; ++j)
-#pragma unroll
-            for (int c = 0; c < NCH; ++c) {
-                acc[j][c] = 0.0;
-                accw[j][c] = 0.0f;
-            }
-        fetch(0);
-        for (int is = 0; is < nfull; is += U) {   // trip counts are uniform over the wavefront
-            int off[U][LPW];
-            float frs[U][LPW];
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-                for (int j = 0; j < LPW; ++j) back_locate(tm[u][j], tg[u][j], K, span, origin, off[u][j], frs[u][j]);
-            DetValue h[U][LPW][NCH];
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-                for (int j = 0; j < LPW; ++j)
-#pragma unroll
-                    for (int c = 0; c < NCH; ++c) h[u][j][c] = load_det(tc, off[u][j], (c * V + sl0 + is + u) * row);
-            __builtin_amdgcn_sched_barrier(0);
-            fetch(is + U);
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-                for (int j = 0; j < LPW; ++j)
-#pragma unroll
-                    for (int c = 0; c < NCH; ++c) {
-                        acc[j][c] += h[u][j][c].c;
-                        accw[j][c] += fmaf(frs[u][j], h[u][j][c].d, -h[u][j][c].d);
-                        keep(h[u][j][c].dn);
-                    }
-        }
-        // the remaining views (fewer than U); their tables were fetched into slots 0..
-#pragma unroll
-        for (int u = 0; u < U - 1; ++u) {
-            if (nfull + u >= nvh) break;   // uniform
-#pragma unroll
-            for (int j = 0; j < LPW; ++j) {
-                int o;
-                float fr;
-                back_locate(tm[u][j], tg[u][j], K, span, origin, o, fr);
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) {
-                    const DetValue h = load_det(tc, o, (c * V + sl0 + nfull + u) * row);
-                    acc[j][c] += h.c;
-                    accw[j][c] += fmaf(fr, h.d, -h.d);
-                }
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < LPW; ++j) {
-            if (q0 + j >= Nq) break;       // uniform
-            float val[NCH];
-#pragma unroll
-            for (int c = 0; c < NCH; ++c)
-                val[c] = (float)((next_lane(acc[j][c]) - acc[j][c]) + (double)(next_lane(accw[j][c]) - accw[j][c]));
-            if (lane < 63 && pe < Np) {
-                // image layout: rows sweep (iy = q, ix = p), columns sweep (iy = p, ix = q)
-                const size_t pix = frame ? (size_t)pe * nx + (q0 + j) : (size_t)(q0 + j) * nx + pe;
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) {
-                    if (vsplit == 2)
-                        unsafeAtomicAdd(&dst[c * img_stride + pix], val[c]);
-                    else
-                        dst[c * img_stride + pix] = val[c];
-                }
-            }
-        }
-        return;
-    }
-    double acc[LPW][NCH];                           // sum over views of C[b0+1]
-    float wa[LPW][NCH], wb[LPW][NCH];               // sums over views of H(A) - C[b0+1], H(B) - C[b0+1]
-    double accw64[LPW][NCH];                        // the part of the latter from wide lanes' C[bB+1] - C[b0+1]
-#pragma unroll
-    for (int j = 0; j < LPW; ++j)
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            acc[j][c] = 0.0;
-            accw64[j][c] = 0.0;
-            wa[j][c] = 0.0f;
-            wb[j][c] = 0.0f;
-        }
-    // One view's contribution from its edge pair, the entry h of b0 and, for a
-    // wide lane, edge B's own entry hw (of bin bB) and fraction frw: H(B) -
-    // C[b0+1] is then (C[bB+1] - C[b0+1]) + (frw - 1) w[bB] instead of the two
-    // pieces, the difference of cumulative values summed in FP64 on its own.
-    // any_wide (uniform) skips the correction in wavefronts without wide lanes.
-    auto add_view = [&](int j, int c, const EdgePair& e, const DetValue& h, bool any_wide, bool wide,
-                        const DetValue& hw, float frw) {
-        acc[j][c] += h.c;
-        wa[j][c] += fmaf(e.frA, h.d, -h.d);
-        float tb = fmaf(e.f1, h.dn, fmaf(e.f0, h.d, -h.d));
-        if (any_wide) {
-            if (wide) {
-                tb = fmaf(frw, hw.d, -hw.d);
-                accw64[j][c] += hw.c - h.c;
-            }
-            keep(hw.dn);
-        }
-        wb[j][c] += tb;
-    };
-    fetch(0);
-    for (int is = 0; is < nfull; is += U) {   // trip counts are uniform over the wavefront
-        EdgePair ep[U][LPW];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int j = 0; j < LPW; ++j) ep[u][j] = back_pair(tm[u][j], tg[u][j], K, span, origin);
-        DetValue h[U][LPW][NCH];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
+    for (int h = half; h < (vsplit == 2 ? half + 1 : 2); ++h) {   // uniform
+        const int iv0 = h ? nv >> 1 : 0, iv1 = h ? nv : nv >> 1;
+        if (iv0 >= iv1) continue;                  // no views in this half: it adds zero
+        sl0 = slot0 + iv0;
+        nvh = iv1 - iv0;
+        const int nfull = nvh - nvh % U;
+        if constexpr (EPL == 1) {
+            double acc[LPW][NCH];                   // sum over views of C[b+1]
+            float accw[LPW][NCH];                   // sum over views of (fr - 1) w[b]
 #pragma unroll
             for (int j = 0; j < LPW; ++j)
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) h[u][j][c] = load_det(tc, ep[u][j].off, (c * V + sl0 + is + u) * row);
-        // wide lanes: edge B's own bin, entry and fraction (skipped by wavefronts without any)
-        bool wide[U][LPW], any_wide[U][LPW];
-        DetValue hw[U][LPW][NCH];
-        float frw[U][LPW];
+                for (int c = 0; c < NCH; ++c) {
+                    acc[j][c] = 0.0;
+                    accw[j][c] = 0.0f;
+                }
+            fetch(0);
+            for (int is = 0; is < nfull; is += U) {   // trip counts are uniform over the wavefront
+                int off[U][LPW];
+                float frs[U][LPW];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+                for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int j = 0; j < LPW; ++j) {
-                wide[u][j] = ep[u][j].f1 >= 1.0f;
-                any_wide[u][j] = __builtin_amdgcn_ballot_w64(wide[u][j]) != 0;
-                frw[u][j] = 0.0f;
-                if (wide[u][j]) {
+                    for (int j = 0; j < LPW; ++j)
+                        back_locate(tm[u][j], tg[u][j], K, span, origin, off[u][j], frs[u][j]);
+                DetValue hv[U][LPW][NCH];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int j = 0; j < LPW; ++j)
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c)
+                            hv[u][j][c] = load_det(tc, off[u][j], (c * V + sl0 + is + u) * row);
+                __builtin_amdgcn_sched_barrier(0);
+                fetch(is + U);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int j = 0; j < LPW; ++j)
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c) {
+                            acc[j][c] += hv[u][j][c].c;
+                            accw[j][c] = fmaf(frs[u][j], hv[u][j][c].d, accw[j][c] - hv[u][j][c].d);
+                            keep(hv[u][j][c].dn);
+                        }
+            }
+            // the remaining views (fewer than U); their tables were fetched into slots 0..
+#pragma unroll
+            for (int u = 0; u < U - 1; ++u) {
+                if (nfull + u >= nvh) break;   // uniform
+#pragma unroll
+                for (int j = 0; j < LPW; ++j) {
                     int o;
-                    back_locate(tm[u][j], tg[u][j], K + 1.0f, span, origin, o, frw[u][j]);
+                    float fr;
+                    back_locate(tm[u][j], tg[u][j], K, span, origin, o, fr);
 #pragma unroll
-                    for (int c = 0; c < NCH; ++c) hw[u][j][c] = load_det(tc, o, (c * V + sl0 + is + u) * row);
+                    for (int c = 0; c < NCH; ++c) {
+                        const DetValue hr = load_det(tc, o, (c * V + sl0 + nfull + u) * row);
+                        acc[j][c] += hr.c;
+                        accw[j][c] = fmaf(fr, hr.d, accw[j][c] - hr.d);   // as in the main loop
+                    }
                 }
             }
-        __builtin_amdgcn_sched_barrier(0);
-        fetch(is + U);
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int j = 0; j < LPW; ++j)
 #pragma unroll
                 for (int c = 0; c < NCH; ++c)
-                    add_view(j, c, ep[u][j], h[u][j][c], any_wide[u][j], wide[u][j], hw[u][j][c], frw[u][j]);
-    }
-    // the remaining views (fewer than U); their tables were fetched into slots 0..
+                    outa[j][c] += (float)((next_lane(acc[j][c]) - acc[j][c]) +
+                                          (double)(next_lane(accw[j][c]) - accw[j][c]));
+        } else {
+            double acc[LPW][NCH];                   // sum over views of C[b0+1]
+            float wa[LPW][NCH], wb[LPW][NCH];       // sums over views of H(A) - C[b0+1], H(B) - C[b0+1]
+            double accw64[LPW][NCH];                // the part of the latter from wide lanes' C[bB+1] - C[b0+1]
 #pragma unroll
-    for (int u = 0; u < U - 1; ++u) {
-        if (nfull + u >= nvh) break;       // uniform
+            for (int j = 0; j < LPW; ++j)
 #pragma unroll
-        for (int j = 0; j < LPW; ++j) {
-            const EdgePair e = back_pair(tm[u][j], tg[u][j], K, span, origin);
-            const bool wd = e.f1 >= 1.0f;
-            int o = 0;
-            float frw = 0.0f;
-            if (wd) back_locate(tm[u][j], tg[u][j], K + 1.0f, span, origin, o, frw);
+                for (int c = 0; c < NCH; ++c) {
+                    acc[j][c] = 0.0;
+                    accw64[j][c] = 0.0;
+                    wa[j][c] = 0.0f;
+                    wb[j][c] = 0.0f;
+                }
+            // One view's contribution from its edge pair, the entry hp of b0 and,
+            // for a wide lane, edge B's own entry hw (of bin bB) and fraction frw:
+            // H(B) - C[b0+1] is then (C[bB+1] - C[b0+1]) + (frw - 1) w[bB] instead
+            // of the two pieces, the difference of cumulative values summed in
+            // FP64 on its own.  any_wide (uniform) skips the correction in
+            // wavefronts without wide lanes.
+            auto add_view = [&](int j, int c, const EdgePair& e, const DetValue& hp, bool any_wide, bool wide,
+                                const DetValue& hw, float frw) {
+                acc[j][c] += hp.c;
+                wa[j][c] = fmaf(e.frA, hp.d, wa[j][c] - hp.d);
+                float tb = fmaf(e.f1, hp.dn, fmaf(e.f0, hp.d, -hp.d));
+                if (any_wide) {
+                    if (wide) {
+                        tb = fmaf(frw, hw.d, -hw.d);
+                        accw64[j][c] += hw.c - hp.c;
+                    }
+                    keep(hw.dn);
+                }
+                wb[j][c] += tb;
+            };
+            fetch(0);
+            for (int is = 0; is < nfull; is += U) {   // trip counts are uniform over the wavefront
+                EdgePair ep[U][LPW];
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) {
-                const int rc = (c * V + sl0 + nfull + u) * row;
-                const DetValue h = load_det(tc, e.off, rc);
-                DetValue hw = h;
-                if (wd) hw = load_det(tc, o, rc);
-                add_view(j, c, e, h, true, wd, hw, frw);
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int j = 0; j < LPW; ++j) ep[u][j] = back_pair(tm[u][j], tg[u][j], K, span, origin);
+                DetValue hv[U][LPW][NCH];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int j = 0; j < LPW; ++j)
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c)
+                            hv[u][j][c] = load_det(tc, ep[u][j].off, (c * V + sl0 + is + u) * row);
+                // wide lanes: edge B's own bin, entry and fraction (skipped by wavefronts without any)
+                bool wide[U][LPW], any_wide[U][LPW];
+                DetValue hw[U][LPW][NCH];
+                float frw[U][LPW];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int j = 0; j < LPW; ++j) {
+                        wide[u][j] = ep[u][j].f1 >= 1.0f;
+                        any_wide[u][j] = __builtin_amdgcn_ballot_w64(wide[u][j]) != 0;
+                        if (wide[u][j]) {                  // frw is read only where set
+                            int o;
+                            back_locate(tm[u][j], tg[u][j], K + 1.0f, span, origin, o, frw[u][j]);
+#pragma unroll
+                            for (int c = 0; c < NCH; ++c)
+                                hw[u][j][c] = load_det(tc, o, (c * V + sl0 + is + u) * row);
+                        }
+                    }
+                __builtin_amdgcn_sched_barrier(0);
+                fetch(is + U);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int j = 0; j < LPW; ++j)
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c)
+                            add_view(j, c, ep[u][j], hv[u][j][c], any_wide[u][j], wide[u][j], hw[u][j][c],
+                                     frw[u][j]);
             }
+            // the remaining views (fewer than U); their tables were fetched into slots 0..
+#pragma unroll
+            for (int u = 0; u < U - 1; ++u) {
+                if (nfull + u >= nvh) break;       // uniform
+#pragma unroll
+                for (int j = 0; j < LPW; ++j) {
+                    const EdgePair e = back_pair(tm[u][j], tg[u][j], K, span, origin);
+                    const bool wd = e.f1 >= 1.0f;
+                    int o = 0;
+                    float frw = 0.0f;
+                    if (wd) back_locate(tm[u][j], tg[u][j], K + 1.0f, span, origin, o, frw);
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c) {
+                        const int rc = (c * V + sl0 + nfull + u) * row;
+                        const DetValue hp = load_det(tc, e.off, rc);
+                        DetValue hw = hp;
+                        if (wd) hw = load_det(tc, o, rc);
+                        add_view(j, c, e, hp, true, wd, hw, frw);
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < LPW; ++j)
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    outa[j][c] += (float)(accw64[j][c] + (double)(wb[j][c] - wa[j][c]));
+                    outb[j][c] += (float)(((next_lane(acc[j][c]) - acc[j][c]) - accw64[j][c]) +
+                                          (double)(next_lane(wa[j][c]) - wb[j][c]));
+                }
         }
     }
+    // image layout: rows sweep (iy = q, ix = p), columns sweep (iy = p, ix = q)
+    const size_t step = frame ? (size_t)nx : 1;
 #pragma unroll
     for (int j = 0; j < LPW; ++j) {
-        if (q0 + j >= Nq) break;           // uniform
-        float va[NCH], vb[NCH];
+        if (q0 + j >= Nq) break;                   // uniform
+        const size_t pix = frame ? (size_t)pe * nx + (q0 + j) : (size_t)(q0 + j) * nx + pe;
+        // EPL = 1: pixel pe from lanes 0..62; EPL = 2: pixels pe and pe + 1
+        const bool va_ok = EPL == 1 ? lane < 63 && pe < Np : pe < Np;
+        const bool vb_ok = EPL == 2 && lane < 63 && pe + 1 < Np;
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-            va[c] = (float)(accw64[j][c] + (double)(wb[j][c] - wa[j][c]));
-            vb[c] = (float)(((next_lane(acc[j][c]) - acc[j][c]) - accw64[j][c]) +
-                            (double)(next_lane(wa[j][c]) - wb[j][c]));
-        }
-        // image layout: rows sweep (iy = q, ix = p), columns sweep (iy = p, ix = q)
-        const size_t pix_a = frame ? (size_t)pe * nx + (q0 + j) : (size_t)(q0 + j) * nx + pe;
-        const size_t step = frame ? (size_t)nx : 1;
-        if (vsplit == 2) {                 // onto the cleared image (uniform)
-            if (pe < Np) {
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) unsafeAtomicAdd(&dst[c * img_stride + pix_a], va[c]);
-            }
-            if (lane < 63 && pe + 1 < Np) {
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) unsafeAtomicAdd(&dst[c * img_stride + pix_a + step], vb[c]);
-            }
-        } else {
-            if (pe < Np) {
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) dst[c * img_stride + pix_a] = va[c];
-            }
-            if (lane < 63 && pe + 1 < Np) {
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) dst[c * img_stride + pix_a + step] = vb[c];
+            if (vsplit == 2) {                     // onto the cleared image (uniform)
+                if (va_ok) unsafeAtomicAdd(&dst[c * img_stride + pix], outa[j][c]);
+                if (vb_ok) unsafeAtomicAdd(&dst[c * img_stride + pix + step], outb[j][c]);
+            } else {
+                if (va_ok) dst[c * img_stride + pix] = outa[j][c];
+                if (vb_ok) dst[c * img_stride + pix + step] = outb[j][c];
             }
         }
     }
@@ -936,35 +938,38 @@ const float* back_launch(const GeomTables& t, const float* sino, float* x, hipSt
         MBMD_LAUNCHED();
     };
     if (!nv0) launch_fill(NCH * t.nx * t.ny, x, 0.0f, s);
-    // Tile shape: edges per lane, lines per wavefront x views in flight, and
-    // whether each wavefront's views are split in two halves (twice the
-    // wavefronts, each half added onto the cleared image: two additions onto
-    // zero give the same result in either order).  Shapes with the same edges
-    // per lane and split give bit-identical results (the order of the sums over
-    // views is the same); the others agree up to rounding.  The first back
-    // projection of a geometry and channel count outside graph capture times
-    // the candidates on its own inputs and keeps the fastest; under capture, or
-    // when tuning is switched off, a round-count cost model picks between
-    // unsplit two-edge shapes.
+    // Tile shape.  The pixel edges per lane are fixed by the problem: two for
+    // one or two channels when every swept line is at least one wavefront
+    // segment long (two edges per lane halve the gathers, but with more
+    // channels their registers, and on shorter lines their idle lanes, cost
+    // more), else one.  Within that choice the shapes -- lines per wavefront x
+    // views in flight, views split over two wavefronts or not -- give
+    // bit-identical results: every pixel is the sum of the same two halves,
+    // each summing its views in the same order.  The first back projection of
+    // a geometry and channel count outside graph capture times them on its own
+    // inputs and keeps the fastest; under capture, or when tuning is switched
+    // off, a cost model of resident rounds picks between unsplit shapes.
     using Launch = void (*)(const GeomTables&, float*, hipStream_t, int);
     struct Cand {
         Launch fn;
         int vsplit, ppw;
     };
-    Cand cand[7];
+    const int np_min = std::min(nv0 ? t.nx : 1 << 30, nv1 ? t.ny : 1 << 30);
+    Cand cand[5];
     int n_cand = 0;
+    bool two_edges = false;
     if constexpr (NCH <= 2) {
-        // two edges per lane: 1 or 2 lines x 2 or 4 views, unsplit and split;
-        // one edge per lane, unsplit
-        const Cand c[7] = {{back_kernel_launch<NCH, 1, 2, 2>, 1, 127}, {back_kernel_launch<NCH, 1, 4, 2>, 1, 127},
-                           {back_kernel_launch<NCH, 2, 2, 2>, 1, 127}, {back_kernel_launch<NCH, 1, 2, 2>, 2, 127},
-                           {back_kernel_launch<NCH, 1, 4, 2>, 2, 127}, {back_kernel_launch<NCH, 1, 2, 1>, 1, 63},
-                           {back_kernel_launch<NCH, 1, 4, 1>, 1, 63}};
-        for (const Cand& e : c) cand[n_cand++] = e;
-    } else {
-        // more channels (one line per wavefront: two would not fit the registers)
-        const Cand c[4] = {{back_kernel_launch<NCH, 1, 2, 2>, 1, 127}, {back_kernel_launch<NCH, 1, 2, 2>, 2, 127},
-                           {back_kernel_launch<NCH, 1, 2, 1>, 1, 63}, {back_kernel_launch<NCH, 1, 4, 1>, 1, 63}};
+        if (np_min >= back_ppw(2)) {
+            two_edges = true;
+            const Cand c[5] = {{back_kernel_launch<NCH, 1, 2, 2>, 1, 127}, {back_kernel_launch<NCH, 1, 4, 2>, 1, 127},
+                               {back_kernel_launch<NCH, 2, 2, 2>, 1, 127}, {back_kernel_launch<NCH, 1, 2, 2>, 2, 127},
+                               {back_kernel_launch<NCH, 1, 4, 2>, 2, 127}};
+            for (const Cand& e : c) cand[n_cand++] = e;
+        }
+    }
+    if (!two_edges) {
+        const Cand c[4] = {{back_kernel_launch<NCH, 1, 2, 1>, 1, 63}, {back_kernel_launch<NCH, 1, 4, 1>, 1, 63},
+                           {back_kernel_launch<NCH, 1, 2, 1>, 2, 63}, {back_kernel_launch<NCH, 1, 4, 1>, 2, 63}};
         for (const Cand& e : c) cand[n_cand++] = e;
     }
     auto run = [&](int v) {
@@ -988,7 +993,7 @@ const float* back_launch(const GeomTables& t, const float* sino, float* x, hipSt
             // Candidates interleaved over several rounds, each keeping its best
             // round: the shapes are often within a few per cent of each other,
             // closer than the spread of back-to-back launches.
-            float best[7] = {1e30f, 1e30f, 1e30f, 1e30f, 1e30f, 1e30f, 1e30f};
+            float best[5] = {1e30f, 1e30f, 1e30f, 1e30f, 1e30f};
             for (int v = 0; v < n_cand; ++v) run(v);  // warm-up
             for (int round = 0; round < 4; ++round)
                 for (int v = 0; v < n_cand; ++v) {
@@ -1017,9 +1022,10 @@ const float* back_launch(const GeomTables& t, const float* sino, float* x, hipSt
                     nv1 ? (long long)back_main_items(t.ny, t.nx, lpw, 127) + back_tail_items(t.ny, t.nx, 127) : 0;
                 return (u0 + u1) * kWaves;
             };
+            // two edges: one line per wavefront (shape 0) or two (shape 2); one edge: shape 0
             const double c1 = back_cost(waves(1), back_waves_per_round<NCH, 1>(), 1, simds);
             constexpr int N2 = NCH <= 2 ? NCH : 1;
-            const double c2 = NCH <= 2 ? back_cost(waves(2), back_waves_per_round<N2, 2>(), 2, simds) : 1e300;
+            const double c2 = two_edges ? back_cost(waves(2), back_waves_per_round<N2, 2>(), 2, simds) : 1e300;
             const int pick = c2 < c1 ? 2 : 0;
             if (cap != hipStreamCaptureStatusNone) {
                 run(pick);                             // not cached: tune on a later uncaptured call
