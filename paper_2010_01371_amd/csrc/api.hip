@@ -8,6 +8,7 @@
 // in a hipGraph (batched form).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <exception>
 #include <memory>
@@ -289,6 +290,14 @@ void plain_iteration(Problem& P, float* x, double* trace_slot, hipStream_t s) {
     launch_reduce_final(P.partials, counts, P.scal, trace_slot, 0, P.flags, s);
 }
 
+// MBMD_FUSE_ROWS=0 in the environment (read on every iteration) keeps the
+// gradient launch and the detector prefix apart (a testing hook: both ways give
+// the same iterates).
+bool fuse_rows_enabled() {
+    const char* e = std::getenv("MBMD_FUSE_ROWS");
+    return !(e && e[0] == '0');
+}
+
 // One preconditioned iteration.  On entry l = A x up to the step the previous
 // iteration left pending in alpha (zero when none), which this one applies first;
 // on exit its own step is pending.
@@ -296,8 +305,22 @@ void precond_iteration(Problem& P, float* x, int kind, double* trace_slot, hipSt
     int counts[kRegions] = {0};
     // the previous iteration's step (x += alpha p, l += alpha q) is applied by this launch
     const StepUpdate up{P.scal + S_ALPHA, P.q, P.l, x, P.p_img, P.K * P.nj};
-    counts[R_PHI_L] = launch_ray_grad(ray_args(P), P.l, P.u, nullptr, P.r, region(P, R_PHI_L), s, &up);
-    const float* part = backproject_parts(P, P.u, P.g_img, P.K, s);   // summed by the penalty pass
+    // Once the back projector's shape is chosen for K channels, the gradient
+    // launch of a single-energy problem writes its detector rows itself (the
+    // same bits as storing u and running the detector prefix), and only the
+    // back projection kernel follows.  With many energies per ray the fused
+    // launch, one workgroup per view, has too few threads for the ray work.
+    const float* part = nullptr;                                       // summed by the penalty pass
+    const bool fuse = !P.identity && P.E == 1 && fuse_rows_enabled();
+    const BackRows br = fuse ? back_rows(*P.geom, P.g_img, P.K) : BackRows{};
+    const int n_rows = br.ok ? launch_ray_grad_rows(ray_args(P), P.l, P.r, region(P, R_PHI_L), s, up, br) : -1;
+    if (n_rows >= 0) {
+        counts[R_PHI_L] = n_rows;
+        part = launch_back_kernel(*P.geom, P.g_img, P.K, s);
+    } else {
+        counts[R_PHI_L] = launch_ray_grad(ray_args(P), P.l, P.u, nullptr, P.r, region(P, R_PHI_L), s, &up);
+        part = backproject_parts(P, P.u, P.g_img, P.K, s);
+    }
     counts[R_PHI_R] = launch_penalty_grad(pen_args(P), x, P.g_img, nullptr, P.g_img, nullptr,
                                           region(P, R_PHI_R), s, part);
     counts[R_GP] = apply_direction(P, kind, P.g_img, P.p_img, -1.0f, region(P, R_GP), s);

@@ -222,6 +222,34 @@ void launch_backproject(const GeomTables& t, const float* sino, float* x, int n_
 const float* launch_backproject_parts(const GeomTables& t, const float* sino, float* x, int n_ch, hipStream_t s);
 long long count_nonzeros(const GeomTables& t, hipStream_t s);
 
+// Pixels that a back projection adds into, cleared before it: the last w0
+// columns of x (row sweeps) and the last h1 rows of part (column sweeps), nch
+// channels each -- the tail pixels, or every pixel when the main wavefronts'
+// views are split over two wavefronts; zero sizes when there is none.
+struct BackClear {
+    float* x;
+    float* part;
+    int nx, ny, w0, h1, nch;
+};
+// What a producer of a back projection's input needs to write the detector
+// rows itself (instead of the detector-prefix launch): the rows, the per-view
+// records and path lengths they are built from, and the pixels to clear for the
+// tile shape in use.  ok is false until that shape is chosen for n_ch channels
+// (the first back projection of a geometry and channel count tunes it).
+struct BackRows {
+    bool ok;
+    DetEntry* rows;               // [n_ch][V][det_row(B)]
+    const ViewParams* view;       // [slot]
+    const float* path;            // [slot][B]
+    int V, B;
+    BackClear clr;
+};
+BackRows back_rows(const GeomTables& t, float* x, int n_ch);
+// The back projection kernel alone in the chosen shape, with the detector rows
+// already written (by a launch given back_rows(t, x, n_ch)); returns the
+// column-sweep part as launch_backproject_parts does.
+const float* launch_back_kernel(const GeomTables& t, float* x, int n_ch, hipStream_t s);
+
 // ---------------------------------------------------------------- problem
 struct Problem {
     mbmd_geometry g{};
@@ -300,6 +328,15 @@ struct StepUpdate {
 };
 int launch_ray_grad(const RayArgs& a, const float* l, float* u, float* v, float* r,
                     double* phi_partials, hipStream_t s, const StepUpdate* up = nullptr);
+// The ray gradient u (a.K channels) written straight into the back projector's
+// detector rows (br = back_rows(...) with br.ok): one workgroup per view slot,
+// each computing its rays as launch_ray_grad does and building the rows of u
+// times the path length, bit for bit as the detector-prefix launch would from
+// the stored u; also clears br.clr.  Residuals r, objective partials (one per
+// view slot; returns their count) and the step update as launch_ray_grad.
+// Returns -1, launching nothing, when the rows of one slot do not fit in LDS.
+int launch_ray_grad_rows(const RayArgs& a, const float* l, float* r, double* phi_partials, hipStream_t s,
+                         const StepUpdate& up, const BackRows& br);
 int launch_ray_curv(const RayArgs& a, const float* l, const float* r, const float* q,
                     double* partials, hipStream_t s);
 // Curvature along the direction in one launch: the rays' c q^2 into region CQ2

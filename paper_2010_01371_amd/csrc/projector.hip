@@ -47,6 +47,7 @@
 #include <type_traits>
 #include <cstdlib>
 
+#include "back_rows.h"
 #include "internal.h"
 
 namespace mbmd {
@@ -183,84 +184,29 @@ __global__ __launch_bounds__(kScanThreads) void k_line_prefix(const float* __res
     if (threadIdx.x < 4) dst[Np + threadIdx.x] = (float)part[kScanThreads - 1];
 }
 
-// Per slot and channel, the row of detector entries (C[b+1], w[b], w[b+1]) with
-// widths w[b] = sino[b'] path[b'] of the bins in increasing-K order (b' = b, or
-// B - 1 - b for views with orient < 0) and C[b] = sum_{b''<b} w[b''] (FP64 sums
-// of the FP32 widths, so that C[b+1] - w[b] gives C[b] up to FP64 rounding),
-// w[B] = 0, and the total with zero widths at entries B and B+1.  One workgroup
-// per (slot, channel); each lane takes a contiguous run of bins, an FP64
-// shuffle scan combines the lanes of a wavefront and one barrier the wavefronts.
-constexpr int kPrefixThreads = 256;
-// Pixels that the back projection adds into: the last w0 columns of x (row
-// sweeps) and the last h1 rows of part (column sweeps), nch channels each --
-// the tail pixels (see back_tiling), or every pixel when the main wavefronts'
-// views are split in two as well; zero sizes when there is none.
-struct TailClear {
-    float* x;
-    float* part;
-    int nx, ny, w0, h1, nch;
-};
+// Per slot and channel, the row of detector entries (see build_detector_row)
+// of the widths w[b] = sino[b'] path[b'] of the bins in increasing-K order
+// (b' = b, or B - 1 - b for views with orient < 0).  One workgroup per (slot,
+// channel); every workgroup also clears its share of the pixels the back
+// projection kernel adds into.
+constexpr int kPrefixThreads = kRowThreads;
 __global__ __launch_bounds__(kPrefixThreads) void k_detector_prefix(const float* __restrict__ sino,
                                                                      const float* __restrict__ path,
                                                                      const ViewParams* __restrict__ view, int V,
                                                                      int B, DetEntry* __restrict__ C,
-                                                                     TailClear tc) {
-    {   // side job: clear the back projection's tail pixels, which its tail wavefronts add into
-        const int n0 = tc.nch * tc.ny * tc.w0, n1 = tc.nch * tc.h1 * tc.nx, nj = tc.nx * tc.ny;
-        for (int i = (blockIdx.y * gridDim.x + blockIdx.x) * kPrefixThreads + threadIdx.x; i < n0 + n1;
-             i += gridDim.x * gridDim.y * kPrefixThreads) {
-            if (i < n0) {                                      // row sweeps: columns [nx - w0, nx) of x
-                const int c = i / (tc.ny * tc.w0), r = i - c * tc.ny * tc.w0;
-                const int iy = r / tc.w0, ix = tc.nx - tc.w0 + (r - iy * tc.w0);
-                tc.x[(size_t)c * nj + (size_t)iy * tc.nx + ix] = 0.0f;
-            } else {                                           // column sweeps: rows [ny - h1, ny) of part
-                const int k = i - n0;
-                const int c = k / (tc.h1 * tc.nx), r = k - c * tc.h1 * tc.nx;
-                tc.part[(size_t)c * nj + (size_t)(tc.ny - tc.h1) * tc.nx + r] = 0.0f;
-            }
-        }
-    }
+                                                                     BackClear tc) {
+    clear_back_pixels(tc, blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);   // side job
     const int slot = blockIdx.x, ch = blockIdx.y;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const bool rev = view[slot].orient < 0.0f;
     const float* s = sino + ((size_t)ch * V + vp_view(view[slot])) * B;
     const float* pa = path + (size_t)slot * B;
-    DetEntry* dst = C + ((size_t)ch * V + slot) * det_row(B);
-    auto width = [&](int b) {                                     // b in row order, < B
-        const int k = rev ? B - 1 - b : b;
-        return (float)((double)s[k] * (double)pa[k]);
-    };
     __shared__ double wave_total[kPrefixThreads / 64];
-    const int per = (B + kPrefixThreads - 1) / kPrefixThreads;
-    const int b0 = threadIdx.x * per;
-    double acc = 0.0;
-    for (int i = 0; i < per; ++i) {
-        const int b = b0 + i;
-        if (b < B) acc += (double)width(b);
-    }
-    double inc = acc;                                             // inclusive scan over the wavefront
-    for (int off = 1; off < 64; off <<= 1) {
-        const double t = __shfl_up(inc, off, 64);
-        if (lane >= off) inc += t;
-    }
-    if (lane == 63) wave_total[wave] = inc;
-    __syncthreads();
-    double run = inc - acc;
-    for (int w = 0; w < wave; ++w) run += wave_total[w];          // fixed order
-    float d = b0 < B ? width(b0) : 0.0f;
-    for (int i = 0; i < per; ++i) {
-        const int b = b0 + i;
-        if (b < B) {
-            const float dn = b + 1 < B ? width(b + 1) : 0.0f;
-            run += (double)d;
-            dst[b] = DetEntry{run, d, dn};
-            d = dn;
-        }
-    }
-    if (threadIdx.x == kPrefixThreads - 1) {                      // holds the total after its run
-        dst[B] = DetEntry{run, 0.0f, 0.0f};
-        dst[B + 1] = DetEntry{run, 0.0f, 0.0f};
-    }
+    build_detector_row(
+        [&](int b) {                                              // b in row order, < B
+            const int k = rev ? B - 1 - b : b;
+            return (float)((double)s[k] * (double)pa[k]);
+        },
+        B, C + ((size_t)ch * V + slot) * det_row(B), wave_total);
 }
 
 // Work of the two sweep frames of one launch.
@@ -918,62 +864,89 @@ void back_kernel_launch(const GeomTables& t, float* x, hipStream_t s, int vsplit
     kt_.stop();
 }
 
+// Tile shape.  The pixel edges per lane are fixed by the problem: two for one
+// or two channels when every swept line is at least one wavefront segment long
+// (two edges per lane halve the gathers, but with more channels their
+// registers, and on shorter lines their idle lanes, cost more), else one.
+// Within that choice the shapes -- lines per wavefront x views in flight, views
+// split over two wavefronts or not -- give bit-identical results: every pixel
+// is the sum of the same two halves, each summing its views in the same order.
+using BackLaunch = void (*)(const GeomTables&, float*, hipStream_t, int);
+struct BackShape {
+    BackLaunch fn;
+    int vsplit, ppw;
+};
+template <int NCH>
+int back_shapes(const GeomTables& t, BackShape* cand, bool& two_edges) {
+    const int nv0 = t.n_frame_views[0], nv1 = t.n_frame_views[1];
+    const int np_min = std::min(nv0 ? t.nx : 1 << 30, nv1 ? t.ny : 1 << 30);
+    int n = 0;
+    two_edges = false;
+    if constexpr (NCH <= 2) {
+        if (np_min >= back_ppw(2)) {
+            two_edges = true;
+            const BackShape c[5] = {
+                {back_kernel_launch<NCH, 1, 2, 2>, 1, 127}, {back_kernel_launch<NCH, 1, 4, 2>, 1, 127},
+                {back_kernel_launch<NCH, 2, 2, 2>, 1, 127}, {back_kernel_launch<NCH, 1, 2, 2>, 2, 127},
+                {back_kernel_launch<NCH, 1, 4, 2>, 2, 127}};
+            for (const BackShape& e : c) cand[n++] = e;
+        }
+    }
+    if (!two_edges) {
+        const BackShape c[4] = {{back_kernel_launch<NCH, 1, 2, 1>, 1, 63}, {back_kernel_launch<NCH, 1, 4, 1>, 1, 63},
+                                {back_kernel_launch<NCH, 1, 2, 1>, 2, 63}, {back_kernel_launch<NCH, 1, 4, 1>, 2, 63}};
+        for (const BackShape& e : c) cand[n++] = e;
+    }
+    return n;
+}
+constexpr int kMaxBackShapes = 5;
+
+// The pixels a back projection in shape sh adds into (the tail's, or all with
+// split views), which its detector rows' launch clears.
+BackClear back_clear(const GeomTables& t, float* x, int nch, const BackShape& sh) {
+    const int nv0 = t.n_frame_views[0], nv1 = t.n_frame_views[1];
+    const BackTiling b0 = back_tiling(t.nx, sh.ppw), b1 = back_tiling(t.ny, sh.ppw);
+    const int w0 = !nv0 ? 0 : sh.vsplit == 2 ? t.nx : b0.tail_lines ? t.nx - b0.full * sh.ppw : 0;
+    const int h1 = !nv1 ? 0 : sh.vsplit == 2 ? t.ny : b1.tail_lines ? t.ny - b1.full * sh.ppw : 0;
+    return BackClear{x, t.back_part, t.nx, t.ny, w0, h1, nch};
+}
+
+// The shape in use for NCH channels: forced by the testing hook, else the
+// tuned one; -1 when none is chosen yet.
+template <int NCH>
+int back_chosen(const GeomTables& t) {
+    BackShape cand[kMaxBackShapes];
+    bool two_edges;
+    const int n = back_shapes<NCH>(t, cand, two_edges);
+    const int forced = forced_back_variant();
+    if (forced >= 0 && forced < n) return forced;
+    return t.back_variant[NCH];
+}
+
 // Writes the row-sweep part of A^T sino to x (zero when no view sweeps rows) and
 // returns the column-sweep part, in image layout, or nullptr when there is none.
 template <int NCH>
 const float* back_launch(const GeomTables& t, const float* sino, float* x, hipStream_t s) {
     const int nv0 = t.n_frame_views[0], nv1 = t.n_frame_views[1];
-    // The detector prefix, which also clears the pixels the kernel adds into
-    // (the tail's, or all with split views), precedes every back projection
-    // kernel (the tuner's too).
-    auto prefix = [&](int vsplit, int ppw) {
+    BackShape cand[kMaxBackShapes];
+    bool two_edges;
+    const int n_cand = back_shapes<NCH>(t, cand, two_edges);
+    // The detector prefix, which also clears the pixels the kernel adds into,
+    // precedes every back projection kernel (the tuner's too).
+    auto prefix = [&](const BackShape& sh) {
         KernelTimer kt_("k_detector_prefix", s);
-        const BackTiling b0 = back_tiling(t.nx, ppw), b1 = back_tiling(t.ny, ppw);
-        const int w0 = !nv0 ? 0 : vsplit == 2 ? t.nx : b0.tail_lines ? t.nx - b0.full * ppw : 0;
-        const int h1 = !nv1 ? 0 : vsplit == 2 ? t.ny : b1.tail_lines ? t.ny - b1.full * ppw : 0;
-        const TailClear clr{x, t.back_part, t.nx, t.ny, w0, h1, NCH};
         hipLaunchKernelGGL(k_detector_prefix, dim3(t.V, NCH), dim3(kPrefixThreads), 0, s, sino, t.path, t.view,
-                           t.V, t.B, t.det_prefix, clr);
+                           t.V, t.B, t.det_prefix, back_clear(t, x, NCH, sh));
         kt_.stop();
         MBMD_LAUNCHED();
     };
     if (!nv0) launch_fill(NCH * t.nx * t.ny, x, 0.0f, s);
-    // Tile shape.  The pixel edges per lane are fixed by the problem: two for
-    // one or two channels when every swept line is at least one wavefront
-    // segment long (two edges per lane halve the gathers, but with more
-    // channels their registers, and on shorter lines their idle lanes, cost
-    // more), else one.  Within that choice the shapes -- lines per wavefront x
-    // views in flight, views split over two wavefronts or not -- give
-    // bit-identical results: every pixel is the sum of the same two halves,
-    // each summing its views in the same order.  The first back projection of
-    // a geometry and channel count outside graph capture times them on its own
-    // inputs and keeps the fastest; under capture, or when tuning is switched
-    // off, a cost model of resident rounds picks between unsplit shapes.
-    using Launch = void (*)(const GeomTables&, float*, hipStream_t, int);
-    struct Cand {
-        Launch fn;
-        int vsplit, ppw;
-    };
-    const int np_min = std::min(nv0 ? t.nx : 1 << 30, nv1 ? t.ny : 1 << 30);
-    Cand cand[5];
-    int n_cand = 0;
-    bool two_edges = false;
-    if constexpr (NCH <= 2) {
-        if (np_min >= back_ppw(2)) {
-            two_edges = true;
-            const Cand c[5] = {{back_kernel_launch<NCH, 1, 2, 2>, 1, 127}, {back_kernel_launch<NCH, 1, 4, 2>, 1, 127},
-                               {back_kernel_launch<NCH, 2, 2, 2>, 1, 127}, {back_kernel_launch<NCH, 1, 2, 2>, 2, 127},
-                               {back_kernel_launch<NCH, 1, 4, 2>, 2, 127}};
-            for (const Cand& e : c) cand[n_cand++] = e;
-        }
-    }
-    if (!two_edges) {
-        const Cand c[4] = {{back_kernel_launch<NCH, 1, 2, 1>, 1, 63}, {back_kernel_launch<NCH, 1, 4, 1>, 1, 63},
-                           {back_kernel_launch<NCH, 1, 2, 1>, 2, 63}, {back_kernel_launch<NCH, 1, 4, 1>, 2, 63}};
-        for (const Cand& e : c) cand[n_cand++] = e;
-    }
+    // The first back projection of a geometry and channel count outside graph
+    // capture times the shapes on its own inputs and keeps the fastest; under
+    // capture, or when tuning is switched off, a cost model of resident rounds
+    // picks between unsplit shapes.
     auto run = [&](int v) {
-        prefix(cand[v].vsplit, cand[v].ppw);
+        prefix(cand[v]);
         cand[v].fn(t, x, s, cand[v].vsplit);
         MBMD_LAUNCHED();
     };
@@ -1110,6 +1083,61 @@ const float* launch_backproject_parts(const GeomTables& t, const float* sino, fl
         case 9: return back_launch<9>(t, sino, x, s);
         default: return back_launch<10>(t, sino, x, s);
     }
+}
+
+namespace {
+template <int NCH>
+BackRows back_rows_n(const GeomTables& t, float* x) {
+    BackRows r{};
+    const int v = back_chosen<NCH>(t);
+    if (v < 0) return r;                          // ok = false
+    BackShape cand[kMaxBackShapes];
+    bool two_edges;
+    back_shapes<NCH>(t, cand, two_edges);
+    r.ok = true;
+    r.rows = t.det_prefix;
+    r.view = t.view;
+    r.path = t.path;
+    r.V = t.V;
+    r.B = t.B;
+    r.clr = back_clear(t, x, NCH, cand[v]);
+    return r;
+}
+template <int NCH>
+const float* back_kernel_n(const GeomTables& t, float* x, hipStream_t s) {
+    const int v = back_chosen<NCH>(t);
+    MBMD_REQUIRE(v >= 0, MBMD_ERR_ARG, "back projection shape not chosen yet");
+    BackShape cand[kMaxBackShapes];
+    bool two_edges;
+    back_shapes<NCH>(t, cand, two_edges);
+    if (!t.n_frame_views[0]) launch_fill(NCH * t.nx * t.ny, x, 0.0f, s);
+    cand[v].fn(t, x, s, cand[v].vsplit);
+    MBMD_LAUNCHED();
+    return t.n_frame_views[1] ? t.back_part : nullptr;
+}
+}  // namespace
+
+BackRows back_rows(const GeomTables& t, float* x, int n_ch) {
+    MBMD_REQUIRE(n_ch >= 1 && n_ch <= kMaxBackCh, MBMD_ERR_SHAPE, "back projection channels must be in 1..10");
+    MBMD_REQUIRE(t.det_prefix != nullptr && t.back_ch >= n_ch, MBMD_ERR_ARG, "back projection scratch too small");
+    switch (n_ch) {
+        case 1: return back_rows_n<1>(t, x);
+        case 2: return back_rows_n<2>(t, x);
+        case 3: return back_rows_n<3>(t, x);
+        case 4: return back_rows_n<4>(t, x);
+        default: return BackRows{};               // more channels: the detector-prefix path
+    }
+}
+
+const float* launch_back_kernel(const GeomTables& t, float* x, int n_ch, hipStream_t s) {
+    switch (n_ch) {
+        case 1: return back_kernel_n<1>(t, x, s);
+        case 2: return back_kernel_n<2>(t, x, s);
+        case 3: return back_kernel_n<3>(t, x, s);
+        case 4: return back_kernel_n<4>(t, x, s);
+        default: MBMD_REQUIRE(false, MBMD_ERR_ARG, "detector rows are written by the caller for 1..4 channels only");
+    }
+    return nullptr;
 }
 
 void launch_backproject(const GeomTables& t, const float* sino, float* x, int n_ch, hipStream_t s) {

@@ -15,6 +15,7 @@
 // reduced per block in a fixed order.
 #include <cmath>
 
+#include "back_rows.h"
 #include "device_common.h"
 #include "internal.h"
 
@@ -69,6 +70,60 @@ __device__ __forceinline__ void channel_means(const RayModel& m, const SharedMod
     }
 }
 
+// Ray i of the gradient pass: applies the pending step to its line integrals
+// (l += a q, a = the step size, 0 for none), and returns its share of the data
+// term of Phi, with uk[k] (and vk[k] when want_v) of the ray and the residuals
+// r_c stored to r_out (when not NULL).
+template <int KT, int CT>
+__device__ __forceinline__ double ray_grad_at(const RayModel& m, const SharedModel& sm, int ni, int i,
+                                              const float* __restrict__ l, const float* __restrict__ y,
+                                              const float* __restrict__ w, const float* __restrict__ gammaA,
+                                              float* __restrict__ r_out, const StepUpdate& up, float a,
+                                              bool want_v, float* uk, float* vk) {
+    const int K = KT ? KT : m.K, C = CT ? CT : m.C;
+    float lk[kMaxMat], ybar[kMaxChan], rc[kMaxChan], sig[kMaxChan];
+    if (a != 0.0f) {                                       // l += alpha q, then use it
+        for (int k = 0; k < K; ++k) {
+            lk[k] = fmaf(a, up.q[(size_t)k * ni + i], up.l[(size_t)k * ni + i]);
+            up.l[(size_t)k * ni + i] = lk[k];
+        }
+    } else {
+        for (int k = 0; k < K; ++k) lk[k] = l[(size_t)k * ni + i];
+    }
+    channel_means<KT, CT>(m, sm, lk, ybar);
+    double phi = 0.0;
+    for (int c = 0; c < C; ++c) {
+        const float yc = y[(size_t)c * ni + i], wc = w[(size_t)c * ni + i];
+        const float dv = ybar[c] - yc;
+        rc[c] = wc * dv;
+        sig[c] = wc * m.rowS[c];
+        phi += 0.5 * (double)wc * (double)dv * (double)dv;
+        if (r_out) r_out[(size_t)c * ni + i] = rc[c];
+    }
+    const float gA = gammaA ? gammaA[i] : 1.0f;
+    for (int k = 0; k < K; ++k) uk[k] = vk[k] = 0.0f;
+#pragma unroll 2
+    for (int e = 0; e < m.E; ++e) {
+        float le = 0.0f;
+        for (int k = 0; k < K; ++k) le = fmaf(sm.Q[e * K + k], lk[k], le);
+        const float t = expf(-le);
+        float s = 0.0f, eta = 0.0f;
+        for (int c = 0; c < C; ++c) {
+            const float sce = sm.S[e * C + c];
+            s = fmaf(sce, rc[c], s);
+            eta = fmaf(sce, sig[c], eta);
+        }
+        const float hdot = -t * s;
+        for (int k = 0; k < K; ++k) uk[k] = fmaf(sm.Q[e * K + k], hdot, uk[k]);
+        if (want_v) {
+            const float ce = fmaxf(2.0f * eta + s - eta * t, 0.0f);
+            const float gc = gA * sm.Qsum[e] * ce;
+            for (int k = 0; k < K; ++k) vk[k] = fmaf(sm.Q[e * K + k], gc, vk[k]);
+        }
+    }
+    return phi;
+}
+
 template <int KT, int CT>
 __global__ __launch_bounds__(kRayThreads) void k_ray_grad(RayModel m, int ni, const float* __restrict__ l,
                                                           const float* __restrict__ y,
@@ -86,52 +141,13 @@ __global__ __launch_bounds__(kRayThreads) void k_ray_grad(RayModel m, int ni, co
         return;
     }
     stage_model<KT, CT>(m, sm);
-    const int K = KT ? KT : m.K, C = CT ? CT : m.C;
+    const int K = KT ? KT : m.K;
     const int i = blockIdx.x * kRayThreads + threadIdx.x;
     double phi = 0.0;
     if (i < ni) {
-        float lk[kMaxMat], ybar[kMaxChan], rc[kMaxChan], sig[kMaxChan];
         const float a = up.alpha ? (float)*up.alpha : 0.0f;
-        if (a != 0.0f) {                                   // l += alpha q, then use it
-            for (int k = 0; k < K; ++k) {
-                lk[k] = fmaf(a, up.q[(size_t)k * ni + i], up.l[(size_t)k * ni + i]);
-                up.l[(size_t)k * ni + i] = lk[k];
-            }
-        } else {
-            for (int k = 0; k < K; ++k) lk[k] = l[(size_t)k * ni + i];
-        }
-        channel_means<KT, CT>(m, sm, lk, ybar);
-        for (int c = 0; c < C; ++c) {
-            const float yc = y[(size_t)c * ni + i], wc = w[(size_t)c * ni + i];
-            const float dv = ybar[c] - yc;
-            rc[c] = wc * dv;
-            sig[c] = wc * m.rowS[c];
-            phi += 0.5 * (double)wc * (double)dv * (double)dv;
-            if (r_out) r_out[(size_t)c * ni + i] = rc[c];
-        }
-        const float gA = gammaA ? gammaA[i] : 1.0f;
         float uk[kMaxMat], vk[kMaxMat];
-        for (int k = 0; k < K; ++k) uk[k] = vk[k] = 0.0f;
-#pragma unroll 2
-        for (int e = 0; e < m.E; ++e) {
-            float le = 0.0f;
-            for (int k = 0; k < K; ++k) le = fmaf(sm.Q[e * K + k], lk[k], le);
-            const float t = expf(-le);
-            float s = 0.0f, eta = 0.0f;
-            for (int c = 0; c < C; ++c) {
-                const float sce = sm.S[e * C + c];
-                s = fmaf(sce, rc[c], s);
-                eta = fmaf(sce, sig[c], eta);
-            }
-            const float hdot = -t * s;
-            const float ce = fmaxf(2.0f * eta + s - eta * t, 0.0f);
-            const float gc = gA * sm.Qsum[e] * ce;
-            for (int k = 0; k < K; ++k) {
-                const float qek = sm.Q[e * K + k];
-                uk[k] = fmaf(qek, hdot, uk[k]);
-                vk[k] = fmaf(qek, gc, vk[k]);
-            }
-        }
+        phi = ray_grad_at<KT, CT>(m, sm, ni, i, l, y, w, gammaA, r_out, up, a, v != nullptr, uk, vk);
         for (int k = 0; k < K; ++k) {
             u[(size_t)k * ni + i] = uk[k];
             if (v) v[(size_t)k * ni + i] = vk[k];
@@ -139,6 +155,54 @@ __global__ __launch_bounds__(kRayThreads) void k_ray_grad(RayModel m, int ni, co
     }
     const double tot = block_sum(phi, sh);
     if (threadIdx.x == 0 && partials) partials[blockIdx.x] = tot;
+}
+
+// The gradient pass fused with the back projector's detector rows of u: block
+// slot < br.V takes the rays of that view slot (bins in row order, strided over
+// the threads), keeps u times the path length in LDS and builds the rows from
+// there -- the same values and arithmetic as storing u and running the
+// detector prefix; blocks from br.V on apply the image part of the step.  Every
+// block clears its share of br.clr.  Objective partials: one per view slot.
+template <int KT, int CT>
+__global__ __launch_bounds__(kRayThreads) void k_ray_grad_rows(RayModel m, int ni, const float* __restrict__ l,
+                                                               const float* __restrict__ y,
+                                                               const float* __restrict__ w,
+                                                               float* __restrict__ r_out,
+                                                               double* __restrict__ partials, StepUpdate up,
+                                                               BackRows br) {
+    extern __shared__ float wl[];                          // [K][B] widths of the slot's rows
+    __shared__ double sh[kRayThreads / 64];
+    __shared__ double wave_total[kMaxMat][kRayThreads / 64];
+    __shared__ SharedModel sm;
+    clear_back_pixels(br.clr, blockIdx.x, gridDim.x);      // side job
+    if ((int)blockIdx.x >= br.V) {                         // the image part of the step: x += alpha p
+        const float a = up.alpha ? (float)*up.alpha : 0.0f;
+        const int i = ((int)blockIdx.x - br.V) * kRayThreads + threadIdx.x;
+        if (a != 0.0f && i < up.n_img) up.x[i] = fmaf(a, up.p[i], up.x[i]);
+        return;
+    }
+    stage_model<KT, CT>(m, sm);
+    const int K = KT ? KT : m.K;
+    const int slot = blockIdx.x, B = br.B;
+    const ViewParams vp = br.view[slot];
+    const bool rev = vp.orient < 0.0f;
+    const int view = vp_view(vp);
+    const float* pa = br.path + (size_t)slot * B;
+    const float a = up.alpha ? (float)*up.alpha : 0.0f;
+    double phi = 0.0;
+    for (int pos = threadIdx.x; pos < B; pos += kRayThreads) {
+        const int bin = rev ? B - 1 - pos : pos;           // row order runs along +K
+        float uk[kMaxMat], vk[kMaxMat];
+        phi += ray_grad_at<KT, CT>(m, sm, ni, view * B + bin, l, y, w, nullptr, r_out, up, a, false, uk, vk);
+        const double L = (double)pa[bin];
+        for (int k = 0; k < K; ++k) wl[k * B + pos] = (float)((double)uk[k] * L);
+    }
+    const double tot = block_sum(phi, sh);                 // its barriers also publish wl
+    if (threadIdx.x == 0 && partials) partials[slot] = tot;
+    __syncthreads();
+    for (int k = 0; k < K; ++k)
+        build_detector_row([&](int b) { return wl[k * B + b]; }, B,
+                           br.rows + ((size_t)k * br.V + slot) * det_row(B), wave_total[k]);
 }
 
 // Ray i's share of sum_iE c_iE q_iE^2 with q_iE = sum_k Q_Ek q_ik, c recomputed
@@ -483,6 +547,26 @@ int launch_ray_grad(const RayArgs& a, const float* l, float* u, float* v, float*
     }
     MBMD_LAUNCHED();
     return nb;
+}
+
+int launch_ray_grad_rows(const RayArgs& a, const float* l, float* r, double* phi_partials, hipStream_t s,
+                         const StepUpdate& up, const BackRows& br) {
+    MBMD_REQUIRE(br.ok && br.V * br.B == a.ni, MBMD_ERR_ARG, "detector rows do not match the rays");
+    MBMD_REQUIRE(br.V <= kMaxPartials, MBMD_ERR_SHAPE, "too many views for the partial-sum buffer");
+    MBMD_REQUIRE(up.l == l, MBMD_ERR_ARG, "the step update must update the l it reads");
+    const size_t lds = sizeof(float) * (size_t)a.K * br.B;
+    if (lds > 32768) return -1;                            // with the static LDS, over the per-block budget
+    const int nb_img = up.alpha ? blocks_for(up.n_img) : 0;
+    {
+        KernelTimer kt_("k_ray_grad_rows", s);
+#define L_(KT, CT) hipLaunchKernelGGL((k_ray_grad_rows<KT, CT>), dim3(br.V + nb_img), dim3(kRayThreads), lds, s, \
+                                   model_of(a), a.ni, l, a.y, a.w, r, phi_partials, up, br)
+        MBMD_RAY_DISPATCH(a.K, a.C, L_);
+#undef L_
+        kt_.stop();
+    }
+    MBMD_LAUNCHED();
+    return br.V;
 }
 
 int launch_ray_curv(const RayArgs& a, const float* l, const float* r, const float* q, double* partials,

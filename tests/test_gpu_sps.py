@@ -167,3 +167,29 @@ def test_unbuilt_preconditioner_is_an_error():
     P = mb.Problem.from_workload(wl)
     with pytest.raises(RuntimeError, match="not built"):
         P.sps_step(P.zeros_image(), "haar", 1)
+
+
+@pytest.mark.parametrize("name", ["fan64_huber", "fan128_quad"])
+def test_gradient_rows_fused_match_separate_launches(name, monkeypatch):
+    """Once the back projector's shape is chosen, the gradient launch of a
+    single-energy problem writes its detector rows itself; the iterates are
+    bitwise those of storing the gradient and running the detector prefix (one
+    pixel edge per lane at 64^2, two at 128^2)."""
+    wl = {
+        "fan64_huber": lambda: C.make_small_fan(n=64, views=90, bins=128, penalty="huber"),
+        "fan128_quad": lambda: C.make_small_fan(n=128, views=120, bins=200, penalty="quadratic"),
+    }[name]()
+    announce("sps fused gradient rows", name)
+    out, fused_launches = [], []
+    for fuse in ("0", "1"):
+        monkeypatch.setenv("MBMD_FUSE_ROWS", fuse)
+        P = mb.Problem.from_workload(wl)
+        P.precond_build("fourier")
+        x = P.zeros_image()
+        with mb.KernelProfile(only=["k_ray_grad_rows"]) as prof:
+            P.sps_step(x, "fourier", 12)
+            fused_launches.append(prof.query("k_ray_grad_rows")[0])
+        out.append(host(x))
+    monkeypatch.delenv("MBMD_FUSE_ROWS")
+    assert fused_launches[0] == 0 and fused_launches[1] >= 11, fused_launches   # the first one tunes
+    np.testing.assert_array_equal(out[1], out[0])
