@@ -6,31 +6,38 @@
 //
 // Forward (ray-driven): each image line of each sweep frame is integrated once
 // per call into exclusive prefix sums F[k] = sum_{p<k} img[p] (FP64
-// accumulation, stored FP32 next to img[k]).  F is linear inside a pixel, so
-// the integral of the line over a footprint [K_b, K_b+1] is F(K_b+1) - F(K_b).
-// One lane per bin BOUNDARY: a wavefront evaluates F at 64 consecutive
-// boundaries and takes its right-hand neighbour's value with a wave shuffle,
-// giving 63 bins per wavefront.  The footprint width is the difference of the
-// same two FP32 boundary positions that F is evaluated at, so position
-// rounding cancels to first order in the ratio (the exact width would not);
-// signs cancel too, whatever the orientation of the view.
+// accumulation, stored FP32).  F is linear inside a pixel, so the integral of
+// the line over a footprint [K_b, K_b+1] is F(K_b+1) - F(K_b).  Each lane owns
+// two neighbouring bin BOUNDARIES and takes the next lane's first one with a
+// wave shift, giving 127 bins per wavefront; one 16-byte read of F[k..k+3]
+// serves both boundaries when no bin is wider than two pixels.  The footprint
+// width is the difference of the same two FP32 boundary positions that F is
+// evaluated at, so position rounding cancels to first order in the ratio (the
+// exact width would not); signs cancel too, whatever the orientation of the
+// view.  Each wavefront's active lines are split into two work items added
+// atomically onto the cleared output (two additions onto zero commute), taken
+// heaviest first.
 //
 // Back projection (pixel-driven gather): per call and view the sinogram times
-// the per-line path length is integrated over the detector in FP64,
-// C_v[b] = sum_{b'<b} sino * path.  The back projected detector signal on a
-// sweep line is piecewise constant in the along-line position K, with
-// cumulative integral H(K) = C[b] + (C[b+1] - C[b]) (K - K_b)/(K_b+1 - K_b)
-// for K in bin b, so a pixel [K, K+1] receives H(K+1) - H(K); the view's
-// orientation sign is folded into C.  One lane per pixel EDGE: each lane sums
-// H over the views and the pixel value is the difference of the right
-// neighbour lane's sum and its own (63 pixels per wavefront).  The bin holding
-// an edge and the fraction (K - K_b)/(K_b+1 - K_b) both come from the
-// projective map K -> fractional bin index restricted to the sweep line, whose
-// per-line coefficients are read with scalar loads; the only per-lane table
-// read is the pair (C[b], C[b+1] - C[b]).  The fraction is clamped to [0, 1],
-// which keeps H continuous when the bin index is off by rounding near a
-// boundary.  H and the sums over views are FP64 (full rate on CDNA); no
-// atomics, so results are bitwise reproducible.
+// the per-line path length is integrated over the detector in FP64, C[b] =
+// sum_{b'<b} w[b'], in increasing-K order (the rows of views whose bins run
+// along -K are stored from the last bin, with the map of the reversed index).
+// The back projected detector signal on a sweep line is piecewise constant in
+// the along-line position K, with cumulative integral H(K) = C[b] + w[b] (K -
+// K_b)/(K_b+1 - K_b) for K in bin b, so a pixel [K, K+1] receives H(K+1) -
+// H(K).  Lanes own pixel EDGES (one or two per lane: 63 or 127 pixels per
+// wavefront), sum H over the views and take pixel values as differences of
+// neighbouring edges' sums.  The bin holding an edge and the fraction
+// (K - K_b)/(K_b+1 - K_b) come from the projective map K -> fractional bin
+// index restricted to the sweep line, whose per-line coefficients are read
+// with scalar loads; the only per-lane table read is a 16-byte detector entry
+// {C[b+1], w[b], w[b+1]}, which serves both edges of a lane.  The fractions are
+// clamped to [0, 1], which keeps H continuous when the bin index is off by
+// rounding near a boundary.  Sums over views of C are FP64 (full rate on
+// CDNA), the in-bin parts (within one bin width) FP32.  Every pixel is the sum
+// of two halves of its views, added onto zero, which two wavefronts may do with
+// atomics (they commute exactly): results are bitwise reproducible whatever
+// the tile shape.
 //
 // Table reads go through buffer loads (32-bit offsets from a base held in
 // scalar registers; out-of-range offsets read zero), neighbour exchanges are
@@ -40,9 +47,9 @@
 // Views sweeping rows and views sweeping columns are interleaved in one launch
 // with an XCD-aware block order: blocks are dispatched round-robin to the 8
 // XCDs, and blocks landing on XCDs 0-3 take row-sweep work, 4-7 column-sweep
-// work, so each XCD's L2 holds one frame's prefix arrays.  The column-sweep
-// part of a back projection is written in its own (transposed) layout and
-// added by a tiled transpose.
+// work, so each XCD's L2 holds one frame's tables.  The column-sweep part of a
+// back projection is written in image layout to a buffer of its own and added
+// by the caller (the iteration does it in the penalty pass).
 #include <cmath>
 #include <type_traits>
 #include <cstdlib>
