@@ -28,6 +28,11 @@ GEOMS = {
     # pixels), so that one or two channels take two pixel edges per lane
     "fan_ragged_wide": C.geometry("fan", 150, 131, 0.9, 1.1, 37, 2 * np.pi, 301, 1.1, dso=400.0,
                                   dsd=700.0, u_offset=-0.23),
+    # every view in one sweep frame (rows only / columns only), the swept lines
+    # long enough for two pixel edges per lane while the other side is short
+    "parallel_rows_only": C.geometry("parallel", 140, 40, 1.0, 1.0, 6, 0.6, 170, 0.9, theta0=-0.3),
+    "parallel_cols_only": C.geometry("parallel", 40, 150, 1.0, 1.0, 6, 0.6, 170, 0.9,
+                                     theta0=np.pi / 2 - 0.3),
 }
 
 
