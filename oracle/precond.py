@@ -40,7 +40,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import haar, projector
+from . import haar, model, projector
 from . import penalty as pen
 
 M0_FLOOR = 1e-6
@@ -65,17 +65,26 @@ def water_only_estimate(prob, n_steps=GN_STEPS):
     return lw
 
 
-def transmission_estimate(prob):
-    """D per (energy, ray) [N_E, V, B] approximating exp(-AA x_hat)."""
+def transmission_estimate(prob, x_ref=None):
+    """D per (energy, ray) [N_E, V, B] approximating exp(-AA x_hat).
+
+    With a reference image x_ref [N_k, ny, nx], the transmission there,
+    exp(-AA x_ref) (the Fisher information at an iterate, for a rebuild during
+    the iterations); else from the data: y / I0 for one energy and channel, the
+    water-only estimate otherwise.
+    """
+    if x_ref is not None:
+        return model.transmission(prob, model.line_integrals(prob, np.asarray(x_ref, dtype=np.float64)))
     if prob.n_energy == 1 and prob.n_chan == 1:
         return (prob.y[0] / prob.S[0, 0])[None]
     lw = water_only_estimate(prob)
     return np.exp(-prob.Q[:, 0][:, None, None] * lw[None])
 
 
-def fisher_weights(prob):
-    """W_i = J_i^T diag(w_i) J_i  ->  [N_k, N_k, V, B]."""
-    D = transmission_estimate(prob)
+def fisher_weights(prob, x_ref=None):
+    """W_i = J_i^T diag(w_i) J_i  ->  [N_k, N_k, V, B], J = -S D{D_i} Q with D
+    from transmission_estimate(prob, x_ref)."""
+    D = transmission_estimate(prob, x_ref)
     J = -np.einsum("ce,evb,ek->ckvb", prob.S, D, prob.Q)
     return np.einsum("cvb,ckvb,clvb->klvb", prob.w, J, J)
 
@@ -179,17 +188,18 @@ def _global_floor(blocks, eps):
     return block_inv_sqrt(B, floor_abs=eps * lmax)
 
 
-def build(prob, kind, eps=None, modified=True, W=None, hop=None):
+def build(prob, kind, eps=None, modified=True, W=None, hop=None, x_ref=None):
     """Build the tables of preconditioner ``kind`` in {'blockdiag','fourier','haar'}.
 
     ``modified=False`` gives the unmodified preconditioners (M0 = I), e.g. the
-    Fourier preconditioner of eq:fourierEigenbasis.  ``hop`` replaces the
+    Fourier preconditioner of eq:fourierEigenbasis.  ``x_ref`` takes the Fisher
+    weights at that image instead of from the data.  ``hop`` replaces the
     Hessian operator v -> H v (tests use it to feed known operators).
     """
     K = prob.n_mat
     ny, nx = prob.geom["ny"], prob.geom["nx"]
     if hop is None:
-        W = fisher_weights(prob) if W is None else W
+        W = fisher_weights(prob, x_ref) if W is None else W
     if not modified:
         M0 = np.broadcast_to(np.eye(K), (ny, nx, K, K)).copy()
     else:

@@ -1,6 +1,7 @@
 """Pins of the oracle's preconditioner builds (CPU only): exact cases where the
 approximate eigenbasis is the true one, the Haar transform, the block
-inverse square roots and the data-based Fisher weights."""
+inverse square roots, and the Fisher weights from the data and from a
+reference image."""
 
 import numpy as np
 import pytest
@@ -173,3 +174,36 @@ def test_floors_are_reported_and_positive():
         assert t["n_floored"] > 0
         eig = np.linalg.eigvalsh(t["P"])
         assert np.all(eig > 0)
+
+
+def test_reference_weights_equal_data_weights_on_consistent_data():
+    """Single energy: with counts y = I0 exp(-A x_ref) exactly, the data-based
+    D = y / I0 and the transmission at x_ref are the same, so are the weights."""
+    wl = C.make_small_fan(n=16, views=12, bins=32)
+    prob = oracle.OracleProblem.from_workload(wl)
+    x_ref = np.abs(wl.x_true) + 0.01
+    y = prob.S[0, 0] * np.exp(-oracle.projector.project(prob.geom, x_ref))
+    prob_c = oracle.OracleProblem(prob.geom, prob.Q, prob.S, y, prob.w, prob.penalty)
+    np.testing.assert_allclose(precond.fisher_weights(prob_c, x_ref), precond.fisher_weights(prob_c), rtol=1e-12)
+
+
+def test_reference_weights_are_the_gram_of_the_jacobian():
+    """Three materials, four channels: the weights at x_ref are sum_c w_c J_ck J_cl
+    with J the Jacobian of ybar_c with respect to the material line integrals
+    l_k, here by central differences of the forward model."""
+    wl = C.make_small_mbmd(n=16, views=10, bins=24, n_mat=3, n_energy_step=10)
+    prob = oracle.OracleProblem.from_workload(wl)
+    x_ref = np.abs(wl.x_true) * 0.5
+    W = precond.fisher_weights(prob, x_ref)
+    l0 = model.line_integrals(prob, x_ref)
+    h = 1e-5
+    J = np.empty((prob.n_chan, prob.n_mat) + prob.sino_shape)
+    for k in range(prob.n_mat):
+        dl = np.zeros_like(l0)
+        dl[k] = h
+        up = model.mean_counts(prob, model.transmission(prob, l0 + dl))
+        dn = model.mean_counts(prob, model.transmission(prob, l0 - dl))
+        J[:, k] = (up - dn) / (2 * h)
+    W_fd = np.einsum("cvb,ckvb,clvb->klvb", prob.w, J, J)
+    np.testing.assert_allclose(W, W_fd, rtol=1e-6, atol=1e-9 * np.abs(W_fd).max())
+
