@@ -69,6 +69,11 @@ typedef enum {
     MBMD_PRECOND_BLOCKDIAG = 3  /* per-pixel N_k x N_k block diagonal: M = M0 */
 } mbmd_precond;
 
+/* Flags of mbmd_precond_build_ex. */
+typedef enum {
+    MBMD_PRECOND_UNMODIFIED = 1 /* M0 = I: the unmodified preconditioners (the Fourier one of eq:fourierEigenbasis) */
+} mbmd_precond_flags;
+
 typedef enum {
     MBMD_PENALTY_QUADRATIC = 0, /* R = 1/2 x^T (beta (x) Gamma) x */
     MBMD_PENALTY_HUBER = 1      /* R = beta sum_pairs psi_delta(x_j - x_j'), one material */
@@ -194,6 +199,26 @@ void mbmd_problem_destroy(mbmd_problem* prob);
  * Errors: MBMD_ERR_ARG, MBMD_ERR_SHAPE, MBMD_ERR_UNSUPPORTED, MBMD_ERR_HIP.
  */
 int mbmd_precond_build(mbmd_problem* prob, int kind, void* stream);
+
+/*
+ * mbmd_precond_build with options ("Preconditioned Optimization": D
+ * approximates the transmission at the solution, and the modified
+ * preconditioners differ from the plain ones by M0):
+ *   - flags: 0, or MBMD_PRECOND_UNMODIFIED for M0 = I (FOURIER then is
+ *     U^H L^-1/2 U with L from the bare Hessian's impulse response; HAAR
+ *     likewise; BLOCKDIAG is then no preconditioning);
+ *   - x_ref_dev: NULL for the data-based D above, or a device image
+ *     [n_mat][ny][nx] (FP32, caller-owned, read only during the call) whose
+ *     transmission D = exp(-AA x_ref) replaces it -- the Fisher information
+ *     at an iterate, for rebuilding the preconditioner during the iterations.
+ * The Fisher weights and M0 are shared by the problem's preconditioners, so
+ * any call with options (and the next plain mbmd_precond_build after one)
+ * voids the others: apply or iterate with them only after building them
+ * again (MBMD_ERR_NOT_BUILT otherwise).  Uses the problem's scratch between
+ * runs; asynchronous on `stream` like the other calls.
+ * Errors: as mbmd_precond_build, and MBMD_ERR_ARG for an unknown flag.
+ */
+int mbmd_precond_build_ex(mbmd_problem* prob, int kind, int flags, const float* x_ref_dev, void* stream);
 
 /*
  * out_dev = M M^T g_dev for a built preconditioner (the direction operator

@@ -17,6 +17,7 @@ from ._lib import check
 
 KINDS = {"parallel": 0, "fan": 1, "identity": 2}
 PRECONDS = {"none": 0, "fourier": 1, "haar": 2, "blockdiag": 3}
+PRECOND_UNMODIFIED = 1          # mbmd_precond_flags
 PENALTIES = {"quadratic": 0, "huber": 1}
 
 
@@ -135,8 +136,18 @@ class Problem:
     def zeros_image(self):
         return torch.zeros(self.image_shape, device=self.device, dtype=torch.float32)
 
-    def precond_build(self, kind):
-        check(self._lib.mbmd_precond_build(self._h, PRECONDS[kind], _stream()), "mbmd_precond_build")
+    def precond_build(self, kind, modified=True, x_ref=None):
+        """mbmd_precond_build, or mbmd_precond_build_ex with M0 = I
+        (modified=False) and / or the Fisher weights at the image x_ref."""
+        if modified and x_ref is None:
+            check(self._lib.mbmd_precond_build(self._h, PRECONDS[kind], _stream()), "mbmd_precond_build")
+            return
+        if x_ref is not None:
+            _dev_f32(x_ref, self.image_shape, "x_ref")
+        flags = 0 if modified else PRECOND_UNMODIFIED
+        check(self._lib.mbmd_precond_build_ex(self._h, PRECONDS[kind], flags,
+                                              _ptr(x_ref) if x_ref is not None else None, _stream()),
+              "mbmd_precond_build_ex")
 
     def precond_apply(self, kind, g):
         _dev_f32(g, self.image_shape, "g")

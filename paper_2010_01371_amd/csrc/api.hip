@@ -182,18 +182,33 @@ void hessian_apply(Problem& P, const float* v, float* out, const float* M0, hipS
     if (M0) launch_block_apply(P.nj, P.K, M0, out, out, 1.0f, s);
 }
 
-void ensure_fisher_m0(Problem& P, hipStream_t s) {
-    if (P.m0_built) return;
-    launch_fisher(ray_args(P), P.W, s);
-    // Htilde_j = column blocks of (F + R) 1_k = A^T (gamma_A W_kk')  (Gamma 1 = 0)
-    if (P.identity) {
-        launch_scale_copy(P.npk * P.ni, P.W, P.t_img, 1.0f, s);
+// The Fisher weights W (from the data, or at reference line integrals lref) and
+// M0: modified, M0_j = Htilde_j^-1/2 from the material columns; else M0 = I.
+// state (see Problem::m0_state) records what they are; a new state, or any
+// rebuild from a reference image, voids the preconditioners built on the old
+// ones.
+void build_fisher_m0(Problem& P, int state, const float* lref, bool modified, hipStream_t s) {
+    launch_fisher(ray_args(P), P.W, s, lref);
+    if (!modified) {
+        launch_fill(P.npk * P.nj, P.M0, 0.0f, s);
+        for (int k = 0; k < P.K; ++k) launch_fill(P.nj, P.M0 + (size_t)packed_index(k, k, P.K) * P.nj, 1.0f, s);
     } else {
-        launch_scale_by_vec(P.ni, P.npk, P.W, P.gammaA, P.sino_tmp, s);
-        backproject(P, P.sino_tmp, P.t_img, P.npk, s);
+        // Htilde_j = column blocks of (F + R) 1_k = A^T (gamma_A W_kk')  (Gamma 1 = 0)
+        if (P.identity) {
+            launch_scale_copy(P.npk * P.ni, P.W, P.t_img, 1.0f, s);
+        } else {
+            launch_scale_by_vec(P.ni, P.npk, P.W, P.gammaA, P.sino_tmp, s);
+            backproject(P, P.sino_tmp, P.t_img, P.npk, s);
+        }
+        launch_block_invsqrt(P.nj, P.K, P.t_img, P.M0, -0.5, kM0Floor, nullptr, 0.0, P.flags + 1, s);
     }
-    launch_block_invsqrt(P.nj, P.K, P.t_img, P.M0, -0.5, kM0Floor, nullptr, 0.0, P.flags + 1, s);
-    P.m0_built = 1;
+    for (int k = 0; k < 4; ++k) P.built[k] = 0;
+    P.m0_state = state;
+}
+
+// The data-based, modified weights and M0 (built once).
+void ensure_fisher_m0(Problem& P, hipStream_t s) {
+    if (P.m0_state != 1) build_fisher_m0(P, 1, nullptr, true, s);
 }
 
 void finish_filter(Problem& P, const float* blocks, float* out, double eps, hipStream_t s) {
@@ -596,10 +611,11 @@ void mbmd_problem_destroy(mbmd_problem* prob) {
     delete prob;
 }
 
-int mbmd_precond_build(mbmd_problem* prob, int kind, void* stream) {
+int mbmd_precond_build_ex(mbmd_problem* prob, int kind, int flags, const float* x_ref_dev, void* stream) {
     return guarded([&] {
         MBMD_REQUIRE(prob, MBMD_ERR_ARG, "NULL problem");
         MBMD_REQUIRE(kind >= 0 && kind <= 3, MBMD_ERR_ARG, "unknown preconditioner");
+        MBMD_REQUIRE((flags & ~MBMD_PRECOND_UNMODIFIED) == 0, MBMD_ERR_ARG, "unknown preconditioner build flag");
         hipStream_t s = static_cast<hipStream_t>(stream);
         prob->last_stream = s;
         if (kind == MBMD_PRECOND_NONE) return;
@@ -610,11 +626,26 @@ int mbmd_precond_build(mbmd_problem* prob, int kind, void* stream) {
             MBMD_REQUIRE(prob->spec != nullptr, MBMD_ERR_SHAPE, "the Fourier preconditioner needs power-of-two sizes");
         if (kind == MBMD_PRECOND_HAAR)
             MBMD_REQUIRE(prob->coef != nullptr, MBMD_ERR_SHAPE, "the Haar preconditioner needs a square power-of-two image");
-        ensure_fisher_m0(*prob, s);
+        if (flags == 0 && !x_ref_dev) {
+            ensure_fisher_m0(*prob, s);
+        } else {
+            // reference line integrals into q, which holds nothing between runs
+            // (every run ends with its pending step applied)
+            const float* lref = nullptr;
+            if (x_ref_dev) {
+                project(*prob, x_ref_dev, prob->q, prob->K, s);
+                lref = prob->q;
+            }
+            build_fisher_m0(*prob, 2, lref, !(flags & MBMD_PRECOND_UNMODIFIED), s);
+        }
         if (kind == MBMD_PRECOND_FOURIER) build_fourier(*prob, s);
         if (kind == MBMD_PRECOND_HAAR) build_haar(*prob, s);
         prob->built[kind] = 1;
     });
+}
+
+int mbmd_precond_build(mbmd_problem* prob, int kind, void* stream) {
+    return mbmd_precond_build_ex(prob, kind, 0, nullptr, stream);
 }
 
 int mbmd_precond_apply(mbmd_problem* prob, int kind, const float* g_dev, float* out_dev, void* stream) {

@@ -276,7 +276,7 @@ struct Problem {
     float *dL_const = nullptr;       // single-energy data curvature A^T(gamma c), built once
     int dL_valid = 0;
     // preconditioners
-    float* M0 = nullptr;             // [nj][npk]
+    float* M0 = nullptr;             // [npk][nj]
     float* Linv = nullptr;           // [ny][nx][npk]  (L^-1 blocks)
     float* Kinv = nullptr;           // [ny][nx][npk]  (K^-1 blocks)
     float* W = nullptr;              // [npk][ni] Fisher weights (build)
@@ -286,7 +286,9 @@ struct Problem {
     float* coef = nullptr;           // [K][ny][nx] Haar coefficients
     float* coarse = nullptr;         // [K][ny/T][nx/T]
     int built[4] = {0, 0, 0, 0};
-    int m0_built = 0;
+    // Fisher weights W and M0 in use: 0 none, 1 from the data (modified),
+    // 2 from a reference image and / or M0 = I (mbmd_precond_build_ex)
+    int m0_state = 0;
     int n_floored[4] = {0, 0, 0, 0};
     // reductions
     double* partials = nullptr;      // [kRegions][kMaxPartials]
@@ -346,7 +348,9 @@ void launch_curvature(const RayArgs& a, const float* l, const float* r, const fl
                       const float* x, const float* p, double* partials, int* counts, hipStream_t s);
 void launch_forward_model(const RayArgs& a, const float* l, float* ybar, hipStream_t s);
 void launch_forward_vjp(const RayArgs& a, const float* l, const float* gbar, float* sk, hipStream_t s);
-void launch_fisher(const RayArgs& a, float* W, hipStream_t s);
+// Fisher weights [npk][ni]; lref [K][ni]: reference line integrals (D the
+// transmission there), or NULL for the data-based D.
+void launch_fisher(const RayArgs& a, float* W, hipStream_t s, const float* lref = nullptr);
 void launch_fisher_mix(int ni, int K, const float* W, const float* in, float* out, hipStream_t s);
 int launch_identity_iterate(const RayArgs& a, float* x, const float* M0, int precond, int n_iter,
                             double* partials_per_iter, int stride, hipStream_t s);

@@ -332,11 +332,14 @@ __global__ __launch_bounds__(kRayThreads) void k_forward_vjp(RayModel m, int ni,
     for (int k = 0; k < K; ++k) sk[(size_t)k * ni + i] = acc[k];
 }
 
-// Fisher weights W_i = J^T diag(w) J, J[c,k] = -sum_E S_cE D_E Q_Ek, with the
-// data-based D: y / I0 for one energy and channel, else exp(-mu_w(E) l_w)
-// from a 10-step Gauss-Newton water-only estimate (material 0 is water).
+// Fisher weights W_i = J^T diag(w) J, J[c,k] = -sum_E S_cE D_E Q_Ek, with D
+// the transmission exp(-sum_k Q_Ek lref_k) at reference line integrals lref
+// [K][ni] when given, else the data-based D: y / I0 for one energy and
+// channel, else exp(-mu_w(E) l_w) from a 10-step Gauss-Newton water-only
+// estimate (material 0 is water).
 __global__ __launch_bounds__(kRayThreads) void k_fisher(RayModel m, int ni, const float* __restrict__ y,
                                                         const float* __restrict__ w,
+                                                        const float* __restrict__ lref,
                                                         float* __restrict__ W) {
     const int i = blockIdx.x * kRayThreads + threadIdx.x;
     if (i >= ni) return;
@@ -347,7 +350,21 @@ __global__ __launch_bounds__(kRayThreads) void k_fisher(RayModel m, int ni, cons
         wc[c] = w[(size_t)c * ni + i];
     }
     double J[kMaxChan][kMaxMat];
-    if (m.E == 1 && m.C == 1) {
+    if (lref) {
+        double lk[kMaxMat];
+        for (int k = 0; k < m.K; ++k) lk[k] = lref[(size_t)k * ni + i];
+        for (int c = 0; c < m.C; ++c)
+            for (int k = 0; k < m.K; ++k) J[c][k] = 0.0;
+        for (int e = 0; e < m.E; ++e) {
+            double le = 0.0;
+            for (int k = 0; k < m.K; ++k) le += (double)m.Q[e * m.K + k] * lk[k];
+            const double D = exp(-le);
+            for (int c = 0; c < m.C; ++c) {
+                const double sd = (double)m.S[c * m.E + e] * D;
+                for (int k = 0; k < m.K; ++k) J[c][k] -= sd * (double)m.Q[e * m.K + k];
+            }
+        }
+    } else if (m.E == 1 && m.C == 1) {
         const double D = yc[0] / (double)m.S[0];
         for (int k = 0; k < m.K; ++k) J[0][k] = -(double)m.S[0] * D * (double)m.Q[k];
     } else {
@@ -629,11 +646,11 @@ void launch_forward_vjp(const RayArgs& a, const float* l, const float* gbar, flo
     MBMD_LAUNCHED();
 }
 
-void launch_fisher(const RayArgs& a, float* W, hipStream_t s) {
+void launch_fisher(const RayArgs& a, float* W, hipStream_t s, const float* lref) {
     {
         KernelTimer kt_("k_fisher", s);
         hipLaunchKernelGGL(k_fisher, dim3(blocks_for(a.ni)), dim3(kRayThreads), 0, s, model_of(a), a.ni, a.y,
-                       a.w, W);
+                       a.w, lref, W);
         kt_.stop();
     }
     MBMD_LAUNCHED();

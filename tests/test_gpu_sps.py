@@ -193,3 +193,66 @@ def test_gradient_rows_fused_match_separate_launches(name, monkeypatch):
     monkeypatch.delenv("MBMD_FUSE_ROWS")
     assert fused_launches[0] == 0 and fused_launches[1] >= 11, fused_launches   # the first one tunes
     np.testing.assert_array_equal(out[1], out[0])
+
+
+def _x_ref(wl):
+    """A reference image near the solution: the phantom, smoothed by a
+    positive perturbation (not the data's own image)."""
+    rng = np.random.default_rng(21)
+    return np.abs(wl.x_true) * (1.0 + 0.1 * rng.uniform(size=wl.x_true.shape))
+
+
+@pytest.mark.parametrize("case", ["fan64", "mbmd32"])
+@pytest.mark.parametrize("kind,modified,ref", [("fourier", False, False), ("haar", False, False),
+                                               ("fourier", True, True), ("haar", True, True),
+                                               ("blockdiag", True, True), ("fourier", False, True)])
+def test_precond_build_options_match_oracle(kind, modified, ref, case):
+    """mbmd_precond_build_ex: M0 = I (unmodified) and / or the Fisher weights at
+    a reference image; M M^T g against the oracle built the same way."""
+    wl = (C.make_small_fan(n=64, views=90, bins=128) if case == "fan64"
+          else C.make_small_mbmd(n=32, views=60, bins=64, n_mat=3))
+    op = oracle.OracleProblem.from_workload(wl)
+    g = np.random.default_rng(13).normal(size=wl.x_true.shape)
+    x_ref = _x_ref(wl) if ref else None
+    announce("precond_build_ex", case, kind, modified, ref)
+    P = mb.Problem.from_workload(wl)
+    P.precond_build(kind, modified=modified, x_ref=dev(x_ref) if ref else None)
+    got = host(P.precond_apply(kind, dev(g)))
+    tab = opre.build(op, kind, modified=modified, x_ref=x_ref)
+    want = opre.apply_M(tab, opre.apply_Mt(tab, g))
+    assert l2rel(got, want) <= TOL_APPLY, l2rel(got, want)
+
+
+def test_rebuild_voids_the_other_preconditioners():
+    """Fisher weights and M0 are shared: after a build with options the other
+    preconditioners must be built again, and a plain build restores the
+    data-based ones (bitwise the first build's apply)."""
+    wl = C.make_small_fan(n=64, views=90, bins=128)
+    g = dev(np.random.default_rng(14).normal(size=wl.x_true.shape))
+    announce("precond rebuild")
+    P = mb.Problem.from_workload(wl)
+    P.precond_build("fourier")
+    P.precond_build("haar")
+    first = host(P.precond_apply("fourier", g))
+    P.precond_build("fourier", x_ref=dev(_x_ref(wl)))
+    with pytest.raises(RuntimeError):
+        P.precond_apply("haar", g)
+    P.precond_build("fourier")
+    np.testing.assert_array_equal(host(P.precond_apply("fourier", g)), first)
+
+
+def test_sps_with_a_rebuild_from_the_iterate():
+    """10 Fourier-preconditioned iterations, a rebuild with the Fisher weights
+    at the current iterate, 10 more: against the oracle doing the same."""
+    wl = C.make_small_fan(n=64, views=90, bins=128, penalty="huber")
+    announce("sps rebuild from iterate")
+    P = mb.Problem.from_workload(wl)
+    P.precond_build("fourier")
+    x = P.zeros_image()
+    P.sps_step(x, "fourier", 10)
+    P.precond_build("fourier", x_ref=x.clone())
+    P.sps_step(x, "fourier", 10)
+    op = oracle.OracleProblem.from_workload(wl)
+    xo, _, _ = osps.sps_precond(op, opre.build(op, "fourier"), 10)
+    xo, _, _ = osps.sps_precond(op, opre.build(op, "fourier", x_ref=xo), 10, x0=xo)
+    assert _rmse(host(x), xo) <= TOL_ITER, _rmse(host(x), xo)
