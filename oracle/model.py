@@ -27,9 +27,29 @@ def transmission(prob, l):
     return np.exp(-energy_line_integrals(prob, l))
 
 
+def blur_matrix(prob, c):
+    """B_c [B, B] of channel c: entry (b, b + d) = taps[c, d + h] for |d| <= h."""
+    taps = prob.blur[c]
+    h = (taps.size - 1) // 2
+    nb = prob.geom["n_bins"]
+    return sum(taps[d + h] * np.eye(nb, k=d) for d in range(-h, h + 1))
+
+
+def blur(prob, z, transpose=False):
+    """B z (or B^T z) for z [N_c, V, B], per channel along each view's bins;
+    z itself when the problem has no blur."""
+    if prob.blur is None:
+        return z
+    out = np.empty_like(z)
+    for c in range(prob.n_chan):
+        Bm = blur_matrix(prob, c)
+        out[c] = z[c] @ (Bm if transpose else Bm.T)
+    return out
+
+
 def mean_counts(prob, t):
-    """ybar_ic = sum_E S_cE t_iE  (BB exp(-AA x))."""
-    return np.einsum("ce,evb->cvb", prob.S, t)
+    """ybar_ic = (B_c sum_E S_cE t_E)_i  (BB exp(-AA x))."""
+    return blur(prob, np.einsum("ce,evb->cvb", prob.S, t))
 
 
 def forward(prob, x):
@@ -49,9 +69,9 @@ def objective(prob, x):
 
 
 def hdot(prob, t):
-    """dL/dl_iE = -t_iE sum_c S_cE w_ic (ybar_ic - y_ic)."""
+    """dL/dl_iE = -t_iE sum_c S_cE [B_c^T W_c (ybar_c - y_c)]_i."""
     ybar = mean_counts(prob, t)
-    r = prob.w * (ybar - prob.y)
+    r = blur(prob, prob.w * (ybar - prob.y), transpose=True)
     return -t * np.einsum("ce,cvb->evb", prob.S, r)
 
 
@@ -69,9 +89,10 @@ def gradient(prob, x):
 def forward_vjp(prob, x, gbar):
     """Vector-Jacobian product of ybar(x): returns d<gbar, ybar(x)>/dx.
 
-    = A^T [ sum_E Q_Ek (-t_iE) sum_c S_cE gbar_ic ], the backward of the
-    polyenergetic forward model.
+    = A^T [ sum_E Q_Ek (-t_iE) sum_c S_cE (B_c^T gbar_c)_i ], the backward of
+    the polyenergetic forward model.
     """
     t = transmission(prob, line_integrals(prob, x))
-    s = np.einsum("ek,evb->kvb", prob.Q, -t * np.einsum("ce,cvb->evb", prob.S, gbar))
+    gb = blur(prob, gbar, transpose=True)
+    s = np.einsum("ek,evb->kvb", prob.Q, -t * np.einsum("ce,cvb->evb", prob.S, gb))
     return projector.backproject(prob.geom, s)

@@ -10,7 +10,11 @@ Methods, "Preconditioned Optimization" and the per-application sections:
     first basis material plays water.  The estimate takes 10 Gauss-Newton
     steps from 0 on sum_c w (y - sum_E S exp(-mu_w l))^2, clamped at l >= 0.
     Per ray J[c,k] = -sum_E S_cE D_iE Q_Ek and W_i = J^T diag(w_i) J, so
-    H v = A^T [W_i (A v)_i] + (beta (x) Gamma) v.
+    H v = A^T [W_i (A v)_i] + (beta (x) Gamma) v.  With a projection-domain
+    blur B the data term couples neighbouring bins: H v = A^T [J^T B^T W B J
+    (A v)] + (beta (x) Gamma) v, with J the per-ray Jacobian of the unblurred
+    means (the Hessian formulas with BB = B S).  The data-based D then ignores
+    the blur (the estimate is per ray, from the blurred counts).
   * M0 (eq:diagonalPreconditioner; eq:materialColumns and the MBMD
     cross-material preconditioner): the N_k x N_k block of pixel j is read
     from the material columns (F + R) 1_k (row sums, i.e. the zero-frequency
@@ -83,16 +87,29 @@ def transmission_estimate(prob, x_ref=None):
 
 def fisher_weights(prob, x_ref=None):
     """W_i = J_i^T diag(w_i) J_i  ->  [N_k, N_k, V, B], J = -S D{D_i} Q with D
-    from transmission_estimate(prob, x_ref)."""
+    from transmission_estimate(prob, x_ref).  With a blur the data term does
+    not split by ray, and J itself [N_c, N_k, V, B] is returned (see
+    fisher_sino_apply)."""
     D = transmission_estimate(prob, x_ref)
     J = -np.einsum("ce,evb,ek->ckvb", prob.S, D, prob.Q)
+    if prob.blur is not None:
+        return J
     return np.einsum("cvb,ckvb,clvb->klvb", prob.w, J, J)
 
 
+def fisher_sino_apply(prob, W, q):
+    """The data part of the Fisher information on line integrals q [N_k, V, B]:
+    W_i q_i per ray, or with a blur J^T B^T W B J q (W holding J)."""
+    if prob.blur is None:
+        return np.einsum("klvb,lvb->kvb", W, q)
+    z = model.blur(prob, np.einsum("ckvb,kvb->cvb", W, q))
+    return np.einsum("ckvb,cvb->kvb", W, model.blur(prob, prob.w * z, transpose=True))
+
+
 def hessian_apply(prob, W, v):
-    """H v = A^T [W (A v)] + (beta (x) Gamma) v for v [N_k, ny, nx]."""
+    """H v = A^T [F_data (A v)] + (beta (x) Gamma) v for v [N_k, ny, nx]."""
     Av = projector.project(prob.geom, v)
-    return projector.backproject(prob.geom, np.einsum("klvb,lvb->kvb", W, Av)) + pen.hessian_apply(prob, v)
+    return projector.backproject(prob.geom, fisher_sino_apply(prob, W, Av)) + pen.hessian_apply(prob, v)
 
 
 def block_inv_sqrt(blocks, floor_rel=None, floor_abs=None):

@@ -2,7 +2,13 @@
 
 Mean model (eq:meanModel): ybar(x) = BB exp(-AA x), with
   AA = Q (x) A  (material spectra times the projector; one-step MBMD),
-  BB = S        (channel sensitivity with gain and I0 folded in; blur = I).
+  BB = B S      (channel sensitivity S with gain and I0 folded in, then the
+                 projection-domain blur B of the standard-CT, projection-domain
+                 and MBMD models; B = I unless a blur is given).
+The blur, when given, acts per channel along the detector bins of each view:
+taps [N_c, 2h+1], (B_c z)_b = sum_{|d|<=h} taps[c, d+h] z_{b+d}, with bins
+beyond the detector dropped; the taps are non-negative, so that BB^T W BB has
+no negative entry and the decoupled surrogate of the SPS section majorises.
 Standard CT is N_k = N_E = N_c = 1 with S = I0, Q = 1; projection-domain
 decomposition is the identity geometry (A = I).
 
@@ -27,6 +33,7 @@ class OracleProblem:
     y: np.ndarray
     w: np.ndarray
     penalty: dict
+    blur: np.ndarray = None
 
     def __post_init__(self):
         self.Q = np.asarray(self.Q, dtype=np.float64)
@@ -38,6 +45,11 @@ class OracleProblem:
                             delta=float(self.penalty.get("delta", 0.0)))
         if self.penalty["kind"] == "huber" and self.n_mat != 1:
             raise ValueError("the Huber penalty is defined for one material only")
+        if self.blur is not None:
+            self.blur = np.atleast_2d(np.asarray(self.blur, dtype=np.float64))
+            if (self.blur.shape[0] != self.n_chan or self.blur.shape[1] % 2 != 1
+                    or np.any(self.blur < 0.0) or not np.all(np.isfinite(self.blur))):
+                raise ValueError("blur taps must be finite, non-negative, [n_chan, 2h+1]")
         if self.geom["kind"] == "identity":
             assert self.geom["nx"] == self.geom["n_bins"] and self.geom["ny"] == self.geom["n_views"]
 

@@ -5,7 +5,7 @@ with these readings of its garbled or silent points:
   * rho (the linear coefficient of the decoupled surrogate) is written there
     with x^(n) where the transmission t^(n) = exp(-AA x^(n)) is meant:
         rho = BB^T Sigma^-1 BB t - D{eta} t - BB^T Sigma^-1 y
-            = S^T W (ybar - y) - eta * t ;
+            = S^T B^T W (ybar - y) - eta * t ;
   * the surrogate gradient reads AA^T(-D{eta} t^2 - D{rho} t) (the printed
     D{gamma} is a typo for D{eta}); it equals the true gradient at x^(n);
   * the maximum curvature f_c is that of h(l) = eta/2 e^-2l + rho e^-l over
@@ -43,9 +43,11 @@ def gamma(prob):
 
 
 def eta(prob):
-    """eta = BB^T Sigma^-1 BB 1 per (energy, ray)."""
+    """eta = BB^T Sigma^-1 BB 1 per (energy, ray), BB = B S:
+    sum_c S_cE (sum_E' S_cE') [B_c^T W_c B_c 1]_i."""
     row = prob.S.sum(axis=1)                                  # sum_E' S_cE'
-    return np.einsum("ce,cvb->evb", prob.S, prob.w * row[:, None, None])
+    wb = model.blur(prob, prob.w * model.blur(prob, np.ones_like(prob.w)), transpose=True)
+    return np.einsum("ce,cvb->evb", prob.S, wb * row[:, None, None])
 
 
 def ray_terms(prob, l):
@@ -53,7 +55,8 @@ def ray_terms(prob, l):
     t = model.transmission(prob, l)
     ybar = model.mean_counts(prob, t)
     et = eta(prob)
-    rho = np.einsum("ce,cvb->evb", prob.S, prob.w * (ybar - prob.y)) - et * t
+    rho = np.einsum("ce,cvb->evb", prob.S,
+                    model.blur(prob, prob.w * (ybar - prob.y), transpose=True)) - et * t
     hdot = -et * t * t - rho * t
     c = np.maximum(2.0 * et + rho, 0.0)
     return t, ybar, rho, hdot, c
