@@ -220,6 +220,33 @@ int mbmd_precond_build(mbmd_problem* prob, int kind, void* stream);
  */
 int mbmd_precond_build_ex(mbmd_problem* prob, int kind, int flags, const float* x_ref_dev, void* stream);
 
+/* Largest half width of a projection-domain blur (9 taps). */
+#define MBMD_MAX_BLUR_HALF 4
+
+/*
+ * Projection-domain blur (the operator B of the standard-CT,
+ * projection-domain and one-step MBMD models: the mean becomes
+ * ybar = B S exp(-AA x), e.g. focal spot and detector blur).  Per channel c,
+ * along the bins of each view: (B_c z)_b = sum_{|d|<=h} taps[c][d + h]
+ * z_{b+d}, bins beyond the detector dropped.
+ *   - taps_host: host array [n_chan][2 h + 1] (copied; non-negative and
+ *     finite, so that the decoupled SPS surrogate still majorises);
+ *   - half_width h: 1..MBMD_MAX_BLUR_HALF, or 0 to remove the blur (taps may
+ *     then be NULL).
+ * Every later call uses it: the objective, gradient, SPS iterations
+ * (eta = BB^T W BB 1 and rho = BB^T W (ybar - y) - eta t of the SPS
+ * section, so the one-energy curvature is recomputed every iteration), the
+ * forward model and its VJP, and the preconditioner builds (Fisher
+ * information A^T J^T B^T W B J A; the data-based D ignores the blur).  It
+ * voids every preconditioner built before it.  The first call with h > 0
+ * allocates (3 + n_mat) n_chan n_rays floats on the device, freed by
+ * mbmd_problem_destroy.  Asynchronous on `stream`.
+ * Errors: MBMD_ERR_ARG (NULL problem, h out of range, NULL, negative or
+ * non-finite taps), MBMD_ERR_UNSUPPORTED (identity geometry, whose rays the
+ * blur would couple), MBMD_ERR_HIP.
+ */
+int mbmd_problem_set_blur(mbmd_problem* prob, const float* taps_host, int half_width, void* stream);
+
 /*
  * out_dev = M M^T g_dev for a built preconditioner (the direction operator
  * of the preconditioned SPS step, without its minus sign); for

@@ -14,7 +14,10 @@ Methods, "Preconditioned Optimization" and the per-application sections:
     blur B the data term couples neighbouring bins: H v = A^T [J^T B^T W B J
     (A v)] + (beta (x) Gamma) v, with J the per-ray Jacobian of the unblurred
     means (the Hessian formulas with BB = B S).  The data-based D then ignores
-    the blur (the estimate is per ray, from the blurred counts).
+    the blur (the estimate is per ray, from the blurred counts).  The blur
+    also makes the off-diagonal material blocks of F non-symmetric across
+    pixels, so the material columns below give non-symmetric Htilde_j; their
+    symmetric part is used (block_inv_sqrt symmetrises).
   * M0 (eq:diagonalPreconditioner; eq:materialColumns and the MBMD
     cross-material preconditioner): the N_k x N_k block of pixel j is read
     from the material columns (F + R) 1_k (row sums, i.e. the zero-frequency

@@ -41,6 +41,7 @@ _SIGNATURES = {
     "mbmd_problem_destroy": (None, [c_void_p]),
     "mbmd_precond_build": (c_int, [c_void_p, c_int, c_void_p]),
     "mbmd_precond_build_ex": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p]),
+    "mbmd_problem_set_blur": (c_int, [c_void_p, c_void_p, c_int, c_void_p]),
     "mbmd_precond_apply": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
     "mbmd_gradient": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, P(c_double), c_void_p]),
     "mbmd_sps_step": (c_int, [c_void_p, c_void_p, c_int, c_int, P(c_double), c_void_p]),

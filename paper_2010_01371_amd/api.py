@@ -136,6 +136,21 @@ class Problem:
     def zeros_image(self):
         return torch.zeros(self.image_shape, device=self.device, dtype=torch.float32)
 
+    def set_blur(self, taps=None):
+        """mbmd_problem_set_blur: taps [n_chan, 2 h + 1] (one row is used for
+        every channel), or None to remove the blur."""
+        if taps is None:
+            check(self._lib.mbmd_problem_set_blur(self._h, None, 0, _stream()), "mbmd_problem_set_blur")
+            return
+        t = np.atleast_2d(np.asarray(taps, dtype=np.float32))
+        if t.shape[0] == 1 and self.n_chan > 1:
+            t = np.repeat(t, self.n_chan, axis=0)
+        if t.ndim != 2 or t.shape[0] != self.n_chan or t.shape[1] % 2 != 1:
+            raise ValueError("blur taps must be [n_chan, 2h+1], got %s" % (t.shape,))
+        t = np.ascontiguousarray(t)
+        check(self._lib.mbmd_problem_set_blur(self._h, t.ctypes.data_as(ctypes.c_void_p), (t.shape[1] - 1) // 2,
+                                              _stream()), "mbmd_problem_set_blur")
+
     def precond_build(self, kind, modified=True, x_ref=None):
         """mbmd_precond_build, or mbmd_precond_build_ex with M0 = I
         (modified=False) and / or the Fisher weights at the image x_ref."""

@@ -88,7 +88,8 @@ int guarded(F&& f) {
 bool is_pow2(int n) { return n >= 2 && (n & (n - 1)) == 0; }
 
 RayArgs ray_args(const Problem& P) {
-    return RayArgs{P.ni, P.K, P.E, P.C, P.Q, P.S, P.rowS, P.Qsum, P.y, P.w, P.identity ? nullptr : P.gammaA};
+    return RayArgs{P.ni, P.K, P.E, P.C, P.Q, P.S, P.rowS, P.Qsum, P.y, P.w, P.identity ? nullptr : P.gammaA,
+                   P.blur.h ? P.wb : P.w, P.blur, P.btmp0, P.btmp1};
 }
 
 PenaltyArgs pen_args(const Problem& P) {
@@ -168,7 +169,21 @@ void carve(Problem& P) {
     P.flags = A.take<int>(4);
 }
 
-// r = M0 H M0 v (or H v when M0 is NULL), H = A^T W A + beta Gamma (quadratic).
+// The data part of the Fisher information on line integrals in [K][ni] ->
+// out [K][ni] (distinct buffers): W_i in_i per ray, or with a blur
+// J^T B^T W B J in (J per ray, the blur coupling the bins of a view).
+void fisher_sino_apply(Problem& P, const float* in, float* out, hipStream_t s) {
+    if (P.blur.h == 0) {
+        launch_fisher_mix(P.ni, P.K, P.W, in, out, s);
+        return;
+    }
+    launch_jmix(P.ni, P.K, P.C, P.J, in, P.btmp0, false, s);
+    launch_blur(P.blur, P.ni, P.C, P.btmp0, P.w, P.btmp1, false, s);
+    launch_blur(P.blur, P.ni, P.C, P.btmp1, nullptr, P.btmp0, true, s);
+    launch_jmix(P.ni, P.K, P.C, P.J, P.btmp0, out, true, s);
+}
+
+// r = M0 H M0 v (or H v when M0 is NULL), H = A^T F_data A + beta Gamma (quadratic).
 void hessian_apply(Problem& P, const float* v, float* out, const float* M0, hipStream_t s) {
     const float* src = v;
     if (M0) {
@@ -176,7 +191,7 @@ void hessian_apply(Problem& P, const float* v, float* out, const float* M0, hipS
         src = P.p_img;
     }
     project(P, src, P.q, P.K, s);
-    launch_fisher_mix(P.ni, P.K, P.W, P.q, P.sino_tmp, s);
+    fisher_sino_apply(P, P.q, P.sino_tmp, s);
     backproject(P, P.sino_tmp, out, P.K, s);
     if (P.has_penalty) launch_penalty_hess_add(pen_args(P), src, out, s);
     if (M0) launch_block_apply(P.nj, P.K, M0, out, out, 1.0f, s);
@@ -188,10 +203,24 @@ void hessian_apply(Problem& P, const float* v, float* out, const float* M0, hipS
 // rebuild from a reference image, voids the preconditioners built on the old
 // ones.
 void build_fisher_m0(Problem& P, int state, const float* lref, bool modified, hipStream_t s) {
-    launch_fisher(ray_args(P), P.W, s, lref);
+    launch_fisher(ray_args(P), P.W, s, lref, P.blur.h ? P.J : nullptr);
     if (!modified) {
         launch_fill(P.npk * P.nj, P.M0, 0.0f, s);
         for (int k = 0; k < P.K; ++k) launch_fill(P.nj, P.M0 + (size_t)packed_index(k, k, P.K) * P.nj, 1.0f, s);
+    } else if (P.blur.h) {
+        // Column k of Htilde = A^T F_data (gamma_A e_k), one material column at a
+        // time.  The blur makes the off-diagonal blocks of F non-symmetric across
+        // pixels, so their row sums (column k) and column sums (column k2)
+        // differ: keep the symmetric part, as the eigen-solve does.
+        launch_fill(P.npk * P.nj, P.t_img, 0.0f, s);
+        for (int k = 0; k < P.K; ++k) {
+            launch_fill(P.K * P.ni, P.q, 0.0f, s);
+            launch_scale_copy(P.ni, P.gammaA, P.q + (size_t)k * P.ni, 1.0f, s);
+            fisher_sino_apply(P, P.q, P.sino_tmp, s);
+            backproject(P, P.sino_tmp, P.g_img, P.K, s);
+            launch_block_add_column(P.nj, P.K, k, P.g_img, P.t_img, s);
+        }
+        launch_block_invsqrt(P.nj, P.K, P.t_img, P.M0, -0.5, kM0Floor, nullptr, 0.0, P.flags + 1, s);
     } else {
         // Htilde_j = column blocks of (F + R) 1_k = A^T (gamma_A W_kk')  (Gamma 1 = 0)
         if (P.identity) {
@@ -270,7 +299,8 @@ int apply_direction(Problem& P, int kind, const float* g, float* out, float sign
     }
 }
 
-bool single_energy(const Problem& P) { return P.E == 1 && P.C == 1; }
+// One energy and channel without a blur: the SPS curvature does not depend on x.
+bool single_energy(const Problem& P) { return P.E == 1 && P.C == 1 && P.blur.h == 0; }
 
 void ensure_dL_const(Problem& P, hipStream_t s) {
     if (P.dL_valid || !single_energy(P)) return;
@@ -326,7 +356,7 @@ void precond_iteration(Problem& P, float* x, int kind, double* trace_slot, hipSt
     // back projection kernel follows.  With many energies per ray the fused
     // launch, one workgroup per view, has too few threads for the ray work.
     const float* part = nullptr;                                       // summed by the penalty pass
-    const bool fuse = !P.identity && P.E == 1 && fuse_rows_enabled();
+    const bool fuse = !P.identity && P.E == 1 && P.blur.h == 0 && fuse_rows_enabled();
     const BackRows br = fuse ? back_rows(*P.geom, P.g_img, P.K) : BackRows{};
     const int n_rows = br.ok ? launch_ray_grad_rows(ray_args(P), P.l, P.r, region(P, R_PHI_L), s, up, br) : -1;
     if (n_rows >= 0) {
@@ -604,11 +634,59 @@ void mbmd_problem_destroy(mbmd_problem* prob) {
     if (!prob) return;
     (void)hipStreamSynchronize(prob->last_stream);
     prob->arena.release();
+    prob->blur_arena.release();
     if (prob->geom) {
         free_geometry(*prob->geom);
         delete prob->geom;
     }
     delete prob;
+}
+
+int mbmd_problem_set_blur(mbmd_problem* prob, const float* taps_host, int half_width, void* stream) {
+    return guarded([&] {
+        MBMD_REQUIRE(prob != nullptr, MBMD_ERR_ARG, "NULL problem");
+        Problem& P = *prob;
+        static_assert(MBMD_MAX_BLUR_HALF == kMaxBlurHalf, "blur limit of the header and the kernels");
+        MBMD_REQUIRE(half_width >= 0 && half_width <= kMaxBlurHalf, MBMD_ERR_ARG, "blur half width out of range");
+        MBMD_REQUIRE(!P.identity || half_width == 0, MBMD_ERR_UNSUPPORTED, "no blur on the identity geometry");
+        BlurArgs b;
+        if (half_width > 0) {
+            MBMD_REQUIRE(taps_host != nullptr, MBMD_ERR_ARG, "NULL blur taps");
+            const int nt = 2 * half_width + 1;
+            for (int c = 0; c < P.C; ++c)
+                for (int t = 0; t < nt; ++t) {
+                    const float v = taps_host[c * nt + t];
+                    MBMD_REQUIRE(std::isfinite(v) && v >= 0.0f, MBMD_ERR_ARG, "blur taps must be finite and >= 0");
+                    b.taps[c][t] = v;
+                }
+            b.h = half_width;
+            b.B = P.B;
+        }
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        P.last_stream = s;
+        if (b.h > 0 && P.blur_arena.base == nullptr) {
+            Arena& A = P.blur_arena;
+            const size_t ni = P.ni, C = P.C, K = P.K;
+            auto carve_blur = [&] {
+                P.wb = A.take<float>(C * ni);
+                P.J = A.take<float>(C * K * ni);
+                P.btmp0 = A.take<float>(C * ni);
+                P.btmp1 = A.take<float>(C * ni);
+            };
+            carve_blur();                                   // sizing pass
+            A.reserve(A.used + 4096);
+            carve_blur();
+        }
+        if (b.h > 0) {                                      // wb = B^T (w B 1)
+            launch_fill(P.C * P.ni, P.btmp0, 1.0f, s);
+            launch_blur(b, P.ni, P.C, P.btmp0, P.w, P.btmp1, false, s);
+            launch_blur(b, P.ni, P.C, P.btmp1, nullptr, P.wb, true, s);
+        }
+        P.blur = b;
+        P.dL_valid = 0;
+        P.m0_state = 0;
+        for (int k = 0; k < 4; ++k) P.built[k] = 0;
+    });
 }
 
 int mbmd_precond_build_ex(mbmd_problem* prob, int kind, int flags, const float* x_ref_dev, void* stream) {

@@ -125,6 +125,20 @@ __global__ void k_scale_copy(int n, const float* __restrict__ in, float* __restr
     if (i < n) out[i] = scale * in[i];
 }
 
+// Adds material column k_col of per-pixel blocks (col [K][nj]: entry (k2, k_col)
+// at channel k2) to the packed symmetric blocks: the diagonal entry whole, the
+// others half each (the other half comes from column k2), which gives the
+// symmetric part of blocks that are not exactly symmetric.
+__global__ void k_block_add_column(int nj, int K, int k_col, const float* __restrict__ col,
+                                   float* __restrict__ packed) {
+    const int j = blockIdx.x * kThreads + threadIdx.x;
+    if (j >= nj) return;
+    for (int k2 = 0; k2 < K; ++k2) {
+        const float wgt = k2 == k_col ? 1.0f : 0.5f;
+        packed[(size_t)packed_index(k2, k_col, K) * nj + j] += wgt * col[(size_t)k2 * nj + j];
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_dot(int n, const float* __restrict__ a,
                                                   const float* __restrict__ b,
                                                   double* __restrict__ partials) {
@@ -387,6 +401,15 @@ void launch_fill(int n, float* x, float value, hipStream_t s) {
     {
         KernelTimer kt_("k_fill", s);
         hipLaunchKernelGGL(k_fill, dim3(nblk(n)), dim3(kThreads), 0, s, n, x, value);
+        kt_.stop();
+    }
+    MBMD_LAUNCHED();
+}
+
+void launch_block_add_column(int nj, int K, int k_col, const float* col, float* packed, hipStream_t s) {
+    {
+        KernelTimer kt_("k_block_add_column", s);
+        hipLaunchKernelGGL(k_block_add_column, dim3(nblk(nj)), dim3(kThreads), 0, s, nj, K, k_col, col, packed);
         kt_.stop();
     }
     MBMD_LAUNCHED();

@@ -17,6 +17,17 @@ constexpr int kMaxMat = 4;
 constexpr int kMaxChan = 8;
 constexpr int kMaxEnergy = 256;
 constexpr int kMaxPacked = kMaxMat * (kMaxMat + 1) / 2;   // symmetric N_k x N_k, packed
+constexpr int kMaxBlurHalf = 4;                            // projection-domain blur: at most 9 taps
+constexpr int kBlurTaps = 2 * kMaxBlurHalf + 1;
+
+// Projection-domain blur, per channel along the bins of each view: row b of
+// channel c is (B_c z)_b = sum_{|d|<=h} taps[c][d + h] z_{b+d}, bins beyond
+// the detector dropped.  h = 0: no blur.
+struct BlurArgs {
+    int h = 0;
+    int B = 0;                         // bins per view
+    float taps[kMaxChan][kBlurTaps] = {};
+};
 constexpr int kMaxBackCh = 10;                              // channels of one backprojection
 constexpr int kMaxGpus = 64;                                // devices with cached per-device launch data
 constexpr int kRefreshEvery = 25;                           // recompute l = A x this often
@@ -280,6 +291,13 @@ struct Problem {
     float* Linv = nullptr;           // [ny][nx][npk]  (L^-1 blocks)
     float* Kinv = nullptr;           // [ny][nx][npk]  (K^-1 blocks)
     float* W = nullptr;              // [npk][ni] Fisher weights (build)
+    // projection-domain blur (mbmd_problem_set_blur); buffers in blur_arena
+    BlurArgs blur;
+    Arena blur_arena;
+    float* wb = nullptr;             // [C][ni] B^T W B 1 (the eta factor)
+    float* J = nullptr;              // [C][K][ni] Jacobian of the unblurred means (build)
+    float* btmp0 = nullptr;          // [C][ni] scratch
+    float* btmp1 = nullptr;          // [C][ni] scratch
     float2* spec = nullptr;          // [K][ny][nx] complex scratch
     float2* tw_x = nullptr;          // twiddles for nx
     float2* tw_y = nullptr;          // twiddles for ny
@@ -310,6 +328,9 @@ struct RayArgs {
     int ni, K, E, C;
     const float *Q, *S, *rowS, *Qsum;    // device spectral model
     const float *y, *w, *gammaA;         // [C][ni], [C][ni], [ni] (NULL gammaA = 1)
+    const float* wb;                     // [C][ni] eta factor B^T W B 1 (= w without a blur)
+    BlurArgs blur;
+    float *tmp0, *tmp1;                  // [C][ni] scratch of the blurred passes
 };
 struct PenaltyArgs {
     int K, nx, ny, kind;
@@ -350,7 +371,13 @@ void launch_forward_model(const RayArgs& a, const float* l, float* ybar, hipStre
 void launch_forward_vjp(const RayArgs& a, const float* l, const float* gbar, float* sk, hipStream_t s);
 // Fisher weights [npk][ni]; lref [K][ni]: reference line integrals (D the
 // transmission there), or NULL for the data-based D.
-void launch_fisher(const RayArgs& a, float* W, hipStream_t s, const float* lref = nullptr);
+void launch_fisher(const RayArgs& a, float* W, hipStream_t s, const float* lref = nullptr, float* J = nullptr);
+// Per channel c and ray i: out = wt * (B z) (transpose: B^T z; wt NULL: 1).
+void launch_blur(const BlurArgs& b, int ni, int C, const float* in, const float* wt, float* out, bool transpose,
+                 hipStream_t s);
+// Per ray, with J [C][K][ni]: out_c = sum_k J_ck in_k ([K][ni] -> [C][ni]), or
+// transposed out_k = sum_c J_ck in_c.
+void launch_jmix(int ni, int K, int C, const float* J, const float* in, float* out, bool transpose, hipStream_t s);
 void launch_fisher_mix(int ni, int K, const float* W, const float* in, float* out, hipStream_t s);
 int launch_identity_iterate(const RayArgs& a, float* x, const float* M0, int precond, int n_iter,
                             double* partials_per_iter, int stride, hipStream_t s);
@@ -374,7 +401,9 @@ void launch_scale_copy(int n, const float* in, float* out, float scale, hipStrea
 int launch_dot(int n, const float* a, const float* b, double* partials, hipStream_t s);
 void launch_block_apply(int nj, int K, const float* M, const float* in, float* out, float scale,
                         hipStream_t s);
-void launch_block_pack_from_images(int nj, int K, const float* cols, float* packed, hipStream_t s);
+// packed [npk][nj] += the symmetric share of material column k_col, col [K][nj]
+// (entry (k2, k_col) of every pixel's block at channel k2).
+void launch_block_add_column(int nj, int K, int k_col, const float* col, float* packed, hipStream_t s);
 void launch_block_invsqrt(int n, int K, const float* in_packed, float* out_packed, double power,
                           double floor_rel, const double* floor_abs_scaled, double eps,
                           int* n_floored, hipStream_t s);

@@ -10,7 +10,11 @@
 //   hdot_E = -t_E s_E                      (dL/dl_E)
 //   c_E    = max(2 eta_E + s_E - eta_E t_E, 0)   (maximum curvature on l >= 0)
 // and accumulates u_k = sum_E Q_Ek hdot_E and v_k = sum_E Q_Ek gamma_E c_E
-// with gamma_E = (A 1)_i sum_k Q_Ek.  The spectral model Q, S is read with
+// with gamma_E = (A 1)_i sum_k Q_Ek.  With a projection-domain blur B (BB =
+// B S) the residual couples neighbouring bins, and the pass splits in three
+// launches: the unblurred means ybar0 = S t, then r = W (B ybar0 - y) with the
+// objective, then the energy pass with B^T r in place of r and B^T W B 1 in
+// place of w in eta.  The spectral model Q, S is read with
 // wave-uniform indices (scalar loads).  Objective partial sums are FP64 and
 // reduced per block in a fixed order.
 #include <cmath>
@@ -70,18 +74,12 @@ __device__ __forceinline__ void channel_means(const RayModel& m, const SharedMod
     }
 }
 
-// Ray i of the gradient pass: applies the pending step to its line integrals
-// (l += a q, a = the step size, 0 for none), and returns its share of the data
-// term of Phi, with uk[k] (and vk[k] when want_v) of the ray and the residuals
-// r_c stored to r_out (when not NULL).
-template <int KT, int CT>
-__device__ __forceinline__ double ray_grad_at(const RayModel& m, const SharedModel& sm, int ni, int i,
-                                              const float* __restrict__ l, const float* __restrict__ y,
-                                              const float* __restrict__ w, const float* __restrict__ gammaA,
-                                              float* __restrict__ r_out, const StepUpdate& up, float a,
-                                              bool want_v, float* uk, float* vk) {
-    const int K = KT ? KT : m.K, C = CT ? CT : m.C;
-    float lk[kMaxMat], ybar[kMaxChan], rc[kMaxChan], sig[kMaxChan];
+// Ray i's line integrals, after applying the pending step to them (l += a q,
+// a = the step size, 0 for none).
+template <int KT>
+__device__ __forceinline__ void ray_line_integrals(const RayModel& m, int ni, int i, const float* __restrict__ l,
+                                                   const StepUpdate& up, float a, float* lk) {
+    const int K = KT ? KT : m.K;
     if (a != 0.0f) {                                       // l += alpha q, then use it
         for (int k = 0; k < K; ++k) {
             lk[k] = fmaf(a, up.q[(size_t)k * ni + i], up.l[(size_t)k * ni + i]);
@@ -90,17 +88,16 @@ __device__ __forceinline__ double ray_grad_at(const RayModel& m, const SharedMod
     } else {
         for (int k = 0; k < K; ++k) lk[k] = l[(size_t)k * ni + i];
     }
-    channel_means<KT, CT>(m, sm, lk, ybar);
-    double phi = 0.0;
-    for (int c = 0; c < C; ++c) {
-        const float yc = y[(size_t)c * ni + i], wc = w[(size_t)c * ni + i];
-        const float dv = ybar[c] - yc;
-        rc[c] = wc * dv;
-        sig[c] = wc * m.rowS[c];
-        phi += 0.5 * (double)wc * (double)dv * (double)dv;
-        if (r_out) r_out[(size_t)c * ni + i] = rc[c];
-    }
-    const float gA = gammaA ? gammaA[i] : 1.0f;
+}
+
+// Pass 2 of a ray from its line integrals lk, the residual terms rc[c] (the
+// channel's share of BB^T W (ybar - y)) and sig[c] (its share of eta per unit
+// S_cE): uk[k], and vk[k] when want_v.
+template <int KT, int CT>
+__device__ __forceinline__ void ray_pass2(const RayModel& m, const SharedModel& sm, const float* lk,
+                                          const float* rc, const float* sig, float gA, bool want_v, float* uk,
+                                          float* vk) {
+    const int K = KT ? KT : m.K, C = CT ? CT : m.C;
     for (int k = 0; k < K; ++k) uk[k] = vk[k] = 0.0f;
 #pragma unroll 2
     for (int e = 0; e < m.E; ++e) {
@@ -121,7 +118,154 @@ __device__ __forceinline__ double ray_grad_at(const RayModel& m, const SharedMod
             for (int k = 0; k < K; ++k) vk[k] = fmaf(sm.Q[e * K + k], gc, vk[k]);
         }
     }
+}
+
+// Ray i of the gradient pass: applies the pending step to its line integrals,
+// and returns its share of the data term of Phi, with uk[k] (and vk[k] when
+// want_v) of the ray and the residuals r_c stored to r_out (when not NULL).
+template <int KT, int CT>
+__device__ __forceinline__ double ray_grad_at(const RayModel& m, const SharedModel& sm, int ni, int i,
+                                              const float* __restrict__ l, const float* __restrict__ y,
+                                              const float* __restrict__ w, const float* __restrict__ gammaA,
+                                              float* __restrict__ r_out, const StepUpdate& up, float a,
+                                              bool want_v, float* uk, float* vk) {
+    const int C = CT ? CT : m.C;
+    float lk[kMaxMat], ybar[kMaxChan], rc[kMaxChan], sig[kMaxChan];
+    ray_line_integrals<KT>(m, ni, i, l, up, a, lk);
+    channel_means<KT, CT>(m, sm, lk, ybar);
+    double phi = 0.0;
+    for (int c = 0; c < C; ++c) {
+        const float yc = y[(size_t)c * ni + i], wc = w[(size_t)c * ni + i];
+        const float dv = ybar[c] - yc;
+        rc[c] = wc * dv;
+        sig[c] = wc * m.rowS[c];
+        phi += 0.5 * (double)wc * (double)dv * (double)dv;
+        if (r_out) r_out[(size_t)c * ni + i] = rc[c];
+    }
+    ray_pass2<KT, CT>(m, sm, lk, rc, sig, gammaA ? gammaA[i] : 1.0f, want_v, uk, vk);
     return phi;
+}
+
+// The blur of channel c at ray i = view * b.B + bin, on a channel's rays z:
+// (B z)_bin = sum_d taps[d + h] z_{bin+d}, or (B^T z)_bin = sum_d taps[d + h]
+// z_{bin-d}, bins beyond the detector dropped.
+__device__ __forceinline__ float blur_at(const BlurArgs& b, const float* __restrict__ z, int i, int c,
+                                         bool transpose) {
+    const int bin = i % b.B, row0 = i - bin;
+    float s = 0.0f;
+    for (int d = -b.h; d <= b.h; ++d) {
+        const int bb = transpose ? bin - d : bin + d;
+        if (bb >= 0 && bb < b.B) s = fmaf(b.taps[c][d + b.h], z[row0 + bb], s);
+    }
+    return s;
+}
+
+// Blurred model, pass 1: the pending step (as k_ray_grad) and the unblurred
+// channel means ybar0_c = sum_E S_cE t_E of every ray.
+template <int KT, int CT>
+__global__ __launch_bounds__(kRayThreads) void k_ray_means(RayModel m, int ni, const float* __restrict__ l,
+                                                           float* __restrict__ ybar0, StepUpdate up, int nb_ray) {
+    __shared__ SharedModel sm;
+    if (up.alpha && (int)blockIdx.x >= nb_ray) {           // the image part of the step: x += alpha p
+        const float a = (float)*up.alpha;
+        const int i = ((int)blockIdx.x - nb_ray) * kRayThreads + threadIdx.x;
+        if (a != 0.0f && i < up.n_img) up.x[i] = fmaf(a, up.p[i], up.x[i]);
+        return;
+    }
+    stage_model<KT, CT>(m, sm);
+    const int C = CT ? CT : m.C;
+    const int i = blockIdx.x * kRayThreads + threadIdx.x;
+    if (i >= ni) return;
+    float lk[kMaxMat], ybar[kMaxChan];
+    ray_line_integrals<KT>(m, ni, i, l, up, up.alpha ? (float)*up.alpha : 0.0f, lk);
+    channel_means<KT, CT>(m, sm, lk, ybar);
+    for (int c = 0; c < C; ++c) ybar0[(size_t)c * ni + i] = ybar[c];
+}
+
+// Blurred model, pass 2: ybar = B ybar0, the weighted residuals
+// rres_c = w_c (ybar_c - y_c) and the rays' shares of the data term of Phi
+// (partials per block, when not NULL).
+__global__ __launch_bounds__(kRayThreads) void k_blur_resid(BlurArgs b, int ni, int C,
+                                                            const float* __restrict__ ybar0,
+                                                            const float* __restrict__ y,
+                                                            const float* __restrict__ w,
+                                                            float* __restrict__ rres,
+                                                            double* __restrict__ partials) {
+    __shared__ double sh[kRayThreads / 64];
+    const int i = blockIdx.x * kRayThreads + threadIdx.x;
+    double phi = 0.0;
+    if (i < ni) {
+        for (int c = 0; c < C; ++c) {
+            const float yb = blur_at(b, ybar0 + (size_t)c * ni, i, c, false);
+            const float wc = w[(size_t)c * ni + i];
+            const float dv = yb - y[(size_t)c * ni + i];
+            rres[(size_t)c * ni + i] = wc * dv;
+            phi += 0.5 * (double)wc * (double)dv * (double)dv;
+        }
+    }
+    const double tot = block_sum(phi, sh);
+    if (threadIdx.x == 0 && partials) partials[blockIdx.x] = tot;
+}
+
+// Blurred model, pass 3: r_c = (B^T rres_c)_i (stored to r_out when not NULL)
+// and the energy pass with it and sig_c = wb_c rowS_c (eta = S^T B^T W B S 1).
+template <int KT, int CT>
+__global__ __launch_bounds__(kRayThreads) void k_ray_grad_r(RayModel m, int ni, const float* __restrict__ l,
+                                                            const float* __restrict__ rres,
+                                                            const float* __restrict__ wb,
+                                                            const float* __restrict__ gammaA, BlurArgs b,
+                                                            float* __restrict__ u, float* __restrict__ v,
+                                                            float* __restrict__ r_out) {
+    __shared__ SharedModel sm;
+    stage_model<KT, CT>(m, sm);
+    const int K = KT ? KT : m.K, C = CT ? CT : m.C;
+    const int i = blockIdx.x * kRayThreads + threadIdx.x;
+    if (i >= ni) return;
+    float lk[kMaxMat], rc[kMaxChan], sig[kMaxChan], uk[kMaxMat], vk[kMaxMat];
+    for (int k = 0; k < K; ++k) lk[k] = l[(size_t)k * ni + i];
+    for (int c = 0; c < C; ++c) {
+        rc[c] = blur_at(b, rres + (size_t)c * ni, i, c, true);
+        sig[c] = wb[(size_t)c * ni + i] * m.rowS[c];
+        if (r_out) r_out[(size_t)c * ni + i] = rc[c];
+    }
+    ray_pass2<KT, CT>(m, sm, lk, rc, sig, gammaA ? gammaA[i] : 1.0f, v != nullptr, uk, vk);
+    for (int k = 0; k < K; ++k) {
+        u[(size_t)k * ni + i] = uk[k];
+        if (v) v[(size_t)k * ni + i] = vk[k];
+    }
+}
+
+// out_c = wt_c (B z_c) (or B^T z_c), one channel per grid row.
+__global__ __launch_bounds__(kRayThreads) void k_blur(BlurArgs b, int ni, const float* __restrict__ in,
+                                                      const float* __restrict__ wt, float* __restrict__ out,
+                                                      int transpose) {
+    const int i = blockIdx.x * kRayThreads + threadIdx.x, c = blockIdx.y;
+    if (i >= ni) return;
+    float s = blur_at(b, in + (size_t)c * ni, i, c, transpose != 0);
+    if (wt) s *= wt[(size_t)c * ni + i];
+    out[(size_t)c * ni + i] = s;
+}
+
+// Per ray with J [C][K][ni]: out_c = sum_k J_ck in_k, or transposed
+// out_k = sum_c J_ck in_c.
+__global__ __launch_bounds__(kRayThreads) void k_jmix(int ni, int K, int C, const float* __restrict__ J,
+                                                      const float* __restrict__ in, float* __restrict__ out,
+                                                      int transpose) {
+    const int i = blockIdx.x * kRayThreads + threadIdx.x;
+    if (i >= ni) return;
+    if (!transpose) {
+        for (int c = 0; c < C; ++c) {
+            float s = 0.0f;
+            for (int k = 0; k < K; ++k) s = fmaf(J[((size_t)c * K + k) * ni + i], in[(size_t)k * ni + i], s);
+            out[(size_t)c * ni + i] = s;
+        }
+    } else {
+        for (int k = 0; k < K; ++k) {
+            float s = 0.0f;
+            for (int c = 0; c < C; ++c) s = fmaf(J[((size_t)c * K + k) * ni + i], in[(size_t)c * ni + i], s);
+            out[(size_t)k * ni + i] = s;
+        }
+    }
 }
 
 template <int KT, int CT>
@@ -332,7 +476,8 @@ __global__ __launch_bounds__(kRayThreads) void k_forward_vjp(RayModel m, int ni,
     for (int k = 0; k < K; ++k) sk[(size_t)k * ni + i] = acc[k];
 }
 
-// Fisher weights W_i = J^T diag(w) J, J[c,k] = -sum_E S_cE D_E Q_Ek, with D
+// Fisher weights W_i = J^T diag(w) J (and J itself to Jout when not NULL),
+// J[c,k] = -sum_E S_cE D_E Q_Ek, with D
 // the transmission exp(-sum_k Q_Ek lref_k) at reference line integrals lref
 // [K][ni] when given, else the data-based D: y / I0 for one energy and
 // channel, else exp(-mu_w(E) l_w) from a 10-step Gauss-Newton water-only
@@ -340,7 +485,7 @@ __global__ __launch_bounds__(kRayThreads) void k_forward_vjp(RayModel m, int ni,
 __global__ __launch_bounds__(kRayThreads) void k_fisher(RayModel m, int ni, const float* __restrict__ y,
                                                         const float* __restrict__ w,
                                                         const float* __restrict__ lref,
-                                                        float* __restrict__ W) {
+                                                        float* __restrict__ W, float* __restrict__ Jout) {
     const int i = blockIdx.x * kRayThreads + threadIdx.x;
     if (i >= ni) return;
     const int npk = m.K * (m.K + 1) / 2;
@@ -405,6 +550,9 @@ __global__ __launch_bounds__(kRayThreads) void k_fisher(RayModel m, int ni, cons
             for (int c = 0; c < m.C; ++c) s += wc[c] * J[c][k] * J[c][l2];
             W[(size_t)packed_index(k, l2, m.K) * ni + i] = (float)s;
         }
+    if (Jout)
+        for (int c = 0; c < m.C; ++c)
+            for (int k = 0; k < m.K; ++k) Jout[((size_t)c * m.K + k) * ni + i] = (float)J[c][k];
     (void)npk;
 }
 
@@ -554,6 +702,36 @@ int launch_ray_grad(const RayArgs& a, const float* l, float* u, float* v, float*
     const StepUpdate upd = up ? *up : StepUpdate{nullptr, nullptr, nullptr, nullptr, nullptr, 0};
     MBMD_REQUIRE(!up || up->l == l, MBMD_ERR_ARG, "the step update must update the l it reads");
     const int nb_img = up ? blocks_for(up->n_img) : 0;
+    if (a.blur.h > 0) {                                    // three passes (the residual couples bins)
+        MBMD_REQUIRE(a.tmp0 && a.tmp1 && a.wb && a.blur.B > 0 && a.ni % a.blur.B == 0, MBMD_ERR_ARG,
+                     "blurred ray pass without its buffers");
+        {
+            KernelTimer kt_("k_ray_means", s);
+#define L_(KT, CT) hipLaunchKernelGGL((k_ray_means<KT, CT>), dim3(nb + nb_img), dim3(kRayThreads), 0, s, \
+                                   model_of(a), a.ni, l, a.tmp0, upd, nb)
+            MBMD_RAY_DISPATCH(a.K, a.C, L_);
+#undef L_
+            kt_.stop();
+        }
+        MBMD_LAUNCHED();
+        {
+            KernelTimer kt_("k_blur_resid", s);
+            hipLaunchKernelGGL(k_blur_resid, dim3(nb), dim3(kRayThreads), 0, s, a.blur, a.ni, a.C, a.tmp0, a.y,
+                               a.w, a.tmp1, phi_partials);
+            kt_.stop();
+        }
+        MBMD_LAUNCHED();
+        {
+            KernelTimer kt_("k_ray_grad_r", s);
+#define L_(KT, CT) hipLaunchKernelGGL((k_ray_grad_r<KT, CT>), dim3(nb), dim3(kRayThreads), 0, s, model_of(a), \
+                                   a.ni, l, a.tmp1, a.wb, a.gammaA, a.blur, u, v, r)
+            MBMD_RAY_DISPATCH(a.K, a.C, L_);
+#undef L_
+            kt_.stop();
+        }
+        MBMD_LAUNCHED();
+        return nb;
+    }
     {
         KernelTimer kt_("k_ray_grad", s);
 #define L_(KT, CT) hipLaunchKernelGGL((k_ray_grad<KT, CT>), dim3(nb + nb_img), dim3(kRayThreads), 0, s, model_of(a), \
@@ -569,6 +747,7 @@ int launch_ray_grad(const RayArgs& a, const float* l, float* u, float* v, float*
 int launch_ray_grad_rows(const RayArgs& a, const float* l, float* r, double* phi_partials, hipStream_t s,
                          const StepUpdate& up, const BackRows& br) {
     MBMD_REQUIRE(br.ok && br.V * br.B == a.ni, MBMD_ERR_ARG, "detector rows do not match the rays");
+    MBMD_REQUIRE(a.blur.h == 0, MBMD_ERR_ARG, "the fused gradient rows take no blur");
     MBMD_REQUIRE(br.V <= kMaxPartials, MBMD_ERR_SHAPE, "too many views for the partial-sum buffer");
     MBMD_REQUIRE(up.l == l, MBMD_ERR_ARG, "the step update must update the l it reads");
     const size_t lds = sizeof(float) * (size_t)a.K * br.B;
@@ -593,7 +772,7 @@ int launch_ray_curv(const RayArgs& a, const float* l, const float* r, const floa
     {
         KernelTimer kt_("k_ray_curv", s);
 #define L_(KT, CT) hipLaunchKernelGGL((k_ray_curv<KT, CT>), dim3(nb), dim3(kRayThreads), 0, s, model_of(a), a.ni, \
-                                   l, r, a.w, q, partials)
+                                   l, r, a.wb, q, partials)
         MBMD_RAY_DISPATCH(a.K, a.C, L_);
 #undef L_
         kt_.stop();
@@ -612,7 +791,7 @@ void launch_curvature(const RayArgs& a, const float* l, const float* r, const fl
     {
         KernelTimer kt_("k_curvature", s);
 #define L_(KT, CT) hipLaunchKernelGGL((k_curvature<KT, CT>), dim3(nb_ray + nb_pen), dim3(kRayThreads), 0, s,         \
-                                   model_of(a), a.ni, l, r, a.w, q, nb_ray, pa, x, p, partials)
+                                   model_of(a), a.ni, l, r, a.wb, q, nb_ray, pa, x, p, partials)
         MBMD_RAY_DISPATCH(a.K, a.C, L_);
 #undef L_
         kt_.stop();
@@ -623,18 +802,26 @@ void launch_curvature(const RayArgs& a, const float* l, const float* r, const fl
 }
 
 void launch_forward_model(const RayArgs& a, const float* l, float* ybar, hipStream_t s) {
+    float* out = a.blur.h > 0 ? a.tmp0 : ybar;             // the unblurred means, then B
+    MBMD_REQUIRE(out != nullptr, MBMD_ERR_ARG, "blurred forward model without its buffers");
     {
         KernelTimer kt_("k_forward_model", s);
 #define L_(KT, CT) hipLaunchKernelGGL((k_forward_model<KT, CT>), dim3(blocks_for(a.ni)), dim3(kRayThreads), 0, s, \
-                                   model_of(a), a.ni, l, ybar)
+                                   model_of(a), a.ni, l, out)
         MBMD_RAY_DISPATCH(a.K, a.C, L_);
 #undef L_
         kt_.stop();
     }
     MBMD_LAUNCHED();
+    if (a.blur.h > 0) launch_blur(a.blur, a.ni, a.C, out, nullptr, ybar, false, s);
 }
 
 void launch_forward_vjp(const RayArgs& a, const float* l, const float* gbar, float* sk, hipStream_t s) {
+    if (a.blur.h > 0) {                                    // B^T gbar first
+        MBMD_REQUIRE(a.tmp0 != nullptr, MBMD_ERR_ARG, "blurred VJP without its buffers");
+        launch_blur(a.blur, a.ni, a.C, gbar, nullptr, a.tmp0, true, s);
+        gbar = a.tmp0;
+    }
     {
         KernelTimer kt_("k_forward_vjp", s);
 #define L_(KT, CT) hipLaunchKernelGGL((k_forward_vjp<KT, CT>), dim3(blocks_for(a.ni)), dim3(kRayThreads), 0, s, \
@@ -646,11 +833,35 @@ void launch_forward_vjp(const RayArgs& a, const float* l, const float* gbar, flo
     MBMD_LAUNCHED();
 }
 
-void launch_fisher(const RayArgs& a, float* W, hipStream_t s, const float* lref) {
+void launch_fisher(const RayArgs& a, float* W, hipStream_t s, const float* lref, float* J) {
     {
         KernelTimer kt_("k_fisher", s);
         hipLaunchKernelGGL(k_fisher, dim3(blocks_for(a.ni)), dim3(kRayThreads), 0, s, model_of(a), a.ni, a.y,
-                       a.w, lref, W);
+                       a.w, lref, W, J);
+        kt_.stop();
+    }
+    MBMD_LAUNCHED();
+}
+
+void launch_blur(const BlurArgs& b, int ni, int C, const float* in, const float* wt, float* out, bool transpose,
+                 hipStream_t s) {
+    MBMD_REQUIRE(b.h > 0 && b.h <= kMaxBlurHalf && b.B > 0 && ni % b.B == 0 && C <= kMaxChan && in != out,
+                 MBMD_ERR_ARG, "bad blur launch");
+    {
+        KernelTimer kt_("k_blur", s);
+        hipLaunchKernelGGL(k_blur, dim3(blocks_for(ni), C), dim3(kRayThreads), 0, s, b, ni, in, wt, out,
+                           transpose ? 1 : 0);
+        kt_.stop();
+    }
+    MBMD_LAUNCHED();
+}
+
+void launch_jmix(int ni, int K, int C, const float* J, const float* in, float* out, bool transpose, hipStream_t s) {
+    MBMD_REQUIRE(in != out, MBMD_ERR_ARG, "k_jmix works out of place");
+    {
+        KernelTimer kt_("k_jmix", s);
+        hipLaunchKernelGGL(k_jmix, dim3(blocks_for(ni)), dim3(kRayThreads), 0, s, ni, K, C, J, in, out,
+                           transpose ? 1 : 0);
         kt_.stop();
     }
     MBMD_LAUNCHED();
