@@ -31,6 +31,8 @@ Methods, "Preconditioned Optimization" and the per-application sections:
     part is kept (the even part of the response), each block is symmetrised,
     eigenvalues are floored at eps_F max_f lambda_max(L_f) (eps_F = 1e-2; the
     paper gives no floor, and its approximate eigenvalues can be <= 0).
+  * Haar, and Daubechies-4 as the other unitary wavelet the section names
+    (same build and apply with its transform; floor eps_H).
   * Haar (wavelet and cross-material wavelet sections): test function
     Delta x = U^T 1 in material k, so U Delta x = 1 and column k of the
     per-coefficient blocks K_w is U M0^T H M0 (Delta x (x) e_k); symmetrised
@@ -47,9 +49,10 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import haar, model, projector
+from . import daub, haar, model, projector
 from . import penalty as pen
 
+WAVELETS = {"haar": haar, "daub4": daub}
 M0_FLOOR = 1e-6
 EPS_FOURIER = 1e-2
 EPS_HAAR = 1e-2
@@ -186,20 +189,25 @@ def fourier_blocks(prob, W, M0, hop=None):
     return L
 
 
-def haar_blocks(prob, W, M0, hop=None):
-    """Per-coefficient blocks K_w [ny, nx, K, K] (before any floor)."""
+def wavelet_blocks(prob, W, M0, hop=None, wavelet=haar):
+    """Per-coefficient blocks K_w [ny, nx, K, K] (before any floor) of the
+    wavelet transform ``wavelet`` (the haar or daub module)."""
     H = _hop(prob, W, hop)
     K = prob.n_mat
     ny, nx = prob.geom["ny"], prob.geom["nx"]
-    dx = haar.inverse(np.ones((ny, nx)))
+    dx = wavelet.inverse(np.ones((ny, nx)))
     Kb = np.zeros((ny, nx, K, K))
     for k in range(K):
         e = np.zeros((K, ny, nx))
         e[k] = dx
         r = apply_blocks(M0, H(apply_blocks(M0, e)))
         for kp in range(K):
-            Kb[:, :, kp, k] = haar.forward(r[kp])
+            Kb[:, :, kp, k] = wavelet.forward(r[kp])
     return Kb
+
+
+def haar_blocks(prob, W, M0, hop=None):
+    return wavelet_blocks(prob, W, M0, hop, haar)
 
 
 def _global_floor(blocks, eps):
@@ -209,7 +217,8 @@ def _global_floor(blocks, eps):
 
 
 def build(prob, kind, eps=None, modified=True, W=None, hop=None, x_ref=None):
-    """Build the tables of preconditioner ``kind`` in {'blockdiag','fourier','haar'}.
+    """Build the tables of preconditioner ``kind`` in {'blockdiag','fourier','haar','daub4'}
+    ('daub4': the wavelet preconditioner with the Daubechies-4 transform).
 
     ``modified=False`` gives the unmodified preconditioners (M0 = I), e.g. the
     Fourier preconditioner of eq:fourierEigenbasis.  ``x_ref`` takes the Fisher
@@ -231,8 +240,8 @@ def build(prob, kind, eps=None, modified=True, W=None, hop=None, x_ref=None):
         L = fourier_blocks(prob, W, M0, hop).real
         t["P"], t["n_floored"] = _global_floor(L, EPS_FOURIER if eps is None else eps)
         return t
-    if kind == "haar":
-        Kb = haar_blocks(prob, W, M0, hop)
+    if kind in ("haar", "daub4"):
+        Kb = wavelet_blocks(prob, W, M0, hop, WAVELETS[kind])
         t["P"], t["n_floored"] = _global_floor(Kb, EPS_HAAR if eps is None else eps)
         return t
     raise ValueError("unknown preconditioner %r" % kind)
@@ -245,9 +254,10 @@ def _apply_P(t, v):
         Vf = np.stack([np.fft.fft2(vk) for vk in v])
         Wf = np.einsum("yxkl,lyx->kyx", t["P"], Vf)
         return np.stack([np.fft.ifft2(wk).real for wk in Wf])
-    c = np.stack([haar.forward(vk) for vk in v])
+    wv = WAVELETS[t["kind"]]
+    c = np.stack([wv.forward(vk) for vk in v])
     c = apply_blocks(t["P"], c)
-    return np.stack([haar.inverse(ck) for ck in c])
+    return np.stack([wv.inverse(ck) for ck in c])
 
 
 def apply_M(t, v):

@@ -81,7 +81,7 @@ def test_newton_reference_and_gradient():
     np.testing.assert_allclose(model.gradient(prob, xhat), 0.0, atol=1e-7)
 
 
-@pytest.mark.parametrize("kind", [None, "blockdiag", "fourier", "haar"])
+@pytest.mark.parametrize("kind", [None, "blockdiag", "fourier", "haar", "daub4"])
 def test_every_variant_converges_to_the_newton_minimiser(kind):
     """Any invertible M leaves the minimiser unchanged; all iterations are
     monotone and approach the Newton x_hat (beta = 3000: condition ~50, so
@@ -104,7 +104,7 @@ def test_preconditioning_speeds_up_convergence():
     rel = lambda x: np.linalg.norm(x - xhat) / np.linalg.norm(xhat)
     xp, _ = sps.sps_plain(prob, 1500, trace=False)
     assert rel(xp) > 1e-2
-    for kind in ("blockdiag", "fourier", "haar"):
+    for kind in ("blockdiag", "fourier", "haar", "daub4"):
         x, _, _ = sps.sps_precond(prob, precond.build(prob, kind), 1500, trace=False)
         assert rel(x) < 1e-5, kind
 
