@@ -66,7 +66,9 @@ typedef enum {
     MBMD_PRECOND_NONE = 0,      /* plain SPS */
     MBMD_PRECOND_FOURIER = 1,   /* (cross-material) modified Fourier: M = M0 U^H L^-1/2 U */
     MBMD_PRECOND_HAAR = 2,      /* (cross-material) Haar wavelet:     M = M0 U^T K^-1/2 U */
-    MBMD_PRECOND_BLOCKDIAG = 3  /* per-pixel N_k x N_k block diagonal: M = M0 */
+    MBMD_PRECOND_BLOCKDIAG = 3, /* per-pixel N_k x N_k block diagonal: M = M0 */
+    MBMD_PRECOND_DAUB4 = 4      /* (cross-material) wavelet with the Daubechies-4 transform:
+                                   M = M0 U^T K^-1/2 U, U the periodised orthonormal DWT */
 } mbmd_precond;
 
 /* Flags of mbmd_precond_build_ex. */
@@ -191,11 +193,13 @@ void mbmd_problem_destroy(mbmd_problem* prob);
  *     with the phase removed, real part, symmetrised per-frequency blocks,
  *     eigenvalues floored at 1e-2 of the largest over all frequencies;
  *   - HAAR: response to U^T 1 per material, Haar-transformed; same floor;
+ *   - DAUB4: the same with the periodised orthonormal Daubechies-4 transform
+ *     (the other unitary wavelet the wavelet section names);
  *   - BLOCKDIAG: M0 only.
  * The composition is M = M0 U^H L^-1/2 U (the paper's symmetric sandwich
  * M0^T U^T L^-1/2 U M0 does not whiten M0^T H M0).  Huber problems build
- * with the quadratic Hessian beta Gamma.  FOURIER and HAAR need nx and ny
- * powers of two (HAAR: nx == ny) and a projector geometry.
+ * with the quadratic Hessian beta Gamma.  FOURIER, HAAR and DAUB4 need nx
+ * and ny powers of two (HAAR, DAUB4: nx == ny) and a projector geometry.
  * Errors: MBMD_ERR_ARG, MBMD_ERR_SHAPE, MBMD_ERR_UNSUPPORTED, MBMD_ERR_HIP.
  */
 int mbmd_precond_build(mbmd_problem* prob, int kind, void* stream);

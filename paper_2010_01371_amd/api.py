@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import check
 
 KINDS = {"parallel": 0, "fan": 1, "identity": 2}
-PRECONDS = {"none": 0, "fourier": 1, "haar": 2, "blockdiag": 3}
+PRECONDS = {"none": 0, "fourier": 1, "haar": 2, "blockdiag": 3, "daub4": 4}
 PRECOND_UNMODIFIED = 1          # mbmd_precond_flags
 PENALTIES = {"quadratic": 0, "huber": 1}
 

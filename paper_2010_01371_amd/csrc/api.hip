@@ -160,6 +160,7 @@ void carve(Problem& P) {
             P.coef = A.take<float>(K * nj);
             P.coarse = A.take<float>(K * (size_t)nt * nt);
             P.Kinv = A.take<float>(npk * nj);
+            P.Dinv = A.take<float>(npk * nj);
         }
     }
     P.partials = A.take<double>((size_t)kRegions * kMaxPartials);
@@ -231,7 +232,7 @@ void build_fisher_m0(Problem& P, int state, const float* lref, bool modified, hi
         }
         launch_block_invsqrt(P.nj, P.K, P.t_img, P.M0, -0.5, kM0Floor, nullptr, 0.0, P.flags + 1, s);
     }
-    for (int k = 0; k < 4; ++k) P.built[k] = 0;
+    for (int k = 0; k < kPreconds; ++k) P.built[k] = 0;
     P.m0_state = state;
 }
 
@@ -280,6 +281,24 @@ void build_haar(Problem& P, hipStream_t s) {
     finish_filter(P, blocks, P.Kinv, kEpsHaar, s);
 }
 
+// The same build with the Daubechies-4 transform (the other unitary wavelet).
+void build_daub4(Problem& P, hipStream_t s) {
+    MBMD_REQUIRE(P.coef != nullptr, MBMD_ERR_SHAPE, "the Daubechies preconditioner needs a square power-of-two image");
+    const int n = P.nx;
+    launch_fill(P.nj, P.coef, 1.0f, s);                     // Delta x = U^T 1 (one material), in d_img
+    launch_d4_inverse(1, n, P.coef, nullptr, P.d_img, 1.0f, s);
+    float* blocks = P.t_img;
+    launch_fill(P.npk * P.nj, blocks, 0.0f, s);
+    for (int k = 0; k < P.K; ++k) {
+        launch_fill(P.K * P.nj, P.t2_img, 0.0f, s);
+        launch_scale_copy(P.nj, P.d_img, P.t2_img + (size_t)k * P.nj, 1.0f, s);
+        hessian_apply(P, P.t2_img, P.g_img, P.M0, s);
+        launch_d4_forward(P.K, n, P.g_img, nullptr, P.coef, s);
+        launch_coef_blocks(P.K, n, k, P.coef, blocks, s);
+    }
+    finish_filter(P, blocks, P.Dinv, kEpsHaar, s);
+}
+
 // out = sign * M M^T g, with partials of g.out into `partials` when non-NULL.
 int apply_direction(Problem& P, int kind, const float* g, float* out, float sign, double* partials,
                     hipStream_t s) {
@@ -293,6 +312,8 @@ int apply_direction(Problem& P, int kind, const float* g, float* out, float sign
                                         partials, s);
         case MBMD_PRECOND_HAAR:
             return launch_haar_apply(P.K, P.nx, g, P.M0, P.Kinv, P.coef, P.coarse, out, sign, g, partials, s);
+        case MBMD_PRECOND_DAUB4:
+            return launch_d4_apply(P.K, P.nx, g, P.M0, P.Dinv, P.coef, out, sign, g, partials, s);
         default:
             launch_scale_copy(P.K * P.nj, g, out, sign, s);
             return partials ? launch_dot(P.K * P.nj, g, out, partials, s) : 0;
@@ -384,7 +405,7 @@ void flush_step(Problem& P, float* x, hipStream_t s) {
 }
 
 void check_precond_ready(Problem& P, int precond) {
-    MBMD_REQUIRE(precond >= 0 && precond <= 3, MBMD_ERR_ARG, "unknown preconditioner");
+    MBMD_REQUIRE(precond >= 0 && precond < kPreconds, MBMD_ERR_ARG, "unknown preconditioner");
     if (P.identity) {
         MBMD_REQUIRE(!P.has_penalty, MBMD_ERR_UNSUPPORTED,
                      "identity geometry iterations need a zero penalty (the problem separates by ray)");
@@ -685,14 +706,14 @@ int mbmd_problem_set_blur(mbmd_problem* prob, const float* taps_host, int half_w
         P.blur = b;
         P.dL_valid = 0;
         P.m0_state = 0;
-        for (int k = 0; k < 4; ++k) P.built[k] = 0;
+        for (int k = 0; k < kPreconds; ++k) P.built[k] = 0;
     });
 }
 
 int mbmd_precond_build_ex(mbmd_problem* prob, int kind, int flags, const float* x_ref_dev, void* stream) {
     return guarded([&] {
         MBMD_REQUIRE(prob, MBMD_ERR_ARG, "NULL problem");
-        MBMD_REQUIRE(kind >= 0 && kind <= 3, MBMD_ERR_ARG, "unknown preconditioner");
+        MBMD_REQUIRE(kind >= 0 && kind < kPreconds, MBMD_ERR_ARG, "unknown preconditioner");
         MBMD_REQUIRE((flags & ~MBMD_PRECOND_UNMODIFIED) == 0, MBMD_ERR_ARG, "unknown preconditioner build flag");
         hipStream_t s = static_cast<hipStream_t>(stream);
         prob->last_stream = s;
@@ -702,8 +723,8 @@ int mbmd_precond_build_ex(mbmd_problem* prob, int kind, int flags, const float* 
                          "identity geometry supports the block-diagonal preconditioner only");
         if (kind == MBMD_PRECOND_FOURIER)
             MBMD_REQUIRE(prob->spec != nullptr, MBMD_ERR_SHAPE, "the Fourier preconditioner needs power-of-two sizes");
-        if (kind == MBMD_PRECOND_HAAR)
-            MBMD_REQUIRE(prob->coef != nullptr, MBMD_ERR_SHAPE, "the Haar preconditioner needs a square power-of-two image");
+        if (kind == MBMD_PRECOND_HAAR || kind == MBMD_PRECOND_DAUB4)
+            MBMD_REQUIRE(prob->coef != nullptr, MBMD_ERR_SHAPE, "the wavelet preconditioners need a square power-of-two image");
         if (flags == 0 && !x_ref_dev) {
             ensure_fisher_m0(*prob, s);
         } else {
@@ -718,6 +739,7 @@ int mbmd_precond_build_ex(mbmd_problem* prob, int kind, int flags, const float* 
         }
         if (kind == MBMD_PRECOND_FOURIER) build_fourier(*prob, s);
         if (kind == MBMD_PRECOND_HAAR) build_haar(*prob, s);
+        if (kind == MBMD_PRECOND_DAUB4) build_daub4(*prob, s);
         prob->built[kind] = 1;
     });
 }
@@ -729,7 +751,7 @@ int mbmd_precond_build(mbmd_problem* prob, int kind, void* stream) {
 int mbmd_precond_apply(mbmd_problem* prob, int kind, const float* g_dev, float* out_dev, void* stream) {
     return guarded([&] {
         MBMD_REQUIRE(prob && g_dev && out_dev && g_dev != out_dev, MBMD_ERR_ARG, "bad argument");
-        MBMD_REQUIRE(kind >= 0 && kind <= 3, MBMD_ERR_ARG, "unknown preconditioner");
+        MBMD_REQUIRE(kind >= 0 && kind < kPreconds, MBMD_ERR_ARG, "unknown preconditioner");
         if (kind != MBMD_PRECOND_NONE) MBMD_REQUIRE(prob->built[kind], MBMD_ERR_NOT_BUILT, "preconditioner not built");
         hipStream_t s = static_cast<hipStream_t>(stream);
         prob->last_stream = s;

@@ -17,6 +17,7 @@ constexpr int kMaxMat = 4;
 constexpr int kMaxChan = 8;
 constexpr int kMaxEnergy = 256;
 constexpr int kMaxPacked = kMaxMat * (kMaxMat + 1) / 2;   // symmetric N_k x N_k, packed
+constexpr int kPreconds = 5;                               // mbmd_precond values 0..4
 constexpr int kMaxBlurHalf = 4;                            // projection-domain blur: at most 9 taps
 constexpr int kBlurTaps = 2 * kMaxBlurHalf + 1;
 
@@ -290,6 +291,7 @@ struct Problem {
     float* M0 = nullptr;             // [npk][nj]
     float* Linv = nullptr;           // [ny][nx][npk]  (L^-1 blocks)
     float* Kinv = nullptr;           // [ny][nx][npk]  (K^-1 blocks)
+    float* Dinv = nullptr;           // [npk][nj] Daubechies-4 coefficient blocks (inverse)
     float* W = nullptr;              // [npk][ni] Fisher weights (build)
     // projection-domain blur (mbmd_problem_set_blur); buffers in blur_arena
     BlurArgs blur;
@@ -303,11 +305,11 @@ struct Problem {
     float2* tw_y = nullptr;          // twiddles for ny
     float* coef = nullptr;           // [K][ny][nx] Haar coefficients
     float* coarse = nullptr;         // [K][ny/T][nx/T]
-    int built[4] = {0, 0, 0, 0};
+    int built[kPreconds] = {};
     // Fisher weights W and M0 in use: 0 none, 1 from the data (modified),
     // 2 from a reference image and / or M0 = I (mbmd_precond_build_ex)
     int m0_state = 0;
-    int n_floored[4] = {0, 0, 0, 0};
+    int n_floored[kPreconds] = {};
     // reductions
     double* partials = nullptr;      // [kRegions][kMaxPartials]
     double* scal = nullptr;          // device scalars (alpha, phi, flags...)
@@ -433,5 +435,14 @@ int launch_haar_apply(int K, int n, const float* in, const float* M, const float
                       float* coarse, float* out, float out_sign, const float* g, double* partials,
                       hipStream_t s);
 void launch_coef_blocks(int K, int n, int k_col, const float* coef, float* blocks, hipStream_t s);
+// Orthonormal Daubechies-4 transform of [K][n][n] images (square power of two):
+// coef = U (M in) (M NULL: identity), in place in coef; the inverse
+// out = out_sign M (U^T coef) overwrites coef.  The apply is
+// out = out_sign M U^T Dinv U M in, with the partials of g . out (returns their
+// count) when partials is not NULL.
+void launch_d4_forward(int K, int n, const float* in, const float* M, float* coef, hipStream_t s);
+void launch_d4_inverse(int K, int n, float* coef, const float* M, float* out, float out_sign, hipStream_t s);
+int launch_d4_apply(int K, int n, const float* in, const float* M, const float* Dinv, float* coef, float* out,
+                    float out_sign, const float* g, double* partials, hipStream_t s);
 
 }  // namespace mbmd

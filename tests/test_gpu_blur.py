@@ -112,7 +112,7 @@ def test_blurred_sps_iterates(case, kind):
     np.testing.assert_allclose(tg[:5], to[:5], rtol=1e-4)
 
 
-@pytest.mark.parametrize("kind", ["blockdiag", "fourier", "haar"])
+@pytest.mark.parametrize("kind", ["blockdiag", "fourier", "haar", "daub4"])
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_blurred_precond_apply(case, kind):
     wl, op, P = _problems(case)

@@ -57,7 +57,7 @@ def test_c1_plain_50():
     _check(C.make_c1(), "none", 50, "c1")
 
 
-@pytest.mark.parametrize("kind", ["none", "blockdiag", "fourier", "haar"])
+@pytest.mark.parametrize("kind", ["none", "blockdiag", "fourier", "haar", "daub4"])
 def test_fan64_huber(kind):
     _check(C.make_small_fan(n=64, views=90, bins=128, penalty="huber"), kind, 50, "fan64_huber")
 
@@ -67,7 +67,7 @@ def test_fan64_quadratic(kind):
     _check(C.make_small_fan(n=64, views=90, bins=128, penalty="quadratic"), kind, 50, "fan64_quad")
 
 
-@pytest.mark.parametrize("kind", ["none", "blockdiag", "fourier", "haar"])
+@pytest.mark.parametrize("kind", ["none", "blockdiag", "fourier", "haar", "daub4"])
 def test_mbmd32_3mat(kind):
     # The cross-material Haar iteration is chaotic on this problem: its step
     # size jumps by 10-80x between iterations, and in the FP64 oracle a 1e-7
@@ -80,8 +80,9 @@ def test_mbmd32_3mat(kind):
     # 10), while the iterate stays within RMSE 6e-5 of the unperturbed run; so
     # its iterate is compared after 30 iterations and its objective over the
     # first 10.
-    n = 10 if kind == "haar" else 30
-    trace_n = 10 if kind in ("haar", "fourier") else n
+    # The Daubechies wavelet is compared like Haar.
+    n = 10 if kind in ("haar", "daub4") else 30
+    trace_n = 10 if kind in ("haar", "fourier", "daub4") else n
     _check(C.make_small_mbmd(n=32, views=60, bins=64, n_mat=3), kind, n, "mbmd32_3mat", trace_n)
 
 
@@ -90,7 +91,7 @@ def test_identity_c3_small(kind):
     _check(C.make_c3(n_views=24, n_bins=40), kind, 50, "c3_small")
 
 
-@pytest.mark.parametrize("kind", ["blockdiag", "fourier", "haar"])
+@pytest.mark.parametrize("kind", ["blockdiag", "fourier", "haar", "daub4"])
 @pytest.mark.parametrize("case", ["fan64", "mbmd32"])
 def test_precond_apply_matches_oracle(kind, case):
     wl = (C.make_small_fan(n=64, views=90, bins=128) if case == "fan64"
@@ -117,6 +118,22 @@ def test_fourier_apply_image_sizes(n):
     P.precond_build("fourier")
     got = host(P.precond_apply("fourier", dev(g)))
     tab = opre.build(op, "fourier")
+    want = opre.apply_M(tab, opre.apply_Mt(tab, g))
+    assert l2rel(got, want) <= TOL_APPLY, l2rel(got, want)
+
+
+@pytest.mark.parametrize("n", [128, 256, 512])
+def test_daub4_apply_image_sizes(n):
+    """The Daubechies transform with levels above the in-LDS coarse part (rows
+    and column strips per level), as the wavelet preconditioner's apply."""
+    wl = C.make_small_fan(n=n, views=24, bins=96)
+    op = oracle.OracleProblem.from_workload(wl)
+    g = np.random.default_rng(n + 1).normal(size=wl.x_true.shape)
+    announce("precond_apply", "fan%d" % n, "daub4")
+    P = mb.Problem.from_workload(wl)
+    P.precond_build("daub4")
+    got = host(P.precond_apply("daub4", dev(g)))
+    tab = opre.build(op, "daub4")
     want = opre.apply_M(tab, opre.apply_Mt(tab, g))
     assert l2rel(got, want) <= TOL_APPLY, l2rel(got, want)
 
@@ -205,7 +222,8 @@ def _x_ref(wl):
 @pytest.mark.parametrize("case", ["fan64", "mbmd32"])
 @pytest.mark.parametrize("kind,modified,ref", [("fourier", False, False), ("haar", False, False),
                                                ("fourier", True, True), ("haar", True, True),
-                                               ("blockdiag", True, True), ("fourier", False, True)])
+                                               ("blockdiag", True, True), ("fourier", False, True),
+                                               ("daub4", False, False), ("daub4", True, True)])
 def test_precond_build_options_match_oracle(kind, modified, ref, case):
     """mbmd_precond_build_ex: M0 = I (unmodified) and / or the Fisher weights at
     a reference image; M M^T g against the oracle built the same way."""
