@@ -286,14 +286,14 @@ void build_daub4(Problem& P, hipStream_t s) {
     MBMD_REQUIRE(P.coef != nullptr, MBMD_ERR_SHAPE, "the Daubechies preconditioner needs a square power-of-two image");
     const int n = P.nx;
     launch_fill(P.nj, P.coef, 1.0f, s);                     // Delta x = U^T 1 (one material), in d_img
-    launch_d4_inverse(1, n, P.coef, nullptr, P.d_img, 1.0f, s);
+    launch_d4_inverse(1, n, P.coef, nullptr, P.d_img, 1.0f, P.d_img, s);
     float* blocks = P.t_img;
     launch_fill(P.npk * P.nj, blocks, 0.0f, s);
     for (int k = 0; k < P.K; ++k) {
         launch_fill(P.K * P.nj, P.t2_img, 0.0f, s);
         launch_scale_copy(P.nj, P.d_img, P.t2_img + (size_t)k * P.nj, 1.0f, s);
         hessian_apply(P, P.t2_img, P.g_img, P.M0, s);
-        launch_d4_forward(P.K, n, P.g_img, nullptr, P.coef, s);
+        launch_d4_forward(P.K, n, P.g_img, nullptr, P.coef, P.t2_img, s);
         launch_coef_blocks(P.K, n, k, P.coef, blocks, s);
     }
     finish_filter(P, blocks, P.Dinv, kEpsHaar, s);

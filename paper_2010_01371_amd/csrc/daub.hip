@@ -10,10 +10,10 @@
 // half that land on j.  h = (1 + r3, 3 + r3, 3 - r3, 1 - r3) / (4 r2),
 // g_k = (-1)^k h_{3-k}.
 //
-// Levels with m > kCoarse run as two launches each (a workgroup per row, then
-// per strip of columns, staged in LDS); the levels from kCoarse down run in one
-// workgroup per channel, entirely in LDS.  The work is HBM/latency-bound:
-// 8 bytes per coefficient per level pass.
+// Levels with m > kCoarse run as two out-of-place launches each (rows into a
+// scratch image, columns back), one thread per output; the levels from
+// kCoarse down run in one workgroup per channel, entirely in LDS.  The work is
+// L2/latency-bound: 8 bytes per coefficient per level pass.
 #include <algorithm>
 #include <cmath>
 
@@ -63,31 +63,17 @@ __device__ __forceinline__ float d4_line(const D4Filter& f, const float* src, in
     return acc;
 }
 
-// One level along rows y < m of block [0:m, 0:m]: a workgroup per (row, channel).
-__global__ __launch_bounds__(kThreads) void k_d4_rows(D4Filter f, int n, int m, int inverse, float* __restrict__ a) {
-    extern __shared__ float line[];
-    float* row = a + ((size_t)blockIdx.y * n + blockIdx.x) * n;
-    for (int j = threadIdx.x; j < m; j += kThreads) line[j] = row[j];
-    __syncthreads();
-    for (int t = threadIdx.x; t < m; t += kThreads) row[t] = d4_line(f, line, 1, m, t, inverse != 0);
-}
-
-// One level along columns x < m of block [0:m, 0:m]: a workgroup per (strip of
-// cw columns, channel), the strip staged as [m][cw] in LDS.
-__global__ __launch_bounds__(kThreads) void k_d4_cols(D4Filter f, int n, int m, int cw, int inverse,
-                                                       float* __restrict__ a) {
-    extern __shared__ float strip[];
-    float* img = a + (size_t)blockIdx.y * n * n;
-    const int c0 = blockIdx.x * cw;
-    for (int t = threadIdx.x; t < m * cw; t += kThreads) {
-        const int r = t / cw, c = t - r * cw;
-        if (c0 + c < m) strip[t] = img[(size_t)r * n + c0 + c];
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < m * cw; t += kThreads) {
-        const int r = t / cw, c = t - r * cw;
-        if (c0 + c < m) img[(size_t)r * n + c0 + c] = d4_line(f, strip + c, cw, m, r, inverse != 0);
-    }
+// One pass of one level over block [0:m, 0:m] of every channel, out of place
+// (src and dst [K][n][n], only the block is written): along rows or along
+// columns, one thread per output, consecutive threads on consecutive columns.
+__global__ __launch_bounds__(kThreads) void k_d4_pass(D4Filter f, int n, int m, int along_rows, int inverse,
+                                                       const float* __restrict__ src, float* __restrict__ dst) {
+    const int t = blockIdx.x * kThreads + threadIdx.x;
+    if (t >= m * m) return;
+    const int r = t / m, c = t - r * m;
+    const size_t base = (size_t)blockIdx.y * n * n;
+    dst[base + (size_t)r * n + c] = along_rows ? d4_line(f, src + base + (size_t)r * n, 1, m, c, inverse != 0)
+                                               : d4_line(f, src + base + c, n, m, r, inverse != 0);
 }
 
 // The levels m <= T of channel blockIdx.x (T = min(n, kCoarse)), in LDS:
@@ -119,23 +105,14 @@ void check(int n) {
                  "the Daubechies preconditioner needs a square power-of-two image");
 }
 
-int strip_width(int m) { return std::max(1, std::min(64, 8192 / m)); }
-
-void level(const D4Filter& f, int K, int n, int m, bool inverse, float* a, hipStream_t s) {
-    const int cw = strip_width(m);
+// One level: forward rows x -> y, columns y -> x; inverse columns, then rows.
+void level(const D4Filter& f, int K, int n, int m, bool inverse, float* x, float* y, hipStream_t s) {
     for (int pass = 0; pass < 2; ++pass) {
         const bool rows = (pass == 0) != inverse;
-        if (rows) {
-            KernelTimer kt_("k_d4_rows", s);
-            hipLaunchKernelGGL(k_d4_rows, dim3(m, K), dim3(kThreads), sizeof(float) * m, s, f, n, m, inverse ? 1 : 0,
-                               a);
-            kt_.stop();
-        } else {
-            KernelTimer kt_("k_d4_cols", s);
-            hipLaunchKernelGGL(k_d4_cols, dim3((m + cw - 1) / cw, K), dim3(kThreads), sizeof(float) * m * cw, s, f, n,
-                               m, cw, inverse ? 1 : 0, a);
-            kt_.stop();
-        }
+        KernelTimer kt_("k_d4_pass", s);
+        hipLaunchKernelGGL(k_d4_pass, dim3((m * m + kThreads - 1) / kThreads, K), dim3(kThreads), 0, s, f, n, m,
+                           rows ? 1 : 0, inverse ? 1 : 0, pass == 0 ? x : y, pass == 0 ? y : x);
+        kt_.stop();
         MBMD_LAUNCHED();
     }
 }
@@ -151,31 +128,34 @@ void coarse(const D4Filter& f, int K, int n, bool inverse, float* a, hipStream_t
 
 }  // namespace
 
-void launch_d4_forward(int K, int n, const float* in, const float* M, float* coef, hipStream_t s) {
+void launch_d4_forward(int K, int n, const float* in, const float* M, float* coef, float* scratch, hipStream_t s) {
     check(n);
-    MBMD_REQUIRE(in != coef, MBMD_ERR_ARG, "the Daubechies transform reads in and writes coef");
+    MBMD_REQUIRE(in != coef && scratch != coef && scratch != in, MBMD_ERR_ARG,
+                 "the Daubechies transform needs distinct in, coef and scratch");
     const D4Filter f = d4_filter();
     if (M) launch_block_apply(n * n, K, M, in, coef, 1.0f, s);
     else launch_scale_copy(K * n * n, in, coef, 1.0f, s);
-    for (int m = n; m > kCoarse; m /= 2) level(f, K, n, m, false, coef, s);
+    for (int m = n; m > kCoarse; m /= 2) level(f, K, n, m, false, coef, scratch, s);
     coarse(f, K, n, false, coef, s);
 }
 
-void launch_d4_inverse(int K, int n, float* coef, const float* M, float* out, float out_sign, hipStream_t s) {
+void launch_d4_inverse(int K, int n, float* coef, const float* M, float* out, float out_sign, float* scratch,
+                       hipStream_t s) {
     check(n);
-    MBMD_REQUIRE(out != coef, MBMD_ERR_ARG, "the Daubechies inverse works in coef, then writes out");
+    MBMD_REQUIRE(out != coef && scratch != coef, MBMD_ERR_ARG,
+                 "the Daubechies inverse works in coef (with scratch), then writes out");
     const D4Filter f = d4_filter();
     coarse(f, K, n, true, coef, s);
-    for (int m = 2 * std::min(n, kCoarse); m <= n; m *= 2) level(f, K, n, m, true, coef, s);
+    for (int m = 2 * std::min(n, kCoarse); m <= n; m *= 2) level(f, K, n, m, true, coef, scratch, s);
     if (M) launch_block_apply(n * n, K, M, coef, out, out_sign, s);
     else launch_scale_copy(K * n * n, coef, out, out_sign, s);
 }
 
 int launch_d4_apply(int K, int n, const float* in, const float* M, const float* Dinv, float* coef, float* out,
                     float out_sign, const float* g, double* partials, hipStream_t s) {
-    launch_d4_forward(K, n, in, M, coef, s);
+    launch_d4_forward(K, n, in, M, coef, out, s);            // out is written last: scratch until then
     launch_block_apply(n * n, K, Dinv, coef, coef, 1.0f, s);
-    launch_d4_inverse(K, n, coef, M, out, out_sign, s);
+    launch_d4_inverse(K, n, coef, M, out, out_sign, out, s);
     return partials ? launch_dot(K * n * n, g, out, partials, s) : 0;
 }
 

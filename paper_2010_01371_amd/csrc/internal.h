@@ -436,12 +436,13 @@ int launch_haar_apply(int K, int n, const float* in, const float* M, const float
                       hipStream_t s);
 void launch_coef_blocks(int K, int n, int k_col, const float* coef, float* blocks, hipStream_t s);
 // Orthonormal Daubechies-4 transform of [K][n][n] images (square power of two):
-// coef = U (M in) (M NULL: identity), in place in coef; the inverse
-// out = out_sign M (U^T coef) overwrites coef.  The apply is
-// out = out_sign M U^T Dinv U M in, with the partials of g . out (returns their
-// count) when partials is not NULL.
-void launch_d4_forward(int K, int n, const float* in, const float* M, float* coef, hipStream_t s);
-void launch_d4_inverse(int K, int n, float* coef, const float* M, float* out, float out_sign, hipStream_t s);
+// coef = U (M in) (M NULL: identity); the inverse out = out_sign M (U^T coef)
+// overwrites coef.  scratch: [K][n][n] overwritten (the inverse may pass out).
+// The apply is out = out_sign M U^T Dinv U M in, with the partials of g . out
+// (returns their count) when partials is not NULL.
+void launch_d4_forward(int K, int n, const float* in, const float* M, float* coef, float* scratch, hipStream_t s);
+void launch_d4_inverse(int K, int n, float* coef, const float* M, float* out, float out_sign, float* scratch,
+                       hipStream_t s);
 int launch_d4_apply(int K, int n, const float* in, const float* M, const float* Dinv, float* coef, float* out,
                     float out_sign, const float* g, double* partials, hipStream_t s);
 
