@@ -19,13 +19,26 @@ def _slices():
     return C.make_c5(per_size=1, sizes=SIZES)
 
 
-@pytest.mark.parametrize("kind", ["fourier", "none", "blockdiag"])
+@pytest.mark.parametrize("kind", ["fourier", "none", "blockdiag", "daub4"])
 def test_batch_matches_single_problem_iterations(kind):
+    _batch_vs_single(kind)
+
+
+@pytest.mark.parametrize("kind", ["fourier", "daub4"])
+def test_batch_of_blurred_problems(kind):
+    """Slices with a projection-domain blur (its three ray passes inside the
+    captured graph)."""
+    _batch_vs_single(kind, blur=[[0.2, 0.6, 0.2]])
+
+
+def _batch_vs_single(kind, blur=None):
     wls = _slices()
-    announce("batch", kind)
+    announce("batch", kind, "blur" if blur else "")
     probs = [mb.Problem.from_workload(w) for w in wls]
     ref_probs = [mb.Problem.from_workload(w) for w in wls]
     for p in probs + ref_probs:
+        if blur is not None:
+            p.set_blur(blur)
         if kind != "none":
             p.precond_build(kind)
     n = 30
