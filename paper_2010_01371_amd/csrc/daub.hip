@@ -25,6 +25,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kCoarse = 64;                     // coarse levels: kCoarse^2 floats x 2 in LDS
+constexpr int kCoarseThreads = 1024;
 
 struct D4Filter {
     float h[4], g[4];
@@ -77,27 +78,30 @@ __global__ __launch_bounds__(kThreads) void k_d4_pass(D4Filter f, int n, int m, 
 }
 
 // The levels m <= T of channel blockIdx.x (T = min(n, kCoarse)), in LDS:
-// forward from m = T down to 2, inverse from 2 up to T.
-__global__ __launch_bounds__(kThreads) void k_d4_coarse(D4Filter f, int n, int T, int inverse, float* __restrict__ a) {
+// forward from m = T down to 2, inverse from 2 up to T.  Each level's first
+// pass goes A -> B and its second B -> A, so a level ends in A; entries of B
+// outside the current block are stale but never read.
+__global__ __launch_bounds__(kCoarseThreads) void k_d4_coarse(D4Filter f, int n, int T, int inverse,
+                                                             float* __restrict__ a) {
     __shared__ float A[kCoarse * kCoarse], B[kCoarse * kCoarse];
     float* img = a + (size_t)blockIdx.x * n * n;
-    for (int t = threadIdx.x; t < T * T; t += kThreads) A[t] = img[(size_t)(t / T) * n + t % T];
+    for (int t = threadIdx.x; t < T * T; t += kCoarseThreads) A[t] = img[(size_t)(t / T) * n + t % T];
     __syncthreads();
-    for (int step = 0, m = inverse ? 2 : T; inverse ? m <= T : m >= 2; ++step, m = inverse ? 2 * m : m / 2) {
+    for (int m = inverse ? 2 : T; inverse ? m <= T : m >= 2; m = inverse ? 2 * m : m / 2) {
         for (int pass = 0; pass < 2; ++pass) {
             // forward: rows then columns; inverse: columns then rows
             const bool along_rows = (pass == 0) != (inverse != 0);
-            for (int t = threadIdx.x; t < m * m; t += kThreads) {
+            const float* src = pass == 0 ? A : B;
+            float* dst = pass == 0 ? B : A;
+            for (int t = threadIdx.x; t < m * m; t += kCoarseThreads) {
                 const int r = t / m, c = t - r * m;
-                B[r * T + c] = along_rows ? d4_line(f, A + r * T, 1, m, c, inverse != 0)
-                                          : d4_line(f, A + c, T, m, r, inverse != 0);
+                dst[r * T + c] = along_rows ? d4_line(f, src + r * T, 1, m, c, inverse != 0)
+                                            : d4_line(f, src + c, T, m, r, inverse != 0);
             }
-            __syncthreads();
-            for (int t = threadIdx.x; t < m * m; t += kThreads) A[(t / m) * T + t % m] = B[(t / m) * T + t % m];
             __syncthreads();
         }
     }
-    for (int t = threadIdx.x; t < T * T; t += kThreads) img[(size_t)(t / T) * n + t % T] = A[t];
+    for (int t = threadIdx.x; t < T * T; t += kCoarseThreads) img[(size_t)(t / T) * n + t % T] = A[t];
 }
 
 void check(int n) {
@@ -120,7 +124,8 @@ void level(const D4Filter& f, int K, int n, int m, bool inverse, float* x, float
 void coarse(const D4Filter& f, int K, int n, bool inverse, float* a, hipStream_t s) {
     {
         KernelTimer kt_("k_d4_coarse", s);
-        hipLaunchKernelGGL(k_d4_coarse, dim3(K), dim3(kThreads), 0, s, f, n, std::min(n, kCoarse), inverse ? 1 : 0, a);
+        hipLaunchKernelGGL(k_d4_coarse, dim3(K), dim3(kCoarseThreads), 0, s, f, n, std::min(n, kCoarse),
+                           inverse ? 1 : 0, a);
         kt_.stop();
     }
     MBMD_LAUNCHED();
