@@ -9,11 +9,13 @@
  *
  * Estimation problem (Methods, "Generalized Models for Data Acquisition and
  * Estimation", eq:meanModel and eq:mapEstimator):
- *     ybar(x) = S exp(-(Q (x) A) x),
+ *     ybar(x) = B S exp(-(Q (x) A) x),
  *     Phi(x)  = 1/2 (y - ybar)^T diag(w) (y - ybar) + R(x),
  * with x the stack of N_k material images, A the 2D projector, Q [N_E x N_k]
  * the attenuation of each material per energy, S [N_c x N_E] the channel
- * sensitivities (gain and I0 folded in), w = 1/variance per ray and channel.
+ * sensitivities (gain and I0 folded in), B an optional projection-domain blur
+ * along the detector (identity unless mbmd_problem_set_blur sets one), and
+ * w = 1/variance per ray and channel.
  * Standard CT is N_k = N_E = N_c = 1 with S = I0 and Q = 1 ("Standard CT
  * Reconstruction"); projection-domain decomposition is the identity geometry
  * (A = I, "Projection-Domain Decomposition"); one-step MBMD is the general
