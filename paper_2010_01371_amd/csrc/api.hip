@@ -30,6 +30,7 @@ struct mbmd_batch {
     std::vector<int> lane;              // branch stream of each problem
     int n_lanes = 0;
     std::vector<float*> xs;
+    std::vector<int> versions;          // each problem's launch_version when captured
     int precond = -1;
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
@@ -704,6 +705,7 @@ int mbmd_problem_set_blur(mbmd_problem* prob, const float* taps_host, int half_w
             launch_blur(b, P.ni, P.C, P.btmp1, nullptr, P.wb, true, s);
         }
         P.blur = b;
+        ++P.launch_version;                                 // a captured batch iteration is stale
         P.dL_valid = 0;
         P.m0_state = 0;
         for (int k = 0; k < kPreconds; ++k) P.built[k] = 0;
@@ -906,7 +908,8 @@ int mbmd_batch_sps_step(mbmd_batch* b, float* const* x_dev, int precond, int n_i
         // captured); the branches join the capture through the fork event, and the
         // instantiated graphs are then launched on the caller's stream.
         bool same = b->captured && b->precond == precond && b->xs.size() == n;
-        for (size_t i = 0; same && i < n; ++i) same = b->xs[i] == x_dev[i];
+        for (size_t i = 0; same && i < n; ++i)
+            same = b->xs[i] == x_dev[i] && b->versions[i] == b->probs[i]->launch_version;
         if (!same) {
             for (int i = 0; i < 2; ++i) {
                 if (b->exec[i]) (void)hipGraphExecDestroy(b->exec[i]);
@@ -937,6 +940,8 @@ int mbmd_batch_sps_step(mbmd_batch* b, float* const* x_dev, int precond, int n_i
             b->captured = true;
             b->precond = precond;
             b->xs.assign(x_dev, x_dev + n);
+            b->versions.resize(n);
+            for (size_t i = 0; i < n; ++i) b->versions[i] = b->probs[i]->launch_version;
         }
         b->stream = s;
         for (int it = 0; it < n_iter; ++it) {

@@ -295,6 +295,7 @@ struct Problem {
     float* W = nullptr;              // [npk][ni] Fisher weights (build)
     // projection-domain blur (mbmd_problem_set_blur); buffers in blur_arena
     BlurArgs blur;
+    int launch_version = 0;          // bumped when the iteration's launch sequence or arguments change
     Arena blur_arena;
     float* wb = nullptr;             // [C][ni] B^T W B 1 (the eta factor)
     float* J = nullptr;              // [C][K][ni] Jacobian of the unblurred means (build)

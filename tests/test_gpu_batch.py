@@ -64,3 +64,35 @@ def _batch_vs_single(kind, blur=None):
     for a, b, r in zip(results[False], results[True], refs):
         np.testing.assert_array_equal(a, b)          # graph replay == eager launches
         np.testing.assert_array_equal(a, r)          # batch == per-problem iterations
+
+
+def test_batch_graph_recaptured_after_a_blur_is_set():
+    """A blur set between two graph calls changes the launch sequence: the
+    batch captures its iteration again (the per-problem runs are the check)."""
+    wls = _slices()
+    announce("batch", "fourier", "blur set between graph calls")
+    taps = [[0.2, 0.6, 0.2]]
+    probs = [mb.Problem.from_workload(w) for w in wls]
+    ref_probs = [mb.Problem.from_workload(w) for w in wls]
+    refs = []
+    for p in ref_probs:
+        p.precond_build("fourier")
+        x = p.zeros_image()
+        p.sps_step(x, "fourier", 10)
+        p.set_blur(taps)
+        p.precond_build("fourier")
+        p.sps_step(x, "fourier", 10)
+        refs.append(host(x))
+    for p in probs:
+        p.precond_build("fourier")
+    xs = [p.zeros_image() for p in probs]
+    batch = mb.Batch(probs)
+    batch.sps_step(xs, "fourier", 10, use_graph=True)
+    for p in probs:
+        p.set_blur(taps)
+        p.precond_build("fourier")
+    batch.sps_step(xs, "fourier", 10, use_graph=True)
+    got = [host(x) for x in xs]
+    batch.close()
+    for a, r in zip(got, refs):
+        np.testing.assert_array_equal(a, r)
