@@ -326,8 +326,10 @@ void mbmd_batch_destroy(mbmd_batch* batch);
  * n_iter iterations of every problem of the batch (x_dev[i] belongs to
  * problem i).  use_graph != 0 captures one iteration over all problems in a
  * hipGraph on the first call (the geometry groups as parallel branches) and
- * replays it on `stream`; the same x pointers must be passed on later calls
- * (a change re-captures).  use_graph == 0 enqueues every iteration of each
+ * replays it on `stream`; other x pointers, another preconditioner kind or a
+ * member problem's blur set since the capture (mbmd_problem_set_blur) make
+ * the call capture again.  Preconditioner tables rebuilt in place need no new
+ * capture: a replay reads them as they are.  use_graph == 0 enqueues every iteration of each
  * geometry group on its stream.  Either way the work is ordered after what
  * `stream` held before the call and before what it receives after it.
  * Preconditioners must have been built.  No objective trace.
