@@ -207,3 +207,37 @@ def test_reference_weights_are_the_gram_of_the_jacobian():
     W_fd = np.einsum("cvb,ckvb,clvb->klvb", prob.w, J, J)
     np.testing.assert_allclose(W, W_fd, rtol=1e-6, atol=1e-9 * np.abs(W_fd).max())
 
+
+
+@pytest.mark.parametrize("kind", ["haar", "daub4"])
+@pytest.mark.parametrize("K", [2, 3])
+def test_cross_material_wavelet_exact_for_coefficient_block_hessian(kind, K):
+    """Cross-material wavelet preconditioner: for a Hessian that is block
+    diagonal in the wavelet domain, H = (I (x) U^T) D{B_w} (I (x) U), with a
+    different symmetric positive definite N_k x N_k material coupling B_w for
+    every coefficient w, the excitation U^T 1 (x) e_k reads column k of every
+    B_w at once (U U^T 1 = 1), so the per-coefficient blocks K_w equal B_w and
+    M = U^T K^-1/2 U whitens H exactly.  Exciting all materials together
+    (U^T 1 in every material), the test function U 1 in place of U^T 1, or
+    the inverse transform of the response in place of U, each fails it."""
+    n = 8
+    wv = precond.WAVELETS[kind]
+    prob = _toy(n, K)
+    rng = np.random.default_rng(40 + K)
+    A = rng.normal(size=(n, n, K, K))
+    Bw = A @ np.swapaxes(A, -1, -2) + 0.5 * np.eye(K)             # SPD per coefficient
+
+    def hop(v):
+        c = np.stack([wv.forward(vk) for vk in v])                 # [K, n, n] coefficients
+        c = np.einsum("yxkl,lyx->kyx", Bw, c)
+        return np.stack([wv.inverse(ck) for ck in c])
+
+    t = precond.build(prob, kind, modified=False, hop=hop, eps=1e-12)
+    assert t["n_floored"] == 0
+    Kb = precond.wavelet_blocks(prob, None, t["M0"], hop=hop, wavelet=wv)
+    np.testing.assert_allclose(Kb, Bw, rtol=1e-12, atol=1e-12)
+    want = np.stack([scipy.linalg.fractional_matrix_power(b, -0.5).real for b in Bw.reshape(-1, K, K)])
+    np.testing.assert_allclose(t["P"].reshape(-1, K, K), want, rtol=1e-9, atol=1e-12)
+    M = _dense(lambda v: precond.apply_M(t, v), (K, n, n))
+    H = _dense(hop, (K, n, n))
+    np.testing.assert_allclose(M.T @ H @ M, np.eye(K * n * n), atol=1e-10)
