@@ -121,11 +121,24 @@ static int ray_capacity(const ogeom* g) {
     return (g->nx + 2) * (g->ny + 2);
 }
 
+/* Threads for one projector call: about one per 2e5 ray-pixel steps, so that
+ * small geometries run on one thread (waking a team costs more than their
+ * work), capped by oracle_set_threads. */
+static int threads_for(const ogeom* g) {
+    int nt = 1;
+#ifdef _OPENMP
+    const double work = (double)g->n_views * g->n_bins * (g->nx > g->ny ? g->nx : g->ny);
+    nt = (int)(work / 2e5) + 1;
+    if (nt > omp_get_max_threads()) nt = omp_get_max_threads();
+#endif
+    return nt;
+}
+
 /* sino[m][v][b] = sum_j A[(v,b), j] x[m][j] for n_mat images. Returns 0 or -1. */
 int oracle_project(const ogeom* g, const double* x, double* sino, int n_mat) {
     const int V = g->n_views, B = g->n_bins, nj = g->nx * g->ny;
     int err = 0;
-#pragma omp parallel
+#pragma omp parallel num_threads(threads_for(g))
     {
         const int cap = ray_capacity(g);
         int* idx = (int*)malloc(sizeof(int) * cap);
@@ -151,10 +164,7 @@ int oracle_project(const ogeom* g, const double* x, double* sino, int n_mat) {
 /* x[m][j] = sum_i A[i, j] sino[m][i] (exact transpose of oracle_project). */
 int oracle_backproject(const ogeom* g, const double* sino, double* x, int n_mat) {
     const int V = g->n_views, B = g->n_bins, nj = g->nx * g->ny;
-    int nthreads = 1;
-#ifdef _OPENMP
-    nthreads = omp_get_max_threads();
-#endif
+    const int nthreads = threads_for(g);
     double* part = (double*)calloc((size_t)nthreads * n_mat * nj, sizeof(double));
     if (!part) return -1;
     int err = 0;

@@ -213,9 +213,10 @@ def make_c4(noise=True):
                     ["none", "blockdiag", "fourier"], energies=E, materials=mats)
 
 
-def make_small_mbmd(n=32, views=60, bins=64, n_mat=3, noise=True, n_energy_step=5):
-    """A small one-step MBMD problem (coarser energy grid) for fast tests."""
-    rng = np.random.default_rng(seed_for(4, 50))
+def make_small_mbmd(n=32, views=60, bins=64, n_mat=3, noise=True, n_energy_step=5, seed_slice=50):
+    """A small one-step MBMD problem (coarser energy grid) for fast tests;
+    seed_slice picks another phantom and noise draw."""
+    rng = np.random.default_rng(seed_for(4, seed_slice))
     if n_mat == 3:
         E, Q, S = c4_spectral()
         mats = ["water", "calcium", "iodine"]
