@@ -33,11 +33,20 @@
  *     in which case the call synchronizes that stream before returning.
  *   - Return value: MBMD_OK (0) or a negative mbmd_status.  No exception
  *     crosses this interface.  mbmd_last_error() returns a thread-local
- *     message for the last failure.  Errors of kernels already enqueued
- *     surface at the next synchronizing call.
- *   - The library allocates its own device memory (geometry tables,
- *     problem state, preconditioner tables) when a problem or geometry is
- *     first set up, never inside mbmd_sps_step's iteration loop.
+ *     message for the last failure.  Numeric failures of kernels already
+ *     enqueued (mbmd_numeric_flags) surface at the next synchronizing call
+ *     on the problem: mbmd_sps_step with a trace, mbmd_gradient with an
+ *     objective, or mbmd_problem_check.
+ *   - Device memory: a problem's whole device state (geometry tables,
+ *     problem state, preconditioner tables, scratch) lives in one block of
+ *     mbmd_workspace_bytes bytes, either a workspace the caller passes to
+ *     mbmd_problem_create (e.g. a torch uint8 tensor; the library then
+ *     allocates nothing for the problem) or, for a NULL workspace, one
+ *     allocation made by mbmd_problem_create.  Nothing is allocated inside
+ *     the iterations, applies, builds or batches.  The standalone projector
+ *     calls (mbmd_project, mbmd_backproject, mbmd_projector_nnz) keep
+ *     library-allocated tables per geometry, device and stream (at most 16,
+ *     least recently used freed first; mbmd_cache_clear frees them).
  */
 #ifndef MBMD_H
 #define MBMD_H
@@ -77,6 +86,27 @@ typedef enum {
 typedef enum {
     MBMD_PRECOND_UNMODIFIED = 1 /* M0 = I: the unmodified preconditioners (the Fourier one of eq:fourierEigenbasis) */
 } mbmd_precond_flags;
+
+/* Flags of mbmd_workspace_bytes / mbmd_problem_create. */
+typedef enum {
+    MBMD_WORKSPACE_BLUR = 1     /* room for a projection-domain blur (mbmd_problem_set_blur) */
+} mbmd_workspace_flags;
+
+/* Numeric flags raised on the device by the iterations and read (and
+ * cleared) by the synchronizing calls.  The first three are failures
+ * (MBMD_ERR_NUMERIC); the last is a warning. */
+typedef enum {
+    MBMD_FLAG_NONFINITE = 1,    /* objective, g^T p, step denominator or step size not finite */
+    MBMD_FLAG_NO_CURVATURE = 2, /* preconditioned step: the 1D majoriser's curvature
+                                   sum_iE c q^2 + p^T R'' p is not positive for g^T p != 0
+                                   (the step is skipped) */
+    MBMD_FLAG_ASCENT = 4,       /* preconditioned step: g^T p > 0, i.e. M M^T is not positive
+                                   semi-definite (the step alpha < 0 is still the majoriser's
+                                   minimiser) */
+    MBMD_FLAG_INCREASE = 8      /* the objective rose between consecutive evaluations of one run
+                                   by more than 1e-5 relative (SPS decreases it monotonically when
+                                   every line integral stays >= 0, which is not enforced) */
+} mbmd_numeric_flags;
 
 typedef enum {
     MBMD_PENALTY_QUADRATIC = 0, /* R = 1/2 x^T (beta (x) Gamma) x */
@@ -140,9 +170,9 @@ typedef struct mbmd_batch mbmd_batch;
  * sino_dev[m] = A x_dev[m] for m < n_mat  (forward projection, the A of
  * eq:meanModel in the standard-CT and one-step MBMD sections).
  * x_dev: [n_mat][ny][nx]; sino_dev: [n_mat][n_views][n_bins]; 1 <= n_mat <= 4.
- * Geometry tables are built on the first call with a given geometry and
- * cached per device; concurrent calls with the same geometry on different
- * streams race on the cached scratch buffer.
+ * Geometry tables are built on the first call with a given geometry on a
+ * given device and stream and cached there (see the conventions above):
+ * calls on different streams have separate scratch and may overlap.
  * Errors: MBMD_ERR_ARG (NULL pointer, bad sizes), MBMD_ERR_SHAPE (fan source
  * inside the image circle or between the sweep lines of a view, a bin
  * boundary parallel to the sweep lines, n_mat out of range), MBMD_ERR_HIP.
@@ -169,18 +199,48 @@ int mbmd_projector_nnz(const mbmd_geometry* geom, long long* nnz_host, void* str
 /* ---------------------------------------------------------------- problems */
 
 /*
- * Create a problem: copies the descriptors, y_dev and w_dev
+ * Device bytes a problem with this geometry and spectral model needs
+ * (flags: 0 or MBMD_WORKSPACE_BLUR); the descriptors' table pointers are not
+ * read.  Errors: MBMD_ERR_ARG (NULL, unknown flag), MBMD_ERR_SHAPE.
+ */
+int mbmd_workspace_bytes(const mbmd_geometry* geom, const mbmd_spectral* spectral, int flags,
+                         size_t* bytes_host);
+
+/*
+ * Create a problem (the estimation problem of eq:mapEstimator with the mean
+ * model of eq:meanModel): copies the descriptors, y_dev and w_dev
  * ([n_chan][n_views][n_bins]; w = inverse variance, or NULL for
- * w = 1/max(y, 1)), allocates device state and computes A 1 (the gamma of
- * the SPS section).  Errors: MBMD_ERR_ARG, MBMD_ERR_SHAPE (limits above;
- * identity geometry with nx != n_bins or ny != n_views), MBMD_ERR_HIP.
+ * w = 1/max(y, 1)), builds the projector tables in FP64 on the host, and
+ * computes A 1 (the gamma of the SPS section).
+ *   - workspace_dev: NULL, or caller-owned device memory of workspace_bytes
+ *     >= mbmd_workspace_bytes(geom, spectral, flags), 256-byte aligned, that
+ *     holds the problem's whole device state until mbmd_problem_destroy (the
+ *     library then allocates no device memory for the problem).  NULL: the
+ *     library allocates that block itself and frees it at destroy.
+ *   - flags: 0 or MBMD_WORKSPACE_BLUR (the blur's buffers are part of the
+ *     block; without it a blur needs library memory, so mbmd_problem_set_blur
+ *     fails on a caller workspace).
+ * Synchronizes `stream` before returning.  Errors: MBMD_ERR_ARG (NULL,
+ * workspace too small or misaligned, unknown flag), MBMD_ERR_SHAPE (limits
+ * above; identity geometry with nx != n_bins or ny != n_views), MBMD_ERR_HIP.
  */
 int mbmd_problem_create(const mbmd_geometry* geom, const mbmd_spectral* spectral,
                         const mbmd_penalty* penalty, const float* y_dev, const float* w_dev,
-                        void* stream, mbmd_problem** out);
+                        void* workspace_dev, size_t workspace_bytes, int flags, void* stream,
+                        mbmd_problem** out);
 
-/* Free a problem (synchronizes its last stream). NULL is ignored. */
+/* Free a problem (synchronizes its last stream; a caller workspace is then
+ * the caller's again). NULL is ignored. */
 void mbmd_problem_destroy(mbmd_problem* prob);
+
+/*
+ * Synchronizes `stream`, writes the numeric flags raised since they were
+ * last read into *flags_host (may be NULL) and clears them.  Returns
+ * MBMD_ERR_NUMERIC when a failure bit (MBMD_FLAG_NONFINITE,
+ * MBMD_FLAG_NO_CURVATURE, MBMD_FLAG_ASCENT) was among them, MBMD_OK
+ * otherwise (MBMD_FLAG_INCREASE alone is a warning).
+ */
+int mbmd_problem_check(mbmd_problem* prob, int* flags_host, void* stream);
 
 /*
  * Build preconditioner `kind` ("Preconditioned Optimization" and the
@@ -244,12 +304,15 @@ int mbmd_precond_build_ex(mbmd_problem* prob, int kind, int flags, const float* 
  * section, so the one-energy curvature is recomputed every iteration), the
  * forward model and its VJP, and the preconditioner builds (Fisher
  * information A^T J^T B^T W B J A; the data-based D ignores the blur).  It
- * voids every preconditioner built before it.  The first call with h > 0
- * allocates (3 + n_mat) n_chan n_rays floats on the device, freed by
- * mbmd_problem_destroy.  Asynchronous on `stream`.
+ * voids every preconditioner built before it.  Its buffers, (3 + n_mat)
+ * n_chan n_rays floats, are part of the problem's block when it was sized
+ * with MBMD_WORKSPACE_BLUR; otherwise the first call with h > 0 allocates
+ * them (library-owned block only), freed by mbmd_problem_destroy.
+ * Asynchronous on `stream`.
  * Errors: MBMD_ERR_ARG (NULL problem, h out of range, NULL, negative or
  * non-finite taps), MBMD_ERR_UNSUPPORTED (identity geometry, whose rays the
- * blur would couple), MBMD_ERR_HIP.
+ * blur would couple; a caller workspace sized without MBMD_WORKSPACE_BLUR),
+ * MBMD_ERR_HIP.
  */
 int mbmd_problem_set_blur(mbmd_problem* prob, const float* taps_host, int half_width, void* stream);
 
@@ -270,7 +333,9 @@ int mbmd_precond_apply(mbmd_problem* prob, int kind, const float* g_dev, float* 
  *          Hessian diagonal, c_E = max(2 eta_E + rho_E, 0)),
  * with rho read as S^T W (ybar - y) - eta t (the printed x^(n) stands for
  * t^(n)).  grad_dev, curv_dev: [n_mat][ny][nx]; curv_dev and
- * objective_host (Phi(x), FP64) may be NULL.
+ * objective_host (Phi(x), FP64) may be NULL.  With objective_host the call
+ * synchronizes and returns MBMD_ERR_NUMERIC when Phi is not finite or an
+ * earlier call raised a numeric failure flag.
  */
 int mbmd_gradient(mbmd_problem* prob, const float* x_dev, float* grad_dev, float* curv_dev,
                   double* objective_host, void* stream);
@@ -286,8 +351,9 @@ int mbmd_gradient(mbmd_problem* prob, const float* x_dev, float* grad_dev, float
  *   carried across iterations and recomputed every 25.  Reductions are FP64
  *   and alpha stays on the device.
  * objective_trace_host: NULL, or n_iter+1 doubles receiving Phi before each
- * iteration and after the last (synchronizes).  Returns MBMD_ERR_NUMERIC if
- * a non-finite objective or step was produced.
+ * iteration and after the last (synchronizes, and returns MBMD_ERR_NUMERIC
+ * when a numeric failure flag was raised).  Without a trace the call only
+ * enqueues; its flags are read by the next synchronizing call.
  */
 int mbmd_sps_step(mbmd_problem* prob, float* x_dev, int precond, int n_iter,
                   double* objective_trace_host, void* stream);
@@ -364,6 +430,9 @@ int mbmd_profile_kernels(char* names, size_t capacity);
 const char* mbmd_status_string(int status);
 const char* mbmd_last_error(void);
 int mbmd_version(void);
+/* Frees the cached tables of the standalone projector calls on every device
+ * (waits for the devices).  Safe to call at any time; the next call rebuilds. */
+int mbmd_cache_clear(void);
 
 #ifdef __cplusplus
 }

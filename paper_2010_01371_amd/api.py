@@ -19,6 +19,9 @@ KINDS = {"parallel": 0, "fan": 1, "identity": 2}
 PRECONDS = {"none": 0, "fourier": 1, "haar": 2, "blockdiag": 3, "daub4": 4}
 PRECOND_UNMODIFIED = 1          # mbmd_precond_flags
 PENALTIES = {"quadratic": 0, "huber": 1}
+WORKSPACE_BLUR = 1              # mbmd_workspace_flags
+# mbmd_numeric_flags
+FLAG_NONFINITE, FLAG_NO_CURVATURE, FLAG_ASCENT, FLAG_INCREASE = 1, 2, 4, 8
 
 
 def _stream():
@@ -73,6 +76,28 @@ def backproject(geom, sino):
     return out
 
 
+def cache_clear():
+    """mbmd_cache_clear: free the standalone projector calls' cached tables."""
+    check(_lib.load().mbmd_cache_clear(), "mbmd_cache_clear")
+
+
+def _spectral_struct(Q, S):
+    return _lib.Spectral(Q.shape[1], Q.shape[0], S.shape[0], Q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                         S.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+
+
+def workspace_bytes(geom, Q, S, flags=0):
+    """mbmd_workspace_bytes: device bytes of a problem's state."""
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    g = geometry_struct(geom)
+    sp = _spectral_struct(Q, S)
+    n = ctypes.c_size_t(0)
+    check(_lib.load().mbmd_workspace_bytes(ctypes.byref(g), ctypes.byref(sp), int(flags), ctypes.byref(n)),
+          "mbmd_workspace_bytes")
+    return int(n.value)
+
+
 def projector_nnz(geom):
     """Nonzeros of A for a geometry (counted on the GPU from the projector tables)."""
     lib = _lib.load()
@@ -83,9 +108,16 @@ def projector_nnz(geom):
 
 
 class Problem:
-    """A PWLS / MBMD estimation problem living on the GPU."""
+    """A PWLS / MBMD estimation problem living on the GPU.
 
-    def __init__(self, geom, Q, S, y, w=None, penalty=None, device="cuda"):
+    workspace: "torch" (default) passes a torch uint8 tensor of
+    mbmd_workspace_bytes as the problem's device memory, so torch owns it;
+    None lets the library allocate it; or a CUDA uint8 tensor to use.
+    blur_room: size the workspace for a projection-domain blur (set_blur);
+    by default only a torch-made workspace is (a library block grows on demand).
+    """
+
+    def __init__(self, geom, Q, S, y, w=None, penalty=None, device="cuda", workspace="torch", blur_room=None):
         lib = _lib.load()
         self.geom = dict(geom)
         Q = np.ascontiguousarray(Q, dtype=np.float64)
@@ -105,27 +137,46 @@ class Problem:
             w = _dev_f32(w.contiguous(), (self.n_chan,) + self.sino_shape, "w")
         self.device = y.device
         g = geometry_struct(geom)
-        sp = _lib.Spectral(self.n_mat, self.n_energy, self.n_chan,
-                           Q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                           S.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        sp = _spectral_struct(Q, S)
         pen = _lib.Penalty(PENALTIES[penalty.get("kind", "quadratic")],
                            beta.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(penalty.get("delta", 0.0)))
+        made_by_torch = isinstance(workspace, str) and workspace == "torch"
+        if blur_room is None:
+            blur_room = made_by_torch
+        flags = WORKSPACE_BLUR if blur_room else 0
+        if made_by_torch:
+            workspace = torch.empty(workspace_bytes(geom, Q, S, flags), dtype=torch.uint8, device=self.device)
+        if workspace is not None and (not torch.is_tensor(workspace) or not workspace.is_cuda
+                                      or workspace.dtype != torch.uint8 or not workspace.is_contiguous()):
+            raise TypeError("workspace must be a contiguous CUDA uint8 tensor, 'torch' or None")
+        self._ws = workspace
         h = ctypes.c_void_p()
         check(lib.mbmd_problem_create(ctypes.byref(g), ctypes.byref(sp), ctypes.byref(pen), _ptr(y),
-                                      _ptr(w) if w is not None else None, _stream(), ctypes.byref(h)),
+                                      _ptr(w) if w is not None else None,
+                                      _ptr(workspace) if workspace is not None else None,
+                                      workspace.numel() if workspace is not None else 0, flags, _stream(),
+                                      ctypes.byref(h)),
               "mbmd_problem_create")
         self._h = h
         self._lib = lib
 
     @classmethod
-    def from_workload(cls, wl, device="cuda"):
-        return cls(wl.geom, wl.Q, wl.S, wl.y, wl.w, wl.penalty, device=device)
+    def from_workload(cls, wl, device="cuda", **kw):
+        return cls(wl.geom, wl.Q, wl.S, wl.y, wl.w, wl.penalty, device=device, **kw)
 
     # ------------------------------------------------------------------
     def close(self):
         if getattr(self, "_h", None):
             self._lib.mbmd_problem_destroy(self._h)
             self._h = None
+        self._ws = None                  # the workspace outlives the problem
+
+    def check(self):
+        """mbmd_problem_check: the numeric flags raised since the last read
+        (cleared); raises MbmdError (MBMD_ERR_NUMERIC) on a failure flag."""
+        f = ctypes.c_int(0)
+        check(self._lib.mbmd_problem_check(self._h, ctypes.byref(f), _stream()), "mbmd_problem_check")
+        return int(f.value)
 
     def __del__(self):
         try:

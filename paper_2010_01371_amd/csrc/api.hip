@@ -58,12 +58,22 @@ void Arena::reserve(size_t bytes) {
     MBMD_HIP(hipMalloc(&base, bytes));
     size = bytes;
     used = 0;
+    owned = true;
+}
+
+void Arena::adopt(void* mem, size_t bytes) {
+    MBMD_REQUIRE((reinterpret_cast<uintptr_t>(mem) & 255) == 0, MBMD_ERR_ARG, "workspace must be 256-byte aligned");
+    base = static_cast<char*>(mem);
+    size = bytes;
+    used = 0;
+    owned = false;
 }
 
 void Arena::release() {
-    if (base) (void)hipFree(base);
+    if (base && owned) (void)hipFree(base);
     base = nullptr;
     size = used = 0;
+    owned = false;
 }
 
 namespace {
@@ -124,10 +134,23 @@ const float* backproject_parts(Problem& P, const float* sino, float* img, int nc
 
 double* region(Problem& P, int r) { return P.partials + (size_t)r * kMaxPartials; }
 
+// The projection-domain blur's buffers, from arena A.
+void carve_blur(Problem& P, Arena& A) {
+    const size_t ni = P.ni, C = P.C, K = P.K;
+    P.wb = A.take<float>(C * ni);
+    P.J = A.take<float>(C * K * ni);
+    P.btmp0 = A.take<float>(C * ni);
+    P.btmp1 = A.take<float>(C * ni);
+}
+
+// Back projection channels a problem's geometry is sized for.
+int problem_back_ch(const Problem& P) { return std::max(P.npk, 2 * P.K); }
+
 // Sizes every buffer; called twice (sizing pass with a null arena base, then for real).
 void carve(Problem& P) {
     Arena& A = P.arena;
     const size_t nj = P.nj, ni = P.ni, K = P.K, C = P.C, E = P.E, npk = P.npk;
+    P.geom_mem = P.identity ? nullptr : A.take<char>(P.geom_bytes);
     P.Q = A.take<float>(E * K);
     P.S = A.take<float>(C * E);
     P.rowS = A.take<float>(C);
@@ -169,6 +192,41 @@ void carve(Problem& P) {
     P.trace = A.take<double>(kTraceCap + 1);
     P.trace_cap = kTraceCap;
     P.flags = A.take<int>(4);
+    if (P.ws_flags & MBMD_WORKSPACE_BLUR) carve_blur(P, A);
+}
+
+// Sizes of a problem from its descriptors (everything carve needs).
+void size_problem(Problem& P, const mbmd_geometry& g, const mbmd_spectral& sp, int flags) {
+    validate_geometry(g);
+    MBMD_REQUIRE(sp.n_mat >= 1 && sp.n_mat <= kMaxMat && sp.n_chan >= 1 && sp.n_chan <= kMaxChan &&
+                     sp.n_energy >= 1 && sp.n_energy <= kMaxEnergy,
+                 MBMD_ERR_SHAPE, "spectral sizes out of range (n_mat<=4, n_chan<=8, n_energy<=256)");
+    MBMD_REQUIRE((flags & ~MBMD_WORKSPACE_BLUR) == 0, MBMD_ERR_ARG, "unknown workspace flag");
+    P.g = g;
+    P.identity = g.kind == MBMD_GEOM_IDENTITY;
+    P.K = sp.n_mat;
+    P.E = sp.n_energy;
+    P.C = sp.n_chan;
+    P.npk = P.K * (P.K + 1) / 2;
+    P.nx = g.nx;
+    P.ny = g.ny;
+    P.V = g.n_views;
+    P.B = g.n_bins;
+    P.nj = g.nx * g.ny;
+    P.ni = g.n_views * g.n_bins;
+    P.ws_flags = flags;
+    MBMD_REQUIRE(P.ni <= 256 * kMaxPartials && P.nj <= 256 * kMaxPartials, MBMD_ERR_SHAPE,
+                 "problem too large for the partial-sum buffer");
+    P.geom_bytes = P.identity ? 0 : geometry_bytes(g, P.K, problem_back_ch(P));
+}
+
+// Bytes of the device state of a problem sized by size_problem.
+size_t problem_bytes(Problem& P) {
+    P.arena = Arena{};
+    carve(P);                                     // sizing pass
+    const size_t bytes = P.arena.used;
+    P.arena = Arena{};
+    return bytes;
 }
 
 // The data part of the Fisher information on line integrals in [K][ni] ->
@@ -340,7 +398,7 @@ void objective_at(Problem& P, const float* x, double* slot, hipStream_t s) {
     counts[R_PHI_L] = launch_ray_grad(ray_args(P), P.l, P.u, nullptr, nullptr, region(P, R_PHI_L), s);
     counts[R_PHI_R] = launch_penalty_grad(pen_args(P), x, P.t2_img, nullptr, P.t2_img, nullptr,
                                           region(P, R_PHI_R), s);
-    launch_reduce_final(P.partials, counts, P.scal, slot, 0, P.flags, s);
+    launch_reduce_final(P.partials, counts, P.scal, slot, RED_MONOTONE, P.flags, s);
 }
 
 // One plain SPS iteration: x <- x - (g + dR)/(d + d_R).
@@ -354,7 +412,7 @@ void plain_iteration(Problem& P, float* x, double* trace_slot, hipStream_t s) {
     counts[R_PHI_R] = launch_penalty_grad(pen_args(P), x, P.g_img, cconst ? P.dL_const : P.d_img, P.g_img,
                                           P.d_img, region(P, R_PHI_R), s);
     launch_plain_update(P.K * P.nj, x, P.g_img, P.d_img, s);
-    launch_reduce_final(P.partials, counts, P.scal, trace_slot, 0, P.flags, s);
+    launch_reduce_final(P.partials, counts, P.scal, trace_slot, RED_MONOTONE, P.flags, s);
 }
 
 // MBMD_FUSE_ROWS=0 in the environment (read on every iteration) keeps the
@@ -394,7 +452,7 @@ void precond_iteration(Problem& P, float* x, int kind, double* trace_slot, hipSt
     project(P, P.p_img, P.q, P.K, s);
     const PenaltyArgs pa = pen_args(P);
     launch_curvature(ray_args(P), P.l, P.r, P.q, P.has_penalty ? &pa : nullptr, x, P.p_img, P.partials, counts, s);
-    launch_reduce_final(P.partials, counts, P.scal, trace_slot, 1, P.flags, s);   // alpha: applied next
+    launch_reduce_final(P.partials, counts, P.scal, trace_slot, RED_STEP | RED_MONOTONE, P.flags, s);   // alpha: applied next
 }
 
 // Applies a pending preconditioned step (x += alpha p, l += alpha q) and clears
@@ -416,21 +474,39 @@ void check_precond_ready(Problem& P, int precond) {
     if (precond != MBMD_PRECOND_NONE) MBMD_REQUIRE(P.built[precond], MBMD_ERR_NOT_BUILT, "preconditioner not built");
 }
 
-void read_flags(Problem& P, hipStream_t s) {
+// Waits for s, returns the numeric flags raised since they were last read
+// (in *out when not NULL) and clears them; throws MBMD_ERR_NUMERIC when one of
+// the error bits is among them.
+void read_flags(Problem& P, hipStream_t s, int* out = nullptr) {
     int f[4];
     MBMD_HIP(hipMemcpyAsync(f, P.flags, sizeof(f), hipMemcpyDeviceToHost, s));
     MBMD_HIP(hipStreamSynchronize(s));
+    if (out) *out = f[0];
     if (f[0]) {
         launch_fill(1, reinterpret_cast<float*>(P.flags), 0.0f, s);
         MBMD_HIP(hipStreamSynchronize(s));
-        throw Error{MBMD_ERR_NUMERIC, "non-finite objective or step size"};
     }
+    if (f[0] & kFlagErrors) {
+        std::string what;
+        if (f[0] & MBMD_FLAG_NONFINITE) what += " non-finite objective or step size;";
+        if (f[0] & MBMD_FLAG_NO_CURVATURE) what += " no positive curvature along a nonzero direction;";
+        if (f[0] & MBMD_FLAG_ASCENT) what += " the direction was not a descent direction (g^T p > 0);";
+        throw Error{MBMD_ERR_NUMERIC, "numeric failure:" + what};
+    }
+}
+
+// Starts a run of iterations: the first objective of the run is checked against nothing.
+void begin_run(Problem& P, hipStream_t s) {
+    launch_fill_double(1, P.scal + S_PHI_PREV, std::nan(""), s);
 }
 
 void identity_iterate(Problem& P, float* x, int precond, int n_iter, double* trace_host, hipStream_t s) {
     const int nb = (P.ni + 255) / 256;
     const int total_slots = kRegions * kMaxPartials;
-    const int chunk_max = total_slots / nb - 1;
+    // A chunk of n iterations writes n + 1 rows of nb partials and, traced, n + 1
+    // trace slots (the device trace holds trace_cap + 1).
+    int chunk_max = total_slots / nb - 1;
+    if (trace_host) chunk_max = std::min(chunk_max, P.trace_cap);
     MBMD_REQUIRE(chunk_max >= 1, MBMD_ERR_SHAPE, "too many rays for the partial-sum buffer");
     int done = 0;
     do {
@@ -441,11 +517,17 @@ void identity_iterate(Problem& P, float* x, int precond, int n_iter, double* tra
                 if (it == n && done + n < n_iter) break;      // next chunk starts from this point
                 int counts[kRegions] = {0};
                 counts[R_PHI_L] = nb;
-                launch_reduce_final(P.partials + (size_t)it * nb, counts, P.scal, P.trace + it, 0, P.flags, s);
+                launch_reduce_final(P.partials + (size_t)it * nb, counts, P.scal, P.trace + it, RED_MONOTONE,
+                                    P.flags, s);
             }
             const int nvals = (done + n < n_iter) ? n : n + 1;
             MBMD_HIP(hipMemcpyAsync(trace_host + done, P.trace, sizeof(double) * nvals, hipMemcpyDeviceToHost, s));
             MBMD_HIP(hipStreamSynchronize(s));
+        } else if (done + n == n_iter) {
+            // the objective after the last iteration, for the numeric flags only
+            int counts[kRegions] = {0};
+            counts[R_PHI_L] = nb;
+            launch_reduce_final(P.partials + (size_t)n * nb, counts, P.scal, nullptr, RED_MONOTONE, P.flags, s);
         }
         done += n;
     } while (done < n_iter);
@@ -454,6 +536,7 @@ void identity_iterate(Problem& P, float* x, int precond, int n_iter, double* tra
 void sps_run(Problem& P, float* x, int precond, int n_iter, double* trace_host, hipStream_t s) {
     check_precond_ready(P, precond);
     P.last_stream = s;
+    begin_run(P, s);
     if (P.identity) {
         identity_iterate(P, x, precond, n_iter, trace_host, s);
         if (trace_host) read_flags(P, s);
@@ -518,6 +601,10 @@ const char* mbmd_status_string(int status) {
     }
 }
 
+int mbmd_cache_clear(void) {
+    return guarded([&] { clear_geometry_cache(); });
+}
+
 int mbmd_project(const mbmd_geometry* geom, const float* x_dev, float* sino_dev, int n_mat, void* stream) {
     return guarded([&] {
         MBMD_REQUIRE(geom && x_dev && sino_dev, MBMD_ERR_ARG, "NULL argument");
@@ -529,7 +616,7 @@ int mbmd_project(const mbmd_geometry* geom, const float* x_dev, float* sino_dev,
                                     hipMemcpyDeviceToDevice, s));
             return;
         }
-        launch_project(cached_geometry(*geom, kMaxMat, kMaxBackCh), x_dev, sino_dev, n_mat, s);
+        launch_project(cached_geometry(*geom, kMaxMat, kMaxBackCh, s), x_dev, sino_dev, n_mat, s);
     });
 }
 
@@ -544,7 +631,7 @@ int mbmd_backproject(const mbmd_geometry* geom, const float* sino_dev, float* x_
                                     hipMemcpyDeviceToDevice, s));
             return;
         }
-        launch_backproject(cached_geometry(*geom, kMaxMat, kMaxBackCh), sino_dev, x_dev, n_ch, s);
+        launch_backproject(cached_geometry(*geom, kMaxMat, kMaxBackCh, s), sino_dev, x_dev, n_ch, s);
     });
 }
 
@@ -556,36 +643,32 @@ int mbmd_projector_nnz(const mbmd_geometry* geom, long long* nnz_host, void* str
             *nnz_host = (long long)geom->nx * geom->ny;
             return;
         }
-        *nnz_host = count_nonzeros(cached_geometry(*geom, kMaxMat, kMaxBackCh), static_cast<hipStream_t>(stream));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        *nnz_host = count_nonzeros(cached_geometry(*geom, kMaxMat, kMaxBackCh, s), s);
+    });
+}
+
+int mbmd_workspace_bytes(const mbmd_geometry* geom, const mbmd_spectral* sp, int flags, size_t* bytes) {
+    return guarded([&] {
+        MBMD_REQUIRE(geom && sp && bytes, MBMD_ERR_ARG, "NULL argument");
+        Problem P;
+        size_problem(P, *geom, *sp, flags);
+        *bytes = problem_bytes(P);
     });
 }
 
 int mbmd_problem_create(const mbmd_geometry* geom, const mbmd_spectral* sp, const mbmd_penalty* pen,
-                        const float* y_dev, const float* w_dev, void* stream, mbmd_problem** out) {
+                        const float* y_dev, const float* w_dev, void* workspace_dev, size_t workspace_bytes,
+                        int flags, void* stream, mbmd_problem** out) {
     return guarded([&] {
         MBMD_REQUIRE(geom && sp && pen && y_dev && out, MBMD_ERR_ARG, "NULL argument");
         *out = nullptr;
-        validate_geometry(*geom);
-        MBMD_REQUIRE(sp->n_mat >= 1 && sp->n_mat <= kMaxMat && sp->n_chan >= 1 && sp->n_chan <= kMaxChan &&
-                         sp->n_energy >= 1 && sp->n_energy <= kMaxEnergy,
-                     MBMD_ERR_SHAPE, "spectral sizes out of range (n_mat<=4, n_chan<=8, n_energy<=256)");
         MBMD_REQUIRE(sp->Q_host && sp->S_host, MBMD_ERR_ARG, "NULL spectral table");
         MBMD_REQUIRE(pen->kind == MBMD_PENALTY_QUADRATIC || pen->kind == MBMD_PENALTY_HUBER, MBMD_ERR_ARG,
                      "unknown penalty kind");
         std::unique_ptr<mbmd_problem> P(new mbmd_problem());
         hipStream_t s = static_cast<hipStream_t>(stream);
-        P->g = *geom;
-        P->identity = geom->kind == MBMD_GEOM_IDENTITY;
-        P->K = sp->n_mat;
-        P->E = sp->n_energy;
-        P->C = sp->n_chan;
-        P->npk = P->K * (P->K + 1) / 2;
-        P->nx = geom->nx;
-        P->ny = geom->ny;
-        P->V = geom->n_views;
-        P->B = geom->n_bins;
-        P->nj = geom->nx * geom->ny;
-        P->ni = geom->n_views * geom->n_bins;
+        size_problem(*P, *geom, *sp, flags);
         P->pen_kind = pen->kind;
         P->delta = pen->delta;
         for (int i = 0; i < P->K * P->K; ++i) P->beta[i] = pen->beta_host ? pen->beta_host[i] : 0.0;
@@ -595,15 +678,21 @@ int mbmd_problem_create(const mbmd_geometry* geom, const mbmd_spectral* sp, cons
         for (int i = 0; i < P->K * P->K; ++i) P->has_penalty |= P->beta[i] != 0.0;
         if (pen->kind == MBMD_PENALTY_HUBER)
             MBMD_REQUIRE(P->K == 1 && pen->delta > 0.0, MBMD_ERR_ARG, "Huber needs one material and delta > 0");
-        MBMD_REQUIRE(P->ni <= 256 * kMaxPartials && P->nj <= 256 * kMaxPartials, MBMD_ERR_SHAPE,
-                     "problem too large for the partial-sum buffer");
+        GeomHost gh;
+        if (!P->identity) build_geometry_host(*geom, gh);      // FP64 on the host, before any device work
+        const size_t need = problem_bytes(*P);
+        if (workspace_dev) {
+            MBMD_REQUIRE(workspace_bytes >= need, MBMD_ERR_ARG,
+                         "workspace smaller than mbmd_workspace_bytes reports");
+            P->arena.adopt(workspace_dev, workspace_bytes);
+        } else {
+            P->arena.reserve(need);
+        }
+        carve(*P);
         if (!P->identity) {
             P->geom = new GeomTables();
-            build_geometry(*geom, *P->geom, P->K, std::max(P->npk, 2 * P->K));
+            place_geometry(*geom, gh, *P->geom, P->geom_mem, P->K, problem_back_ch(*P), s);
         }
-        carve(*P);                                // sizing pass
-        P->arena.reserve(P->arena.used + 4096);
-        carve(*P);
         // spectral model
         const int K = P->K, E = P->E, C = P->C;
         std::vector<float> Qf(E * K), Sf(C * E), rowS(C, 0.0f), Qsum(E, 0.0f), bf(K * K);
@@ -646,7 +735,7 @@ int mbmd_problem_create(const mbmd_geometry* geom, const mbmd_spectral* sp, cons
             fill_twiddles(P->tw_x, P->nx, s);
             fill_twiddles(P->tw_y, P->ny, s);
         }
-        MBMD_HIP(hipStreamSynchronize(s));
+        MBMD_HIP(hipStreamSynchronize(s));        // the host tables and spectra go out of scope
         P->last_stream = s;
         *out = P.release();
     });
@@ -657,11 +746,17 @@ void mbmd_problem_destroy(mbmd_problem* prob) {
     (void)hipStreamSynchronize(prob->last_stream);
     prob->arena.release();
     prob->blur_arena.release();
-    if (prob->geom) {
-        free_geometry(*prob->geom);
-        delete prob->geom;
-    }
+    delete prob->geom;                 // its memory was part of the arena
     delete prob;
+}
+
+int mbmd_problem_check(mbmd_problem* prob, int* flags_host, void* stream) {
+    return guarded([&] {
+        MBMD_REQUIRE(prob != nullptr, MBMD_ERR_ARG, "NULL problem");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        prob->last_stream = s;
+        read_flags(*prob, s, flags_host);
+    });
 }
 
 int mbmd_problem_set_blur(mbmd_problem* prob, const float* taps_host, int half_width, void* stream) {
@@ -686,18 +781,14 @@ int mbmd_problem_set_blur(mbmd_problem* prob, const float* taps_host, int half_w
         }
         hipStream_t s = static_cast<hipStream_t>(stream);
         P.last_stream = s;
-        if (b.h > 0 && P.blur_arena.base == nullptr) {
+        if (b.h > 0 && P.wb == nullptr) {
+            // sized without room for a blur: library memory may grow, a caller's workspace may not
+            MBMD_REQUIRE(P.arena.owned, MBMD_ERR_UNSUPPORTED,
+                         "the problem's workspace was sized without MBMD_WORKSPACE_BLUR");
             Arena& A = P.blur_arena;
-            const size_t ni = P.ni, C = P.C, K = P.K;
-            auto carve_blur = [&] {
-                P.wb = A.take<float>(C * ni);
-                P.J = A.take<float>(C * K * ni);
-                P.btmp0 = A.take<float>(C * ni);
-                P.btmp1 = A.take<float>(C * ni);
-            };
-            carve_blur();                                   // sizing pass
-            A.reserve(A.used + 4096);
-            carve_blur();
+            carve_blur(P, A);                               // sizing pass
+            A.reserve(A.used);
+            carve_blur(P, A);
         }
         if (b.h > 0) {                                      // wb = B^T (w B 1)
             launch_fill(P.C * P.ni, P.btmp0, 1.0f, s);
@@ -778,7 +869,7 @@ int mbmd_gradient(mbmd_problem* prob, const float* x_dev, float* grad_dev, float
         if (objective_host) {
             launch_reduce_final(P.partials, counts, P.scal, nullptr, 0, P.flags, s);
             MBMD_HIP(hipMemcpyAsync(objective_host, P.scal + S_PHI, sizeof(double), hipMemcpyDeviceToHost, s));
-            MBMD_HIP(hipStreamSynchronize(s));
+            read_flags(P, s);
         }
     });
 }
@@ -865,6 +956,7 @@ int mbmd_batch_sps_step(mbmd_batch* b, float* const* x_dev, int precond, int n_i
             MBMD_REQUIRE(x_dev[i] != nullptr, MBMD_ERR_ARG, "NULL image in batch");
             check_precond_ready(*b->probs[i], precond);
             b->probs[i]->last_stream = s;
+            begin_run(*b->probs[i], s);
             if (precond == MBMD_PRECOND_NONE) ensure_dL_const(*b->probs[i], s);
         }
         // one slice iteration on its branch stream

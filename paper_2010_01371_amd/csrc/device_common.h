@@ -148,23 +148,31 @@ __device__ __forceinline__ void region_sums(const double* partials, const Counts
 }
 
 // The scalars formed from the region sums (sh as left by region_sums):
-// phi = PHI_L + PHI_R and, with mode bit 1, the step alpha = -GP / (CQ2 + PRP)
+// phi = PHI_L + PHI_R and, with mode RED_STEP, the step alpha = -GP / (CQ2 + PRP)
 // (0 when the denominator is not positive or alpha is not finite).  With write,
-// stores them to scal (and phi to trace_slot) and raises flags[0] when phi or
-// alpha is not finite.  Returns alpha (0 without mode bit 1).
+// stores them to scal (and phi to trace_slot) and raises numeric flags in
+// flags[0]: MBMD_FLAG_NONFINITE when phi or alpha is not finite,
+// MBMD_FLAG_NO_CURVATURE when the denominator is not positive for a nonzero
+// g^T p, MBMD_FLAG_ASCENT when alpha < 0 (g^T p > 0: M M^T not positive
+// semi-definite), and with mode RED_MONOTONE MBMD_FLAG_INCREASE when phi
+// exceeds the previous objective of the run (scal[S_PHI_PREV], NaN at its
+// start) by more than kIncreaseTol relative; phi then replaces it.  Returns
+// alpha (0 without RED_STEP).
 __device__ __forceinline__ double form_scalars(const double* sh, int mode, double* scal, double* trace_slot,
                                                int* flags, bool write) {
     double sums[kRegions];
     for (int k = 0; k < kRegions; ++k) sums[k] = sh[2 * k] + sh[2 * k + 1];
     const double phi = sums[R_PHI_L] + sums[R_PHI_R];
-    bool bad = !isfinite(phi);
+    int bits = isfinite(phi) ? 0 : MBMD_FLAG_NONFINITE;
     double alpha_out = 0.0;
-    if (mode & 1) {
+    if (mode & RED_STEP) {
         const double gp = sums[R_GP];
         const double den = sums[R_CQ2] + sums[R_PRP];
         const double alpha = den > 0.0 ? -gp / den : 0.0;
         alpha_out = isfinite(alpha) ? alpha : 0.0;
-        bad = bad || !isfinite(alpha);
+        if (!isfinite(alpha) || !isfinite(gp) || !isfinite(den)) bits |= MBMD_FLAG_NONFINITE;
+        else if (!(den > 0.0) && gp != 0.0) bits |= MBMD_FLAG_NO_CURVATURE;
+        else if (alpha < 0.0) bits |= MBMD_FLAG_ASCENT;
         if (write) {
             scal[S_GP] = gp;
             scal[S_DEN] = den;
@@ -172,9 +180,14 @@ __device__ __forceinline__ double form_scalars(const double* sh, int mode, doubl
         }
     }
     if (write) {
+        if (mode & RED_MONOTONE) {
+            const double prev = scal[S_PHI_PREV];
+            if (isfinite(prev) && phi > prev + kIncreaseTol * fabs(prev)) bits |= MBMD_FLAG_INCREASE;
+            scal[S_PHI_PREV] = phi;
+        }
         scal[S_PHI] = phi;
         if (trace_slot) *trace_slot = phi;
-        if (bad && flags) flags[0] = 1;
+        if (bits && flags) flags[0] |= bits;
     }
     return alpha_out;
 }

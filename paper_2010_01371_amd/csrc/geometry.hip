@@ -60,20 +60,19 @@ Ray boundary_ray(const mbmd_geometry& g, double c, double s, double u) {
 
 }  // namespace
 
-void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int back_ch) {
+void build_geometry_host(const mbmd_geometry& g, GeomHost& h) {
     validate_geometry(g);
     MBMD_REQUIRE(g.kind != MBMD_GEOM_IDENTITY, MBMD_ERR_ARG, "identity geometry has no projector tables");
-    t.g = g;
-    t.V = g.n_views;
-    t.B = g.n_bins;
-    t.nx = g.nx;
-    t.ny = g.ny;
-    const int V = t.V, B = t.B;
-    std::vector<ViewParams> vp(V);
-    std::vector<float2> bound((size_t)V * (B + 1));
+    const int V = g.n_views, B = g.n_bins;
+    std::vector<ViewParams>& vp = h.vp;
+    vp.assign(V, ViewParams{});
+    std::vector<float2>& bound = h.bound;
+    bound.assign((size_t)V * (B + 1), make_float2(0.f, 0.f));
     const int QL = g.nx > g.ny ? g.nx : g.ny;
-    std::vector<float4> line((size_t)QL * V * 2, make_float4(0.f, 0.f, 0.f, 0.f));
-    std::vector<float> path((size_t)V * B);
+    std::vector<float4>& line = h.line;
+    line.assign((size_t)QL * V * 2, make_float4(0.f, 0.f, 0.f, 0.f));
+    std::vector<float>& path = h.path;
+    path.assign((size_t)V * B, 0.0f);
     std::vector<int> views[2];
 
     // Per-view tables are stored in "slot" order: the views sweeping rows first,
@@ -85,7 +84,8 @@ void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int b
         frame_of[v] = frame;
         views[frame].push_back(v);
     }
-    std::vector<int> fv(views[0]);
+    std::vector<int>& fv = h.fv;
+    fv = views[0];
     fv.insert(fv.end(), views[1].begin(), views[1].end());
     for (int slot = 0; slot < V; ++slot) {
         const int v = fv[slot];
@@ -193,14 +193,15 @@ void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int b
         p.view_frame = v | (frame << 16);
         vp[slot] = p;
     }
-    t.n_frame_views[0] = (int)views[0].size();
-    t.n_frame_views[1] = (int)views[1].size();
+    h.n_frame_views[0] = (int)views[0].size();
+    h.n_frame_views[1] = (int)views[1].size();
 
     // Forward items of each frame in order of decreasing work: the active lines
     // of the item's half, summed over its wavefronts, from the same hull the
     // kernel computes.  Dispatching the heaviest first balances the CUs (the
     // fan is usually wider than the image, so many items have no lines at all).
-    std::vector<int> order;
+    std::vector<int>& order = h.order;
+    order.clear();
     {
         const int chunks = fwd_chunks(B);
         for (int f = 0; f < 2; ++f) {
@@ -229,39 +230,100 @@ void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int b
         }
     }
 
-    const size_t nj = (size_t)g.nx * g.ny;
-    t.prefix_mat = prefix_mat;
-    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-    const size_t b_view = al(sizeof(ViewParams) * V), b_bound = al(sizeof(float2) * bound.size()),
-                 b_path = al(sizeof(float) * path.size()), b_fv = al(sizeof(int) * V),
-                 b_pre = al(sizeof(float) * prefix_elems(g.nx, g.ny) * prefix_mat),
-                 b_line = al(sizeof(float4) * line.size()), b_ord = al(sizeof(int) * order.size()),
-                 b_det = al(sizeof(DetEntry) * (size_t)back_ch * V * det_row(B)),
-                 b_tmp = al(sizeof(float) * (size_t)back_ch * nj);
-    t.back_ch = back_ch;
-    char* base = nullptr;
-    MBMD_HIP(hipGetDevice(&t.device));
+}
+
+namespace {
+size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+}  // namespace
+
+// Byte layout of a geometry's device block: tables, then the scratch of the
+// forward (line prefixes) and of the back projection (detector rows, column part).
+struct GeomLayout {
+    size_t view, bound, path, fv, pre, line, order, det, part;
+    size_t total() const { return view + bound + path + fv + pre + line + order + det + part; }
+};
+
+static GeomLayout layout_of(const mbmd_geometry& g, int prefix_mat, int back_ch) {
+    const size_t V = g.n_views, B = g.n_bins, nj = (size_t)g.nx * g.ny;
+    const size_t QL = g.nx > g.ny ? g.nx : g.ny;
+    GeomLayout L;
+    L.view = al256(sizeof(ViewParams) * V);
+    L.bound = al256(sizeof(float2) * V * (B + 1));
+    L.path = al256(sizeof(float) * V * B);
+    L.fv = al256(sizeof(int) * V);
+    L.pre = al256(sizeof(float) * prefix_elems(g.nx, g.ny) * prefix_mat);
+    L.line = back_ch ? al256(sizeof(float4) * QL * V * 2) : 0;   // the back projector's per-line maps
+    L.order = al256(sizeof(int) * V * fwd_chunks((int)B) * 2);
+    L.det = al256(sizeof(DetEntry) * (size_t)back_ch * V * det_row((int)B));
+    L.part = al256(sizeof(float) * (size_t)back_ch * nj);
+    return L;
+}
+
+size_t geometry_bytes(const mbmd_geometry& g, int prefix_mat, int back_ch) {
+    return layout_of(g, prefix_mat, back_ch).total();
+}
+
+void place_geometry(const mbmd_geometry& g, const GeomHost& h, GeomTables& t, char* base, int prefix_mat,
+                    int back_ch, hipStream_t s) {
+    t.g = g;
+    t.V = g.n_views;
+    t.B = g.n_bins;
+    t.nx = g.nx;
+    t.ny = g.ny;
+    t.n_frame_views[0] = h.n_frame_views[0];
+    t.n_frame_views[1] = h.n_frame_views[1];
+    const GeomLayout L = layout_of(g, prefix_mat, back_ch);
+    MBMD_REQUIRE(h.order.size() * sizeof(int) <= L.order, MBMD_ERR_ARG, "forward item table larger than its layout");
     // the back projector addresses the detector prefix with 32-bit buffer offsets
-    MBMD_REQUIRE(b_det < (size_t(1) << 31), MBMD_ERR_SHAPE, "too many views x bins x channels for a back projection");
-    MBMD_HIP(hipMalloc(&base, b_view + b_bound + b_path + b_fv + b_pre + b_line + b_ord + b_det + b_tmp));
+    MBMD_REQUIRE(L.det < (size_t(1) << 31), MBMD_ERR_SHAPE, "too many views x bins x channels for a back projection");
+    MBMD_REQUIRE((reinterpret_cast<uintptr_t>(base) & 255) == 0, MBMD_ERR_ARG, "geometry memory must be 256-byte aligned");
+    MBMD_HIP(hipGetDevice(&t.device));
+    t.prefix_mat = prefix_mat;
+    t.back_ch = back_ch;
+    t.back_line_q = g.nx > g.ny ? g.nx : g.ny;
+    char* p = base;
+    t.view = reinterpret_cast<ViewParams*>(p);
+    p += L.view;
+    t.bound = reinterpret_cast<float2*>(p);
+    p += L.bound;
+    t.path = reinterpret_cast<float*>(p);
+    p += L.path;
+    t.frame_views = reinterpret_cast<int*>(p);
+    p += L.fv;
+    t.prefix = prefix_mat ? reinterpret_cast<float*>(p) : nullptr;
+    p += L.pre;
+    t.back_line = back_ch ? reinterpret_cast<float4*>(p) : nullptr;
+    p += L.line;
+    t.fwd_order = reinterpret_cast<int*>(p);
+    p += L.order;
+    t.det_prefix = back_ch ? reinterpret_cast<DetEntry*>(p) : nullptr;
+    p += L.det;
+    t.back_part = back_ch ? reinterpret_cast<float*>(p) : nullptr;
+    for (int i = 0; i <= kMaxBackCh; ++i) t.back_variant[i] = -1;
+    // stream-ordered uploads; the caller keeps h alive until the stream has run them
+    MBMD_HIP(hipMemcpyAsync(t.view, h.vp.data(), sizeof(ViewParams) * h.vp.size(), hipMemcpyHostToDevice, s));
+    MBMD_HIP(hipMemcpyAsync(t.bound, h.bound.data(), sizeof(float2) * h.bound.size(), hipMemcpyHostToDevice, s));
+    MBMD_HIP(hipMemcpyAsync(t.path, h.path.data(), sizeof(float) * h.path.size(), hipMemcpyHostToDevice, s));
+    MBMD_HIP(hipMemcpyAsync(t.frame_views, h.fv.data(), sizeof(int) * h.fv.size(), hipMemcpyHostToDevice, s));
+    if (back_ch)
+        MBMD_HIP(hipMemcpyAsync(t.back_line, h.line.data(), sizeof(float4) * h.line.size(), hipMemcpyHostToDevice, s));
+    MBMD_HIP(hipMemcpyAsync(t.fwd_order, h.order.data(), sizeof(int) * h.order.size(), hipMemcpyHostToDevice, s));
+}
+
+void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int back_ch) {
+    GeomHost h;
+    build_geometry_host(g, h);
+    char* base = nullptr;
+    MBMD_HIP(hipMalloc(&base, geometry_bytes(g, prefix_mat, back_ch)));
     t.mem = base;
-    t.view = reinterpret_cast<ViewParams*>(base);
-    t.bound = reinterpret_cast<float2*>(base + b_view);
-    t.path = reinterpret_cast<float*>(base + b_view + b_bound);
-    t.frame_views = reinterpret_cast<int*>(base + b_view + b_bound + b_path);
-    t.prefix = prefix_mat ? reinterpret_cast<float*>(base + b_view + b_bound + b_path + b_fv) : nullptr;
-    t.back_line = reinterpret_cast<float4*>(base + b_view + b_bound + b_path + b_fv + b_pre);
-    t.back_line_q = QL;
-    t.fwd_order = reinterpret_cast<int*>(base + b_view + b_bound + b_path + b_fv + b_pre + b_line);
-    char* after_pre = base + b_view + b_bound + b_path + b_fv + b_pre + b_line + b_ord;
-    t.det_prefix = back_ch ? reinterpret_cast<DetEntry*>(after_pre) : nullptr;
-    t.back_part = back_ch ? reinterpret_cast<float*>(after_pre + b_det) : nullptr;
-    MBMD_HIP(hipMemcpy(t.view, vp.data(), sizeof(ViewParams) * V, hipMemcpyHostToDevice));
-    MBMD_HIP(hipMemcpy(t.bound, bound.data(), sizeof(float2) * bound.size(), hipMemcpyHostToDevice));
-    MBMD_HIP(hipMemcpy(t.path, path.data(), sizeof(float) * path.size(), hipMemcpyHostToDevice));
-    MBMD_HIP(hipMemcpy(t.frame_views, fv.data(), sizeof(int) * V, hipMemcpyHostToDevice));
-    MBMD_HIP(hipMemcpy(t.back_line, line.data(), sizeof(float4) * line.size(), hipMemcpyHostToDevice));
-    MBMD_HIP(hipMemcpy(t.fwd_order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice));
+    try {
+        place_geometry(g, h, t, base, prefix_mat, back_ch, nullptr);
+        MBMD_HIP(hipStreamSynchronize(nullptr));        // h goes out of scope
+    } catch (...) {
+        (void)hipFree(base);
+        t.mem = nullptr;
+        throw;
+    }
 }
 
 void free_geometry(GeomTables& t) {
@@ -270,27 +332,49 @@ void free_geometry(GeomTables& t) {
 }
 
 namespace {
+// Cached tables of the standalone projector calls, one entry per (geometry,
+// device, stream): every stream has its own scratch, so calls on different
+// streams do not race.  At most kCacheEntries entries; the least recently used
+// one is freed first (hipFree waits for the device).
+constexpr size_t kCacheEntries = 16;
+struct CacheEntry {
+    GeomTables* t;
+    unsigned long long last_use;
+};
 std::mutex g_cache_mu;
-std::map<std::string, GeomTables*> g_cache;
-}
+std::map<std::string, CacheEntry> g_cache;
+unsigned long long g_cache_clock = 0;
+}  // namespace
 
-GeomTables& cached_geometry(const mbmd_geometry& g, int prefix_mat, int back_ch) {
+GeomTables& cached_geometry(const mbmd_geometry& g, int prefix_mat, int back_ch, hipStream_t s) {
     int dev = 0;
     MBMD_HIP(hipGetDevice(&dev));
-    // key from the fields (the struct has padding bytes)
+    // key from the fields (the struct has padding bytes), the device and the stream
     const double f[] = {(double)g.kind, (double)g.nx, (double)g.ny, g.dx, g.dy, (double)g.n_views,
                         g.theta0, g.dtheta, (double)g.n_bins, g.du, g.u_offset, g.dso, g.dsd,
                         (double)dev};
+    const uintptr_t sid = reinterpret_cast<uintptr_t>(s);
     std::string key(reinterpret_cast<const char*>(f), sizeof(f));
+    key.append(reinterpret_cast<const char*>(&sid), sizeof(sid));
     std::lock_guard<std::mutex> lock(g_cache_mu);
     auto it = g_cache.find(key);
-    if (it != g_cache.end() && it->second->prefix_mat >= prefix_mat && it->second->back_ch >= back_ch)
-        return *it->second;
+    if (it != g_cache.end() && it->second.t->prefix_mat >= prefix_mat && it->second.t->back_ch >= back_ch) {
+        it->second.last_use = ++g_cache_clock;
+        return *it->second.t;
+    }
     if (it != g_cache.end()) {
-        // a larger prefix scratch is needed: rebuild (hipFree waits for the device)
-        free_geometry(*it->second);
-        delete it->second;
+        // a larger scratch is needed: rebuild
+        free_geometry(*it->second.t);
+        delete it->second.t;
         g_cache.erase(it);
+    }
+    while (g_cache.size() >= kCacheEntries) {
+        auto old = g_cache.begin();
+        for (auto e = g_cache.begin(); e != g_cache.end(); ++e)
+            if (e->second.last_use < old->second.last_use) old = e;
+        free_geometry(*old->second.t);
+        delete old->second.t;
+        g_cache.erase(old);
     }
     GeomTables* t = new GeomTables();
     try {
@@ -299,8 +383,17 @@ GeomTables& cached_geometry(const mbmd_geometry& g, int prefix_mat, int back_ch)
         delete t;
         throw;
     }
-    g_cache[key] = t;
+    g_cache[key] = CacheEntry{t, ++g_cache_clock};
     return *t;
+}
+
+void clear_geometry_cache() {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    for (auto& e : g_cache) {
+        free_geometry(*e.second.t);
+        delete e.second.t;
+    }
+    g_cache.clear();
 }
 
 }  // namespace mbmd

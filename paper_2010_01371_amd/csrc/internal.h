@@ -79,16 +79,20 @@ class KernelTimer {
 };
 
 // ---------------------------------------------------------------- device memory arena
+// Parts are 256-byte aligned offsets from base.  A null base is a sizing pass:
+// take() only counts.  The memory is the library's (reserve, freed by release)
+// or the caller's (adopt: release forgets it).
 struct Arena {
     char* base = nullptr;
     size_t size = 0, used = 0;
-    std::vector<std::pair<size_t, size_t>> plan;   // unused, kept for symmetry
+    bool owned = false;
     void reserve(size_t bytes);
+    void adopt(void* mem, size_t bytes);
     template <class T> T* take(size_t n) {
         size_t off = (used + 255) & ~size_t(255);
         used = off + n * sizeof(T);
         if (base == nullptr) return nullptr;     // sizing pass
-        if (used > size) throw Error{MBMD_ERR_HIP, "arena overflow"};
+        if (used > size) throw Error{MBMD_ERR_ARG, "workspace too small"};
         return reinterpret_cast<T*>(base + off);
     }
     void release();
@@ -219,11 +223,31 @@ __host__ __device__ inline void active_lines(float2 bf, float2 bl, int Np, int N
 __host__ __device__ inline int back_shift(int B) { return (B + 1) / 2; }
 inline size_t prefix_elems(int nx, int ny) { return (size_t)ny * prefix_row(nx) + (size_t)nx * prefix_row(ny); }
 
-// Builds the tables in FP64 on the host and uploads them (synchronous copy).
+// Host copy of a geometry's tables, built in FP64 and stored in FP32.
+struct GeomHost {
+    std::vector<ViewParams> vp;
+    std::vector<float2> bound;
+    std::vector<float> path;
+    std::vector<int> fv;
+    std::vector<float4> line;
+    std::vector<int> order;
+    int n_frame_views[2] = {0, 0};
+};
+void build_geometry_host(const mbmd_geometry& g, GeomHost& h);
+// Device bytes of the tables and scratch of a geometry (256-byte aligned parts);
+// back_ch = 0 leaves out everything the back projection needs.
+size_t geometry_bytes(const mbmd_geometry& g, int prefix_mat, int back_ch);
+// Points t into base (geometry_bytes(g, ...) bytes, 256-byte aligned, not owned
+// by t) and enqueues the uploads of h on s; h must outlive them.
+void place_geometry(const mbmd_geometry& g, const GeomHost& h, GeomTables& t, char* base, int prefix_mat,
+                    int back_ch, hipStream_t s);
+// Builds the tables into memory of its own (t.mem, freed by free_geometry).
 void build_geometry(const mbmd_geometry& g, GeomTables& t, int prefix_mat, int back_ch);
 void free_geometry(GeomTables& t);
 void validate_geometry(const mbmd_geometry& g);
-GeomTables& cached_geometry(const mbmd_geometry& g, int prefix_mat, int back_ch);
+// Tables and scratch of the standalone projector calls, per geometry, device and stream.
+GeomTables& cached_geometry(const mbmd_geometry& g, int prefix_mat, int back_ch, hipStream_t s);
+void clear_geometry_cache();
 
 // ---------------------------------------------------------------- projector launches
 void launch_project(const GeomTables& t, const float* x, float* sino, int n_mat, hipStream_t s);
@@ -265,7 +289,10 @@ const float* launch_back_kernel(const GeomTables& t, float* x, int n_ch, hipStre
 // ---------------------------------------------------------------- problem
 struct Problem {
     mbmd_geometry g{};
-    GeomTables* geom = nullptr;      // owned (projector geometries only)
+    GeomTables* geom = nullptr;      // owned (projector geometries only); memory in the arena
+    char* geom_mem = nullptr;        // the geometry's part of the arena
+    size_t geom_bytes = 0;
+    int ws_flags = 0;                // mbmd_workspace_flags the arena was sized with
     int identity = 0;
     int K = 1, E = 1, C = 1, npk = 1;
     int nx = 0, ny = 0, V = 0, B = 0;
@@ -324,7 +351,17 @@ struct Problem {
 
 // Reduction regions and scalar slots.
 enum { R_PHI_L = 0, R_PHI_R, R_GP, R_CQ2, R_PRP, R_AUX, kRegions };
-enum { S_ALPHA = 0, S_PHI, S_GP, S_DEN, S_LMAX, S_AUX, S_COUNT, kScalars = 16 };
+// S_PHI_PREV: the objective of the previous evaluation of a run (NaN at its
+// start), against which the next one is checked for an increase.
+enum { S_ALPHA = 0, S_PHI, S_GP, S_DEN, S_LMAX, S_PHI_PREV, kScalars = 16 };
+// Bits of the problem's numeric flags (flags[0] on the device): the mbmd_numeric_flags.
+constexpr int kFlagErrors = MBMD_FLAG_NONFINITE | MBMD_FLAG_NO_CURVATURE | MBMD_FLAG_ASCENT;
+// Reduction modes of launch_reduce_final: form the step size; check the
+// objective against S_PHI_PREV (raising MBMD_FLAG_INCREASE) and replace it.
+enum { RED_STEP = 1, RED_MONOTONE = 2 };
+// Relative rise of the objective between consecutive evaluations that raises
+// MBMD_FLAG_INCREASE (well above the FP32 evaluation noise of about 1e-6).
+constexpr double kIncreaseTol = 1e-5;
 
 // ---------------------------------------------------------------- ray (per detector element) passes
 struct RayArgs {

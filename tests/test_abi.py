@@ -53,3 +53,28 @@ def test_binding_has_no_cpu_fallback():
             text = open(os.path.join(pkg, f)).read()
             assert "oracle" not in text.replace("the oracle", ""), f
             assert "workloads" not in text, f
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmbmd.so not built (run __graft_entry__.build())")
+def test_workspace_bytes_without_a_gpu():
+    """mbmd_workspace_bytes is host arithmetic: it sizes a problem's device block
+    (geometry tables, state, scratch), grows with the blur's room, and rejects
+    unknown flags and bad sizes, all without touching a device."""
+    import numpy as np
+    from paper_2010_01371_amd import api, _lib
+    from workloads import configs as C
+    wl = C.make_small_fan(n=32, views=48, bins=64)
+    n0 = api.workspace_bytes(wl.geom, wl.Q, wl.S)
+    n1 = api.workspace_bytes(wl.geom, wl.Q, wl.S, flags=api.WORKSPACE_BLUR)
+    V, B = wl.geom["n_views"], wl.geom["n_bins"]
+    assert n1 - n0 >= 4 * 4 * V * B                      # (3 + n_mat) n_chan rays floats
+    assert n0 > 8 * 6 * 16384                              # the FP64 partial sums alone
+    g2 = dict(wl.geom, nx=64, ny=64)
+    assert api.workspace_bytes(g2, wl.Q, wl.S) > n0
+    with pytest.raises(_lib.MbmdError):
+        api.workspace_bytes(wl.geom, wl.Q, wl.S, flags=4)
+    with pytest.raises(_lib.MbmdError):
+        api.workspace_bytes(dict(wl.geom, nx=0), wl.Q, wl.S)
+    Q5 = np.ones((3, 5))
+    with pytest.raises(_lib.MbmdError):
+        api.workspace_bytes(wl.geom, Q5, np.ones((1, 3)))    # five materials
