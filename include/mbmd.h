@@ -189,6 +189,27 @@ int mbmd_project(const mbmd_geometry* geom, const float* x_dev, float* sino_dev,
 int mbmd_backproject(const mbmd_geometry* geom, const float* sino_dev, float* x_dev,
                      int n_ch, void* stream);
 
+/* Device bytes of the allocation-free projector's array (per device). */
+#define MBMD_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/*
+ * mbmd_project for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.  Same
+ * arguments, result and errors as mbmd_project (bit for bit the same kernels),
+ * but the projector's tables and line-prefix scratch live in a static device
+ * array of MBMD_NOALLOC_SCRATCH_BYTES per device, held until the process ends;
+ * the call allocates no device memory.  The array keeps the tables of the last
+ * geometry used on the device: a call with another geometry builds that
+ * geometry's tables on the host, waits for the device and uploads them
+ * (so it is not capturable); later calls with the same geometry only enqueue
+ * two kernels on `stream`.  Every call on a device shares its array: calls
+ * that overlap on one device race.
+ * Errors: those of mbmd_project, and MBMD_ERR_SHAPE when the geometry's tables
+ * and scratch (for up to 4 materials) exceed the array.
+ */
+int mbmd_project_noalloc(const mbmd_geometry* geom, const float* x_dev, float* sino_dev,
+                         int n_mat, void* stream);
+
 /*
  * Number of nonzeros of A (pairs of a ray and a pixel with a positive
  * footprint overlap), counted on the device from the projector's own tables;

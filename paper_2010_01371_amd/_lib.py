@@ -36,6 +36,7 @@ _SIGNATURES = {
     "mbmd_status_string": (ctypes.c_char_p, [c_int]),
     "mbmd_project": (c_int, [P(Geometry), c_void_p, c_void_p, c_int, c_void_p]),
     "mbmd_backproject": (c_int, [P(Geometry), c_void_p, c_void_p, c_int, c_void_p]),
+    "mbmd_project_noalloc": (c_int, [P(Geometry), c_void_p, c_void_p, c_int, c_void_p]),
     "mbmd_workspace_bytes": (c_int, [P(Geometry), P(Spectral), c_int, P(c_size_t)]),
     "mbmd_problem_create": (c_int, [P(Geometry), P(Spectral), P(Penalty), c_void_p, c_void_p, c_void_p,
                                     c_size_t, c_int, c_void_p, P(c_void_p)]),
