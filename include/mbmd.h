@@ -400,10 +400,9 @@ int mbmd_forward_vjp(mbmd_problem* prob, const float* l_dev, const float* gbar_d
 /*
  * Group problems (uneven sizes allowed, all on the current device) for a
  * batched iteration.  The problems are borrowed and must outlive the batch.
- * Problems with the same geometry share projector tables and scratch, so
- * they run in order; problems with different geometries run concurrently on
- * up to 4 library-owned streams (default priority) forked from the caller's
- * stream and joined back into it.  Errors: MBMD_ERR_ARG, MBMD_ERR_UNSUPPORTED
+ * Every problem has its own tables and scratch, so the problems are
+ * independent: they are dealt round-robin onto up to 4 library-owned streams
+ * (default priority) forked from the caller's stream and joined back into it.  Errors: MBMD_ERR_ARG, MBMD_ERR_UNSUPPORTED
  * (identity geometry), MBMD_ERR_HIP (stream or event creation).
  */
 int mbmd_batch_create(mbmd_problem* const* probs, int n, mbmd_batch** out);

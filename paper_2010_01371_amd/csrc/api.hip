@@ -19,11 +19,12 @@
 
 struct mbmd_problem : public mbmd::Problem {};
 
-// Problems that share projector tables (same geometry) share their scratch
-// buffers, so they run in order on one stream; different geometries run on
-// different library-owned streams (at most kBatchStreams) forked from and
-// joined back into the caller's stream -- or, captured, as parallel branches
-// of one graph per iteration.
+// Every problem owns its tables and scratch, so the problems of a batch are
+// independent: they are dealt round-robin onto library-owned streams (at most
+// kBatchStreams) forked from and joined back into the caller's stream -- or,
+// captured, as parallel branches of one graph per iteration.  (Problems that
+// shared tables would run in order on one stream: the grouping is by table
+// pointer.)
 constexpr int kBatchStreams = 4;
 struct mbmd_batch {
     std::vector<mbmd_problem*> probs;
