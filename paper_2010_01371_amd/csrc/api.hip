@@ -416,14 +416,6 @@ void plain_iteration(Problem& P, float* x, double* trace_slot, hipStream_t s) {
     launch_reduce_final(P.partials, counts, P.scal, trace_slot, RED_MONOTONE, P.flags, s);
 }
 
-// MBMD_FUSE_ROWS=0 in the environment (read on every iteration) keeps the
-// gradient launch and the detector prefix apart (a testing hook: both ways give
-// the same iterates).
-bool fuse_rows_enabled() {
-    const char* e = std::getenv("MBMD_FUSE_ROWS");
-    return !(e && e[0] == '0');
-}
-
 // One preconditioned iteration.  On entry l = A x up to the step the previous
 // iteration left pending in alpha (zero when none), which this one applies first;
 // on exit its own step is pending.
@@ -437,7 +429,7 @@ void precond_iteration(Problem& P, float* x, int kind, double* trace_slot, hipSt
     // back projection kernel follows.  With many energies per ray the fused
     // launch, one workgroup per view, has too few threads for the ray work.
     const float* part = nullptr;                                       // summed by the penalty pass
-    const bool fuse = !P.identity && P.E == 1 && P.blur.h == 0 && fuse_rows_enabled();
+    const bool fuse = !P.identity && P.E == 1 && P.blur.h == 0 && P.fuse_rows;
     const BackRows br = fuse ? back_rows(*P.geom, P.g_img, P.K) : BackRows{};
     const int n_rows = br.ok ? launch_ray_grad_rows(ray_args(P), P.l, P.r, region(P, R_PHI_L), s, up, br) : -1;
     if (n_rows >= 0) {
@@ -670,6 +662,8 @@ int mbmd_problem_create(const mbmd_geometry* geom, const mbmd_spectral* sp, cons
         std::unique_ptr<mbmd_problem> P(new mbmd_problem());
         hipStream_t s = static_cast<hipStream_t>(stream);
         size_problem(*P, *geom, *sp, flags);
+        const char* fr = std::getenv("MBMD_FUSE_ROWS");
+        P->fuse_rows = !(fr && fr[0] == '0');
         P->pen_kind = pen->kind;
         P->delta = pen->delta;
         for (int i = 0; i < P->K * P->K; ++i) P->beta[i] = pen->beta_host ? pen->beta_host[i] : 0.0;

@@ -16,6 +16,7 @@
 //     turns a residual of the map into the fraction of the bin.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -300,6 +301,8 @@ void place_geometry(const mbmd_geometry& g, const GeomHost& h, GeomTables& t, ch
     p += L.det;
     t.back_part = back_ch ? reinterpret_cast<float*>(p) : nullptr;
     for (int i = 0; i <= kMaxBackCh; ++i) t.back_variant[i] = -1;
+    const char* fv = std::getenv("MBMD_BACK_VARIANT");
+    t.forced_back = fv && fv[0] ? std::atoi(fv) : -1;
     // stream-ordered uploads; the caller keeps h alive until the stream has run them
     MBMD_HIP(hipMemcpyAsync(t.view, h.vp.data(), sizeof(ViewParams) * h.vp.size(), hipMemcpyHostToDevice, s));
     MBMD_HIP(hipMemcpyAsync(t.bound, h.bound.data(), sizeof(float2) * h.bound.size(), hipMemcpyHostToDevice, s));

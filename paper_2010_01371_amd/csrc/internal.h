@@ -155,6 +155,9 @@ struct GeomTables {
     float* back_part = nullptr;
     // tile shape picked for the back projector per channel count (-1: not yet tuned)
     mutable int back_variant[kMaxBackCh + 1] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
+    // Testing hook: MBMD_BACK_VARIANT=v in the environment when the tables are
+    // placed forces back projector candidate v (-1: the tuned choice).
+    int forced_back = -1;
     int back_ch = 0;
     void* mem = nullptr;
     int device = -1;
@@ -346,6 +349,9 @@ struct Problem {
     double* trace_mem_owner = nullptr;
     int* flags = nullptr;
     int l_valid_for_x = 0;
+    // Testing hook: MBMD_FUSE_ROWS=0 in the environment at creation keeps the
+    // gradient launch and the detector prefix apart (the same iterates).
+    bool fuse_rows = true;
     hipStream_t last_stream = nullptr;
 };
 

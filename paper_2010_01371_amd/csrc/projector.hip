@@ -835,12 +835,6 @@ bool autotune_enabled() {
     return on;
 }
 
-// MBMD_BACK_VARIANT=v (read on every call) forces back projector candidate v,
-// for tests that compare the candidates; -1 or unset leaves the choice to tuning.
-int forced_back_variant() {
-    const char* e = std::getenv("MBMD_BACK_VARIANT");
-    return e && e[0] ? std::atoi(e) : -1;
-}
 
 // Relative time of a back projection launch with LPW lines per wavefront:
 // rounds of resident waves, each lasting the longer of the per-view latency
@@ -925,7 +919,7 @@ int back_chosen(const GeomTables& t) {
     BackShape cand[kMaxBackShapes];
     bool two_edges;
     const int n = back_shapes<NCH>(t, cand, two_edges);
-    const int forced = forced_back_variant();
+    const int forced = t.forced_back;
     if (forced >= 0 && forced < n) return forced;
     return t.back_variant[NCH];
 }
@@ -958,7 +952,7 @@ const float* back_launch(const GeomTables& t, const float* sino, float* x, hipSt
         MBMD_LAUNCHED();
     };
     int& choice = t.back_variant[NCH];
-    const int forced = forced_back_variant();
+    const int forced = t.forced_back;
     if (forced >= 0 && forced < n_cand) {           // testing hook: no tuning, nothing cached
         run(forced);
         return nv1 ? t.back_part : nullptr;
