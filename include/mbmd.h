@@ -397,20 +397,41 @@ int mbmd_forward_vjp(mbmd_problem* prob, const float* l_dev, const float* gbar_d
 
 /* ---------------------------------------------------------------- batches */
 
+/* Flags of mbmd_batch_create. */
+typedef enum {
+    MBMD_BATCH_SEPARATE_LAUNCHES = 1  /* every problem its own launches (no shared launches) */
+} mbmd_batch_flags;
+
+/* Device bytes of a batch of n problems (its table of per-slice offsets). */
+int mbmd_batch_workspace_bytes(mbmd_problem* const* probs, int n, size_t* bytes_host);
+
 /*
  * Group problems (uneven sizes allowed, all on the current device) for a
- * batched iteration.  The problems are borrowed and must outlive the batch.
- * Every problem has its own tables and scratch, so the problems are
- * independent: they are dealt round-robin onto up to 4 library-owned streams
- * (default priority) forked from the caller's stream and joined back into it.  Errors: MBMD_ERR_ARG, MBMD_ERR_UNSUPPORTED
- * (identity geometry), MBMD_ERR_HIP (stream or event creation).
+ * batched iteration (the serving form of the one-step MBMD iteration: many
+ * slices per call).  The problems are borrowed and must outlive the batch.
+ * Problems whose launch parameters are all equal -- same geometry, sizes,
+ * penalty kind and block layout (same workspace flags), no blur -- form a
+ * class: for the plain, Fourier and block-diagonal iterations every kernel
+ * runs once per class and iteration, each workgroup working on one member
+ * (the per-member byte offsets of the problem blocks and images live in the
+ * batch's workspace); other problems and other preconditioners get launches of
+ * their own.  Classes and lone problems are dealt round-robin onto up to 4
+ * library-owned streams (default priority) forked from the caller's stream and
+ * joined back into it.
+ *   - workspace_dev: NULL (the library allocates) or caller-owned device memory
+ *     of mbmd_batch_workspace_bytes, 256-byte aligned, kept until destroy;
+ *   - flags: 0 or MBMD_BATCH_SEPARATE_LAUNCHES.
+ * Errors: MBMD_ERR_ARG (NULL, a problem twice, workspace too small, unknown
+ * flag), MBMD_ERR_UNSUPPORTED (identity geometry), MBMD_ERR_HIP.
  */
-int mbmd_batch_create(mbmd_problem* const* probs, int n, mbmd_batch** out);
+int mbmd_batch_create(mbmd_problem* const* probs, int n, void* workspace_dev, size_t workspace_bytes,
+                      int flags, mbmd_batch** out);
 void mbmd_batch_destroy(mbmd_batch* batch);
 
 /*
  * n_iter iterations of every problem of the batch (x_dev[i] belongs to
- * problem i).  use_graph != 0 captures one iteration over all problems in a
+ * problem i; distinct images).  Bit for bit the iterates of each problem
+ * iterated alone.  use_graph != 0 captures one iteration over all problems in a
  * hipGraph on the first call (the geometry groups as parallel branches) and
  * replays it on `stream`; other x pointers, another preconditioner kind or a
  * member problem's blur set since the capture (mbmd_problem_set_blur) make

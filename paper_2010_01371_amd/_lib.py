@@ -51,7 +51,8 @@ _SIGNATURES = {
     "mbmd_sps_step": (c_int, [c_void_p, c_void_p, c_int, c_int, P(c_double), c_void_p]),
     "mbmd_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "mbmd_forward_vjp": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
-    "mbmd_batch_create": (c_int, [P(c_void_p), c_int, P(c_void_p)]),
+    "mbmd_batch_workspace_bytes": (c_int, [P(c_void_p), c_int, P(c_size_t)]),
+    "mbmd_batch_create": (c_int, [P(c_void_p), c_int, c_void_p, c_size_t, c_int, P(c_void_p)]),
     "mbmd_batch_destroy": (None, [c_void_p]),
     "mbmd_batch_sps_step": (c_int, [c_void_p, P(c_void_p), c_int, c_int, c_int, c_void_p]),
     "mbmd_projector_nnz": (c_int, [P(Geometry), P(ctypes.c_longlong), c_void_p]),

@@ -162,7 +162,13 @@ class Problem:
 
     @classmethod
     def from_workload(cls, wl, device="cuda", **kw):
-        return cls(wl.geom, wl.Q, wl.S, wl.y, wl.w, wl.penalty, device=device, **kw)
+        """A problem from a workload's arrays; keyword arguments named like the
+        constructor's data arguments (Q, S, y, w, penalty) replace the workload's."""
+        data = dict(geom=wl.geom, Q=wl.Q, S=wl.S, y=wl.y, w=wl.w, penalty=wl.penalty)
+        for k in list(kw):
+            if k in data:
+                data[k] = kw.pop(k)
+        return cls(device=device, **data, **kw)
 
     # ------------------------------------------------------------------
     def close(self):
@@ -257,14 +263,35 @@ class Problem:
 
 
 class Batch:
-    """Several problems iterated together (optionally as one hipGraph per iteration)."""
+    """Several problems iterated together (optionally as one hipGraph per iteration).
 
-    def __init__(self, problems):
+    shared=True lets problems with equal launch parameters share every kernel
+    launch of the plain, Fourier and block-diagonal iterations (one workgroup
+    grid over all members); shared=False gives each problem launches of its
+    own.  workspace="torch" puts the batch's table of per-member offsets in a
+    torch allocation held by this object; None lets the library allocate it."""
+
+    BATCH_SEPARATE_LAUNCHES = 1
+
+    def __init__(self, problems, shared=True, workspace="torch"):
         self.problems = list(problems)
         lib = _lib.load()
-        arr = (ctypes.c_void_p * len(self.problems))(*[p._h for p in self.problems])
+        n = len(self.problems)
+        arr = (ctypes.c_void_p * n)(*[p._h for p in self.problems])
+        self._ws = None
+        ws_ptr, ws_bytes = None, 0
+        if workspace == "torch":
+            nb = ctypes.c_size_t()
+            check(lib.mbmd_batch_workspace_bytes(arr, n, ctypes.byref(nb)), "mbmd_batch_workspace_bytes")
+            ws_bytes = nb.value
+            dev = torch.device("cuda", torch.cuda.current_device())
+            self._ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
+            ws_ptr = (self._ws.data_ptr() + 255) // 256 * 256
+        elif workspace is not None:
+            raise ValueError("workspace must be 'torch' or None")
+        flags = 0 if shared else self.BATCH_SEPARATE_LAUNCHES
         h = ctypes.c_void_p()
-        check(lib.mbmd_batch_create(arr, len(self.problems), ctypes.byref(h)), "mbmd_batch_create")
+        check(lib.mbmd_batch_create(arr, n, ws_ptr, ws_bytes, flags, ctypes.byref(h)), "mbmd_batch_create")
         self._h = h
         self._lib = lib
 

@@ -19,25 +19,37 @@
 
 struct mbmd_problem : public mbmd::Problem {};
 
-// Every problem owns its tables and scratch, so the problems of a batch are
-// independent: they are dealt round-robin onto library-owned streams (at most
-// kBatchStreams) forked from and joined back into the caller's stream -- or,
-// captured, as parallel branches of one graph per iteration.  (Problems that
-// shared tables would run in order on one stream: the grouping is by table
-// pointer.)
+// Problems whose launch parameters are identical form a class (same geometry,
+// sizes and block layout): each kernel of their iteration runs once for the
+// whole class, blockIdx.z selecting the slice (see ZBatch), so a batch of 24
+// slices in three sizes issues the launches of three iterations per
+// iteration.  The classes (and the problems left alone) are dealt round-robin
+// onto library-owned streams (at most kBatchStreams) forked from and joined
+// back into the caller's stream -- or, captured, onto parallel branches of one
+// graph per iteration.  The per-slice offsets of every class live in the
+// batch's device table zdev: [n][2] int64, a class's rows contiguous.
 constexpr int kBatchStreams = 4;
 struct mbmd_batch {
     std::vector<mbmd_problem*> probs;
-    std::vector<int> lane;              // branch stream of each problem
+    std::vector<std::vector<int>> units;   // classes (members in order) and lone problems
+    std::vector<int> unit_first;           // first row of each unit in the offset table
+    std::vector<int> lane;                 // branch stream of each unit
     int n_lanes = 0;
+    bool shared = true;                    // shared launches within classes (else one unit per problem)
+    long long* zdev = nullptr;             // device offset table [n][2]
+    std::vector<long long> zhost;          // its host copy (kept alive for the asynchronous upload)
+    std::vector<float*> zx;                // images the table was filled for
+    std::vector<int> zversions;            // each problem's launch_version when the units were formed
+    int zprecond = -1;                     // preconditioner the units were formed for
+    bool owns_z = false;
     std::vector<float*> xs;
-    std::vector<int> versions;          // each problem's launch_version when captured
+    std::vector<int> versions;             // each problem's launch_version when captured
     int precond = -1;
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     bool captured = false;
-    hipStream_t stream = nullptr;       // caller stream the graphs were last launched on
-    hipStream_t capture = nullptr;      // library-owned stream used only for capture
+    hipStream_t stream = nullptr;          // caller stream the graphs were last launched on
+    hipStream_t capture = nullptr;         // library-owned stream used only for capture
     hipStream_t branch[kBatchStreams] = {};
     hipEvent_t fork = nullptr;
     hipEvent_t join[kBatchStreams] = {};
@@ -429,7 +441,7 @@ void precond_iteration(Problem& P, float* x, int kind, double* trace_slot, hipSt
     // back projection kernel follows.  With many energies per ray the fused
     // launch, one workgroup per view, has too few threads for the ray work.
     const float* part = nullptr;                                       // summed by the penalty pass
-    const bool fuse = !P.identity && P.E == 1 && P.blur.h == 0 && P.fuse_rows;
+    const bool fuse = !P.identity && P.E == 1 && P.blur.h == 0 && P.fuse_rows && !zarg();
     const BackRows br = fuse ? back_rows(*P.geom, P.g_img, P.K) : BackRows{};
     const int n_rows = br.ok ? launch_ray_grad_rows(ray_args(P), P.l, P.r, region(P, R_PHI_L), s, up, br) : -1;
     if (n_rows >= 0) {
@@ -568,6 +580,37 @@ void sps_run(Problem& P, float* x, int precond, int n_iter, double* trace_host, 
                                 hipMemcpyDeviceToHost, s));
         read_flags(P, s);
     }
+}
+
+// Sets the batched-launch setting for the launches of one class (see ZBatch)
+// and clears it on leaving, also on an error.
+struct ZScope {
+    ZScope(const long long* zd, int nz, const void* x0) {
+        ZBatch& z = zbatch();
+        z.zd = zd;
+        z.nz = nz;
+        z.x0 = x0;
+    }
+    ~ZScope() { zbatch() = ZBatch{}; }
+    ZScope(const ZScope&) = delete;
+    ZScope& operator=(const ZScope&) = delete;
+};
+
+// Problems whose iterations can share launches: every host-side launch
+// parameter equal (geometry, sizes, penalty kind and delta, block layout) and
+// no blur.  Everything else a kernel reads lives in the problem's block.
+std::string batch_class_key(const Problem& P) {
+    const mbmd_geometry& g = P.g;
+    const double f[] = {(double)g.kind, (double)g.nx, (double)g.ny, g.dx, g.dy, (double)g.n_views, g.theta0,
+                        g.dtheta, (double)g.n_bins, g.du, g.u_offset, g.dso, g.dsd, (double)P.K, (double)P.E,
+                        (double)P.C, (double)P.pen_kind, (double)P.has_penalty, (double)(float)P.delta,
+                        (double)P.ws_flags, (double)P.arena.used, (double)P.blur.h, (double)P.fuse_rows};
+    return std::string(reinterpret_cast<const char*>(f), sizeof(f));
+}
+
+// Preconditioners whose apply kernels have the batched form.
+bool shares_launches(int precond) {
+    return precond == MBMD_PRECOND_NONE || precond == MBMD_PRECOND_FOURIER || precond == MBMD_PRECOND_BLOCKDIAG;
 }
 
 }  // namespace
@@ -899,21 +942,39 @@ int mbmd_forward_vjp(mbmd_problem* prob, const float* l_dev, const float* gbar_d
     });
 }
 
-int mbmd_batch_create(mbmd_problem* const* probs, int n, mbmd_batch** out) {
+int mbmd_batch_workspace_bytes(mbmd_problem* const* probs, int n, size_t* bytes) {
+    return guarded([&] {
+        MBMD_REQUIRE(probs && n > 0 && bytes, MBMD_ERR_ARG, "bad argument");
+        *bytes = ((size_t)16 * n + 255) & ~size_t(255);
+    });
+}
+
+int mbmd_batch_create(mbmd_problem* const* probs, int n, void* workspace_dev, size_t workspace_bytes, int flags,
+                      mbmd_batch** out) {
     return guarded([&] {
         MBMD_REQUIRE(probs && n > 0 && out, MBMD_ERR_ARG, "bad argument");
+        MBMD_REQUIRE((flags & ~MBMD_BATCH_SEPARATE_LAUNCHES) == 0, MBMD_ERR_ARG, "unknown batch flag");
+        *out = nullptr;
         std::unique_ptr<mbmd_batch> b(new mbmd_batch());
-        std::vector<const GeomTables*> geoms;
         for (int i = 0; i < n; ++i) {
             MBMD_REQUIRE(probs[i] != nullptr, MBMD_ERR_ARG, "NULL problem in batch");
             MBMD_REQUIRE(!probs[i]->identity, MBMD_ERR_UNSUPPORTED, "batches hold projector geometries");
+            for (int k = 0; k < i; ++k) MBMD_REQUIRE(probs[k] != probs[i], MBMD_ERR_ARG, "a problem twice in a batch");
             b->probs.push_back(probs[i]);
-            const GeomTables* g = probs[i]->geom;
-            int gi = (int)(std::find(geoms.begin(), geoms.end(), g) - geoms.begin());
-            if (gi == (int)geoms.size()) geoms.push_back(g);
-            b->lane.push_back(gi % kBatchStreams);
         }
-        b->n_lanes = (int)std::min<size_t>(geoms.size(), kBatchStreams);
+        b->shared = !(flags & MBMD_BATCH_SEPARATE_LAUNCHES);
+        const size_t need = (size_t)16 * n;
+        if (workspace_dev) {
+            MBMD_REQUIRE(workspace_bytes >= need, MBMD_ERR_ARG, "batch workspace smaller than mbmd_batch_workspace_bytes");
+            MBMD_REQUIRE((reinterpret_cast<uintptr_t>(workspace_dev) & 255) == 0, MBMD_ERR_ARG,
+                         "workspace must be 256-byte aligned");
+            b->zdev = static_cast<long long*>(workspace_dev);
+        } else {
+            MBMD_HIP(hipMalloc(reinterpret_cast<void**>(&b->zdev), need));
+            b->owns_z = true;
+        }
+        b->zhost.assign((size_t)2 * n, 0);
+        b->n_lanes = std::min(n, kBatchStreams);
         for (int i = 0; i < b->n_lanes; ++i) {
             MBMD_HIP(hipStreamCreateWithFlags(&b->branch[i], hipStreamNonBlocking));
             MBMD_HIP(hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming));
@@ -939,6 +1000,10 @@ void mbmd_batch_destroy(mbmd_batch* b) {
         if (b->join[i]) (void)hipEventDestroy(b->join[i]);
     }
     if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->owns_z && b->zdev) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(b->zdev);
+    }
     delete b;
 }
 
@@ -954,21 +1019,69 @@ int mbmd_batch_sps_step(mbmd_batch* b, float* const* x_dev, int precond, int n_i
             begin_run(*b->probs[i], s);
             if (precond == MBMD_PRECOND_NONE) ensure_dL_const(*b->probs[i], s);
         }
-        // one slice iteration on its branch stream
-        auto slice_iter = [&](size_t k, bool refresh) {
-            Problem& P = *b->probs[k];
-            hipStream_t bs = b->branch[b->lane[k]];
+        // Units: classes of problems that share launches (for preconditioners whose
+        // kernels have the batched form), else one unit per problem.
+        bool same_units = b->zprecond == precond && b->zx.size() == n && b->zversions.size() == n &&
+                          std::equal(b->zx.begin(), b->zx.end(), x_dev);
+        for (size_t i = 0; same_units && i < n; ++i) same_units = b->zversions[i] == b->probs[i]->launch_version;
+        if (!same_units) {
+            b->units.clear();
+            b->unit_first.clear();
+            std::vector<std::string> keys;         // per unit: its class key, empty for a lone problem
+            for (size_t i = 0; i < n; ++i) {
+                const bool can = b->shared && shares_launches(precond) && b->probs[i]->blur.h == 0;
+                const std::string key = can ? batch_class_key(*b->probs[i]) : std::string();
+                size_t u = can ? (size_t)(std::find(keys.begin(), keys.end(), key) - keys.begin()) : keys.size();
+                if (u == keys.size()) {
+                    keys.push_back(key);
+                    b->units.push_back({});
+                }
+                b->units[u].push_back((int)i);
+            }
+            // offsets of every class member from its first member: block and image
+            int row = 0;
+            for (const auto& u : b->units) {
+                b->unit_first.push_back(row);
+                const Problem& P0 = *b->probs[u[0]];
+                for (int m : u) {
+                    const Problem& P = *b->probs[m];
+                    b->zhost[2 * row] = (long long)(reinterpret_cast<uintptr_t>(P.arena.base) -
+                                                    reinterpret_cast<uintptr_t>(P0.arena.base));
+                    b->zhost[2 * row + 1] = (long long)(reinterpret_cast<uintptr_t>(x_dev[m]) -
+                                                        reinterpret_cast<uintptr_t>(x_dev[u[0]]));
+                    ++row;
+                }
+            }
+            MBMD_HIP(hipMemcpyAsync(b->zdev, b->zhost.data(), sizeof(long long) * b->zhost.size(),
+                                    hipMemcpyHostToDevice, s));
+            MBMD_HIP(hipStreamSynchronize(s));
+            b->lane.resize(b->units.size());
+            for (size_t u = 0; u < b->units.size(); ++u) b->lane[u] = (int)(u % b->n_lanes);
+            b->zprecond = precond;
+            b->zx.assign(x_dev, x_dev + n);
+            b->zversions.resize(n);
+            for (size_t i = 0; i < n; ++i) b->zversions[i] = b->probs[i]->launch_version;
+        }
+        const size_t nu = b->units.size();
+        // one iteration of unit u on its branch stream: a class as one launch per kernel
+        auto unit_iter = [&](size_t u, bool refresh) {
+            const std::vector<int>& mem = b->units[u];
+            Problem& P = *b->probs[mem[0]];
+            float* x = x_dev[mem[0]];
+            hipStream_t bs = b->branch[b->lane[u]];
+            std::unique_ptr<ZScope> zs;
+            if (mem.size() > 1) zs.reset(new ZScope(b->zdev + 2 * b->unit_first[u], (int)mem.size(), x));
             if (precond == MBMD_PRECOND_NONE) {
-                plain_iteration(P, x_dev[k], nullptr, bs);
+                plain_iteration(P, x, nullptr, bs);
             } else {
                 if (refresh) {
-                    flush_step(P, x_dev[k], bs);
-                    project(P, x_dev[k], P.l, P.K, bs);
+                    flush_step(P, x, bs);
+                    project(P, x, P.l, P.K, bs);
                 }
-                precond_iteration(P, x_dev[k], precond, nullptr, bs);
+                precond_iteration(P, x, precond, nullptr, bs);
             }
         };
-        // the pending step of each slice, after its last iteration
+        // the pending step of each problem, after its last iteration
         auto finish = [&](size_t k, hipStream_t st) {
             if (precond != MBMD_PRECOND_NONE) flush_step(*b->probs[k], x_dev[k], st);
         };
@@ -983,12 +1096,12 @@ int mbmd_batch_sps_step(mbmd_batch* b, float* const* x_dev, int precond, int n_i
             }
         };
         if (!use_graph) {
-            // the slices are independent: each branch runs all its iterations, then joins
+            // the units are independent: each branch runs all its iterations, then joins
             fork(s);
             for (int it = 0; it < n_iter; ++it)
-                for (size_t k = 0; k < n; ++k) slice_iter(k, it % kRefreshEvery == 0);
-            for (size_t k = 0; k < n; ++k) finish(k, b->branch[b->lane[k]]);
+                for (size_t u = 0; u < nu; ++u) unit_iter(u, it % kRefreshEvery == 0);
             join(s);
+            for (size_t k = 0; k < n; ++k) finish(k, s);
             return;
         }
         // Capture on a library-owned stream (the legacy default stream cannot be
@@ -1012,7 +1125,7 @@ int mbmd_batch_sps_step(mbmd_batch* b, float* const* x_dev, int precond, int n_i
                 MBMD_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
                 try {
                     fork(cs);
-                    for (size_t k = 0; k < n; ++k) slice_iter(k, i == 1);
+                    for (size_t u = 0; u < nu; ++u) unit_iter(u, i == 1);
                     join(cs);
                 } catch (...) {
                     hipGraph_t g = nullptr;

@@ -239,8 +239,16 @@ __global__ __launch_bounds__(kThreads) void k_fft_rows_fwd(int K, int nx_rt, int
                                                            const float* __restrict__ in,
                                                            const float* __restrict__ M, int sy, int sx,
                                                            float2* __restrict__ spec,
-                                                           const float2* __restrict__ tw) {
+                                                           const float2* __restrict__ tw,
+                                                           const long long* __restrict__ zd) {
     extern __shared__ float2 buf[];
+    if (zd) {                                              // batched: this slice's buffers
+        const long long d = zoff(zd, Z_BLOCK);
+        in = zshift(in, d);
+        M = zshift(M, d);
+        spec = zshift(spec, d);
+        tw = zshift(tw, d);
+    }
     const int nx = NT ? NT : nx_rt;                        // transform length (a constant when NT > 0)
     const int PN = lds_len(nx);
     float2* twl = buf + (size_t)RB * K * PN;               // twiddle table staged in LDS
@@ -288,8 +296,15 @@ constexpr int kBatch = 8;
 template <int NT>
 __global__ __launch_bounds__(kThreads) void k_fft_cols(int K, int nx, int ny_rt, int C, float2* __restrict__ spec,
                                                        const float* __restrict__ filt,
-                                                       const float2* __restrict__ tw) {
+                                                       const float2* __restrict__ tw,
+                                                       const long long* __restrict__ zd) {
     extern __shared__ float2 buf[];
+    if (zd) {                                              // batched: this slice's buffers
+        const long long d = zoff(zd, Z_BLOCK);
+        spec = zshift(spec, d);
+        filt = zshift(filt, d);
+        tw = zshift(tw, d);
+    }
     const int ny = NT ? NT : ny_rt;                        // transform length (a constant when NT > 0)
     const int PN = lds_len(ny);
     float2* twl = buf + (size_t)K * C * PN;                // twiddle table staged in LDS
@@ -371,9 +386,19 @@ __global__ __launch_bounds__(kThreads) void k_fft_rows_inv(int K, int nx_rt, int
                                                            float* __restrict__ out,
                                                            const float* __restrict__ g,
                                                            double* __restrict__ partials,
-                                                           const float2* __restrict__ tw) {
+                                                           const float2* __restrict__ tw,
+                                                           const long long* __restrict__ zd) {
     extern __shared__ float2 buf[];
     __shared__ double sh[kThreads / 64];
+    if (zd) {                                              // batched: this slice's buffers
+        const long long d = zoff(zd, Z_BLOCK);
+        spec = zshift(spec, d);
+        M = zshift(M, d);
+        out = zshift(out, d);
+        g = zshift(g, d);
+        partials = zshift(partials, d);
+        tw = zshift(tw, d);
+    }
     const int nx = NT ? NT : nx_rt;                        // transform length (a constant when NT > 0)
     const int PN = lds_len(nx);
     float2* twl = buf + (size_t)RB * K * PN;               // twiddle table staged in LDS
@@ -492,8 +517,8 @@ void launch_fft2_forward(int K, int nx, int ny, const float* in, const float* M,
     const int RB = rows_per_block(K, nx, ny);
     {
         KernelTimer kt_("k_fft_rows_fwd", s);
-#define L_(NT) hipLaunchKernelGGL((k_fft_rows_fwd<NT>), dim3((ny + RB - 1) / RB), dim3(kThreads), rows_lds(K, RB, nx), \
-                               s, K, nx, ny, RB, in, M, sy, sx, spec, twx)
+#define L_(NT) hipLaunchKernelGGL((k_fft_rows_fwd<NT>), zgrid(dim3((ny + RB - 1) / RB)), dim3(kThreads),                 \
+                               rows_lds(K, RB, nx), s, K, nx, ny, RB, in, M, sy, sx, spec, twx, zarg())
         MBMD_FFT_DISPATCH(nx, L_);
 #undef L_
         kt_.stop();
@@ -502,8 +527,8 @@ void launch_fft2_forward(int K, int nx, int ny, const float* in, const float* M,
     const int C = col_group(K, nx, ny);
     {
         KernelTimer kt_("k_fft_cols", s);
-#define L_(NT) hipLaunchKernelGGL((k_fft_cols<NT>), dim3(nx / C), dim3(kThreads), cols_lds(K, C, ny, false), s, K, nx, \
-                               ny, C, spec, (const float*)nullptr, twy)
+#define L_(NT) hipLaunchKernelGGL((k_fft_cols<NT>), zgrid(dim3(nx / C)), dim3(kThreads), cols_lds(K, C, ny, false), s, K, \
+                               nx, ny, C, spec, (const float*)nullptr, twy, zarg())
         MBMD_FFT_DISPATCH(ny, L_);
 #undef L_
         kt_.stop();
@@ -520,8 +545,8 @@ int launch_fourier_apply(int K, int nx, int ny, const float* in, const float* M,
     MBMD_REQUIRE(nblk <= kMaxPartials, MBMD_ERR_SHAPE, "too many rows for the partial-sum buffer");
     {
         KernelTimer kt_("k_fft_rows_fwd", s);
-#define L_(NT) hipLaunchKernelGGL((k_fft_rows_fwd<NT>), dim3(nblk), dim3(kThreads), rows_lds(K, RB, nx), s, K, nx, ny, \
-                               RB, in, M, 0, 0, spec, twx)
+#define L_(NT) hipLaunchKernelGGL((k_fft_rows_fwd<NT>), zgrid(dim3(nblk)), dim3(kThreads), rows_lds(K, RB, nx), s, K, nx, \
+                               ny, RB, in, M, 0, 0, spec, twx, zarg())
         MBMD_FFT_DISPATCH(nx, L_);
 #undef L_
         kt_.stop();
@@ -531,8 +556,8 @@ int launch_fourier_apply(int K, int nx, int ny, const float* in, const float* M,
     MBMD_REQUIRE(cols_lds(K, C, ny, true) <= 65536, MBMD_ERR_SHAPE, "image too large for the LDS-resident FFT");
     {
         KernelTimer kt_("k_fft_cols", s);
-#define L_(NT) hipLaunchKernelGGL((k_fft_cols<NT>), dim3(nx / C), dim3(kThreads), cols_lds(K, C, ny, true), s, K, nx, \
-                               ny, C, spec, Filt, twy)
+#define L_(NT) hipLaunchKernelGGL((k_fft_cols<NT>), zgrid(dim3(nx / C)), dim3(kThreads), cols_lds(K, C, ny, true), s, K, \
+                               nx, ny, C, spec, Filt, twy, zarg())
         MBMD_FFT_DISPATCH(ny, L_);
 #undef L_
         kt_.stop();
@@ -540,8 +565,8 @@ int launch_fourier_apply(int K, int nx, int ny, const float* in, const float* M,
     MBMD_LAUNCHED();
     {
         KernelTimer kt_("k_fft_rows_inv", s);
-#define L_(NT) hipLaunchKernelGGL((k_fft_rows_inv<NT>), dim3(nblk), dim3(kThreads), rows_lds(K, RB, nx), s, K, nx, ny, \
-                               RB, spec, M, out_sign / (float)((double)nx * ny), out, g, partials, twx)
+#define L_(NT) hipLaunchKernelGGL((k_fft_rows_inv<NT>), zgrid(dim3(nblk)), dim3(kThreads), rows_lds(K, RB, nx), s, K, nx, \
+                               ny, RB, spec, M, out_sign / (float)((double)nx * ny), out, g, partials, twx, zarg())
         MBMD_FFT_DISPATCH(nx, L_);
 #undef L_
         kt_.stop();

@@ -36,8 +36,20 @@ using dev::Counts;
 __global__ __launch_bounds__(kThreads) void k_penalty_grad(PenaltyArgs a, const float* __restrict__ x,
                                                            const float* gL, const float* dL, float* g, float* d,
                                                            double* __restrict__ partials,
-                                                           const float* __restrict__ gL2) {
+                                                           const float* __restrict__ gL2,
+                                                           const long long* __restrict__ zd) {
     __shared__ double sh[kThreads / 64];
+    if (zd) {                                              // batched: this slice's buffers and image
+        const long long dz = zoff(zd, Z_BLOCK);
+        a.beta = zshift(a.beta, dz);
+        x = zshift(x, zoff(zd, Z_IMAGE));
+        gL = zshift(gL, dz);
+        dL = zshift(dL, dz);
+        g = zshift(g, dz);
+        d = zshift(d, dz);
+        partials = zshift(partials, dz);
+        gL2 = zshift(gL2, dz);
+    }
     const int nj = a.nx * a.ny;
     const int j = blockIdx.x * kThreads + threadIdx.x;
     double phi = 0.0;
@@ -95,7 +107,12 @@ __global__ __launch_bounds__(kThreads) void k_penalty_hess_add(PenaltyArgs a, co
 }
 
 __global__ void k_plain_update(int n, float* __restrict__ x, const float* __restrict__ g,
-                               const float* __restrict__ d) {
+                               const float* __restrict__ d, const long long* __restrict__ zd) {
+    if (zd) {                                              // batched: this slice's buffers and image
+        x = zshift(x, zoff(zd, Z_IMAGE));
+        g = zshift(g, zoff(zd, Z_BLOCK));
+        d = zshift(d, zoff(zd, Z_BLOCK));
+    }
     const int i = blockIdx.x * kThreads + threadIdx.x;
     if (i < n) x[i] -= g[i] / fmaxf(d[i], 1e-30f);
 }
@@ -108,14 +125,23 @@ __global__ void k_axpy_alpha(int n, float* __restrict__ x, const float* __restri
 
 __global__ void k_axpy2_alpha(int n1, float* __restrict__ x1, const float* __restrict__ p1, int n2,
                               float* __restrict__ x2, const float* __restrict__ p2,
-                              const double* __restrict__ alpha) {
+                              const double* __restrict__ alpha, const long long* __restrict__ zd) {
+    if (zd) {                                              // batched: x1 is the slice's image
+        const long long d = zoff(zd, Z_BLOCK);
+        x1 = zshift(x1, zoff(zd, Z_IMAGE));
+        p1 = zshift(p1, d);
+        x2 = zshift(x2, d);
+        p2 = zshift(p2, d);
+        alpha = zshift(alpha, d);
+    }
     const int i = blockIdx.x * kThreads + threadIdx.x;
     const float a = (float)*alpha;
     if (i < n1) x1[i] = fmaf(a, p1[i], x1[i]);
     else if (i - n1 < n2) x2[i - n1] = fmaf(a, p2[i - n1], x2[i - n1]);
 }
 
-__global__ void k_fill(int n, float* __restrict__ x, float value) {
+__global__ void k_fill(int n, float* __restrict__ x, float value, const long long* __restrict__ zd, int x_is_image) {
+    if (zd) x = zshift(x, zoff(zd, x_is_image ? Z_IMAGE : Z_BLOCK));   // batched: this slice's buffer
     const int i = blockIdx.x * kThreads + threadIdx.x;
     if (i < n) x[i] = value;
 }
@@ -141,8 +167,15 @@ __global__ void k_block_add_column(int nj, int K, int k_col, const float* __rest
 
 __global__ __launch_bounds__(kThreads) void k_dot(int n, const float* __restrict__ a,
                                                   const float* __restrict__ b,
-                                                  double* __restrict__ partials) {
+                                                  double* __restrict__ partials,
+                                                  const long long* __restrict__ zd) {
     __shared__ double sh[kThreads / 64];
+    if (zd) {                                              // batched: this slice's buffers
+        const long long d = zoff(zd, Z_BLOCK);
+        a = zshift(a, d);
+        b = zshift(b, d);
+        partials = zshift(partials, d);
+    }
     const int i = blockIdx.x * kThreads + threadIdx.x;
     const double v = i < n ? (double)a[i] * (double)b[i] : 0.0;
     const double tot = block_sum(v, sh);
@@ -151,7 +184,13 @@ __global__ __launch_bounds__(kThreads) void k_dot(int n, const float* __restrict
 
 // out_k = scale * sum_l M_kl in_l per pixel; M packed component-major.  in may alias out.
 __global__ void k_block_apply(int nj, int K, const float* __restrict__ M, const float* in, float* out,
-                              float scale) {
+                              float scale, const long long* __restrict__ zd) {
+    if (zd) {                                              // batched: this slice's buffers
+        const long long d = zoff(zd, Z_BLOCK);
+        M = zshift(M, d);
+        in = zshift(in, d);
+        out = zshift(out, d);
+    }
     const int j = blockIdx.x * kThreads + threadIdx.x;
     if (j >= nj) return;
     float a[kMaxMat];
@@ -287,7 +326,8 @@ __global__ void k_scale_by_vec(int n, int nch, const float* __restrict__ in, con
     for (int c = 0; c < nch; ++c) out[(size_t)c * n + i] = in[(size_t)c * n + i] * s;
 }
 
-__global__ void k_fill_double(int n, double* __restrict__ x, double value) {
+__global__ void k_fill_double(int n, double* __restrict__ x, double value, const long long* __restrict__ zd) {
+    if (zd) x = zshift(x, zoff(zd, Z_BLOCK));             // batched: this slice's buffer
     const int i = blockIdx.x * kThreads + threadIdx.x;
     if (i < n) x[i] = value;
 }
@@ -298,8 +338,16 @@ __global__ void k_fill_double(int n, double* __restrict__ x, double value) {
 __global__ __launch_bounds__(dev::kReduceThreads) void k_reduce_final(const double* __restrict__ partials,
                                                                       Counts counts, double* __restrict__ scal,
                                                                       double* __restrict__ trace_slot, int mode,
-                                                                      int* __restrict__ flags) {
+                                                                      int* __restrict__ flags,
+                                                                      const long long* __restrict__ zd) {
     __shared__ double sh[2 * kRegions];
+    if (zd) {                                              // batched: this slice's buffers
+        const long long d = zoff(zd, Z_BLOCK);
+        partials = zshift(partials, d);
+        scal = zshift(scal, d);
+        trace_slot = zshift(trace_slot, d);
+        flags = zshift(flags, d);
+    }
     dev::region_sums(partials, counts, sh);
     if (threadIdx.x == 0) dev::form_scalars(sh, mode, scal, trace_slot, flags, true);
 }
@@ -329,7 +377,7 @@ void launch_scale_by_vec(int n, int nch, const float* in, const float* vec, floa
 void launch_fill_double(int n, double* x, double value, hipStream_t s) {
     {
         KernelTimer kt_("k_fill_double", s);
-        hipLaunchKernelGGL(k_fill_double, dim3(nblk(n)), dim3(kThreads), 0, s, n, x, value);
+        hipLaunchKernelGGL(k_fill_double, zgrid(dim3(nblk(n))), dim3(kThreads), 0, s, n, x, value, zarg());
         kt_.stop();
     }
     MBMD_LAUNCHED();
@@ -341,7 +389,8 @@ int launch_penalty_grad(const PenaltyArgs& a, const float* x, const float* gL, c
     MBMD_REQUIRE(nb <= kMaxPartials, MBMD_ERR_SHAPE, "image too large for the partial-sum buffer");
     {
         KernelTimer kt_("k_penalty_grad", s);
-        hipLaunchKernelGGL(k_penalty_grad, dim3(nb), dim3(kThreads), 0, s, a, x, gL, dL, g, d, phi_partials, gL2);
+        hipLaunchKernelGGL(k_penalty_grad, zgrid(dim3(nb)), dim3(kThreads), 0, s, a, x, gL, dL, g, d, phi_partials, gL2,
+                           zarg());
         kt_.stop();
     }
     MBMD_LAUNCHED();
@@ -372,7 +421,7 @@ void launch_penalty_hess_add(const PenaltyArgs& a, const float* v, float* out, h
 void launch_plain_update(int n, float* x, const float* g, const float* d, hipStream_t s) {
     {
         KernelTimer kt_("k_plain_update", s);
-        hipLaunchKernelGGL(k_plain_update, dim3(nblk(n)), dim3(kThreads), 0, s, n, x, g, d);
+        hipLaunchKernelGGL(k_plain_update, zgrid(dim3(nblk(n))), dim3(kThreads), 0, s, n, x, g, d, zarg());
         kt_.stop();
     }
     MBMD_LAUNCHED();
@@ -391,7 +440,8 @@ void launch_axpy2_alpha(int n1, float* x1, const float* p1, int n2, float* x2, c
                         const double* alpha, hipStream_t s) {
     {
         KernelTimer kt_("k_axpy2_alpha", s);
-        hipLaunchKernelGGL(k_axpy2_alpha, dim3(nblk(n1 + n2)), dim3(kThreads), 0, s, n1, x1, p1, n2, x2, p2, alpha);
+        hipLaunchKernelGGL(k_axpy2_alpha, zgrid(dim3(nblk(n1 + n2))), dim3(kThreads), 0, s, n1, x1, p1, n2, x2, p2,
+                           alpha, zarg());
         kt_.stop();
     }
     MBMD_LAUNCHED();
@@ -400,7 +450,8 @@ void launch_axpy2_alpha(int n1, float* x1, const float* p1, int n2, float* x2, c
 void launch_fill(int n, float* x, float value, hipStream_t s) {
     {
         KernelTimer kt_("k_fill", s);
-        hipLaunchKernelGGL(k_fill, dim3(nblk(n)), dim3(kThreads), 0, s, n, x, value);
+        hipLaunchKernelGGL(k_fill, zgrid(dim3(nblk(n))), dim3(kThreads), 0, s, n, x, value, zarg(),
+                           (int)(zarg() && x == zbatch().x0));
         kt_.stop();
     }
     MBMD_LAUNCHED();
@@ -429,7 +480,7 @@ int launch_dot(int n, const float* a, const float* b, double* partials, hipStrea
     MBMD_REQUIRE(nb <= kMaxPartials, MBMD_ERR_SHAPE, "vector too long for the partial-sum buffer");
     {
         KernelTimer kt_("k_dot", s);
-        hipLaunchKernelGGL(k_dot, dim3(nb), dim3(kThreads), 0, s, n, a, b, partials);
+        hipLaunchKernelGGL(k_dot, zgrid(dim3(nb)), dim3(kThreads), 0, s, n, a, b, partials, zarg());
         kt_.stop();
     }
     MBMD_LAUNCHED();
@@ -439,7 +490,8 @@ int launch_dot(int n, const float* a, const float* b, double* partials, hipStrea
 void launch_block_apply(int nj, int K, const float* M, const float* in, float* out, float scale, hipStream_t s) {
     {
         KernelTimer kt_("k_block_apply", s);
-        hipLaunchKernelGGL(k_block_apply, dim3(nblk(nj)), dim3(kThreads), 0, s, nj, K, M, in, out, scale);
+        hipLaunchKernelGGL(k_block_apply, zgrid(dim3(nblk(nj))), dim3(kThreads), 0, s, nj, K, M, in, out, scale,
+                           zarg());
         kt_.stop();
     }
     MBMD_LAUNCHED();
@@ -475,8 +527,8 @@ void launch_reduce_final(double* partials, const int* counts, double* scal, doub
     }
     {
         KernelTimer kt_("k_reduce_final", s);
-        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(dev::kReduceThreads), 0, s, partials, c, scal, trace_slot,
-                           mode, flags);
+        hipLaunchKernelGGL(k_reduce_final, zgrid(dim3(1)), dim3(dev::kReduceThreads), 0, s, partials, c, scal,
+                           trace_slot, mode, flags, zarg());
         kt_.stop();
     }
     MBMD_LAUNCHED();

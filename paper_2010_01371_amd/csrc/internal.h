@@ -78,6 +78,35 @@ class KernelTimer {
     bool active_ = false;
 };
 
+// ---------------------------------------------------------------- batched launches
+// A batch runs slices whose launch parameters are identical (a class) as one
+// launch per kernel, blockIdx.z selecting the slice.  Every slice's state lies
+// at the same offsets of its own block as slice 0's in its block, so slice z's
+// pointers are slice 0's plus a byte offset: zd[2 z] for the block, zd[2 z + 1]
+// for the caller's image x.  The launchers read the current setting, which only
+// the batch sets (thread-local, around one class's launches); kernels given a
+// non-null zd shift their pointers by it.  While it is set, KernelTimer refuses
+// every kernel without that form (MBMD_ERR_UNSUPPORTED, before the launch).
+struct ZBatch {
+    const long long* zd = nullptr;   // device [nz][2]
+    int nz = 1;
+    const void* x0 = nullptr;        // slice 0's image, for launchers whose input may be x
+};
+ZBatch& zbatch();
+inline dim3 zgrid(dim3 g) {
+    g.z = (unsigned)zbatch().nz;
+    return g;
+}
+inline const long long* zarg() { return zbatch().zd; }
+enum { Z_BLOCK = 0, Z_IMAGE = 1 };
+__device__ __forceinline__ long long zoff(const long long* zd, int which) {
+    return zd ? zd[2 * (int)blockIdx.z + which] : 0;
+}
+template <class T>
+__device__ __forceinline__ T* zshift(T* p, long long d) {
+    return p ? reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + (uintptr_t)d) : p;
+}
+
 // ---------------------------------------------------------------- device memory arena
 // Parts are 256-byte aligned offsets from base.  A null base is a sizing pass:
 // take() only counts.  The memory is the library's (reserve, freed by release)

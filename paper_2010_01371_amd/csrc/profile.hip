@@ -59,7 +59,28 @@ void resolve_locked() {
 }
 }  // namespace
 
+namespace {
+// Kernels with a batched form (they shift their pointers by the slice offsets).
+bool batched_form(const char* name) {
+    static const char* const names[] = {"k_ray_grad", "k_curvature", "k_line_prefix", "k_dd_forward",
+                                        "k_detector_prefix", "k_dd_back", "k_penalty_grad", "k_fft_rows_fwd",
+                                        "k_fft_cols", "k_fft_rows_inv", "k_reduce_final", "k_axpy2_alpha",
+                                        "k_fill_double", "k_block_apply", "k_dot", "k_plain_update", "k_fill",
+                                        "k_add_part"};
+    for (const char* n : names)
+        if (std::strcmp(n, name) == 0) return true;
+    return false;
+}
+}  // namespace
+
+ZBatch& zbatch() {
+    static thread_local ZBatch z;
+    return z;
+}
+
 KernelTimer::KernelTimer(const char* name, hipStream_t s) : name_(name), s_(s) {
+    MBMD_REQUIRE(zbatch().zd == nullptr || batched_form(name), MBMD_ERR_UNSUPPORTED,
+                 std::string("no batched form of ") + name);
     if (!g_on) return;
     {
         std::lock_guard<std::mutex> lock(g_mu);

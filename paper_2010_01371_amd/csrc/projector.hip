@@ -148,7 +148,15 @@ __device__ __forceinline__ void keep(float v) { asm volatile("" ::"v"(v)); }
 __global__ __launch_bounds__(kScanThreads) void k_line_prefix(const float* __restrict__ img,
                                                                float* __restrict__ rows, float* __restrict__ cols,
                                                                int nx, int ny, int line0,
-                                                               float* __restrict__ zero_out, int zero_n) {
+                                                               float* __restrict__ zero_out, int zero_n,
+                                                               const long long* __restrict__ zd, int img_is_x) {
+    if (zd) {                                                  // batched: this slice's buffers
+        const long long d = zoff(zd, Z_BLOCK);
+        img = zshift(img, img_is_x ? zoff(zd, Z_IMAGE) : d);
+        rows = zshift(rows, d);
+        cols = zshift(cols, d);
+        zero_out = zshift(zero_out, d);
+    }
     // side job: clear the projection's output, which the forward adds into
     for (int i = (blockIdx.y * gridDim.x + blockIdx.x) * kScanThreads + threadIdx.x; i < zero_n;
          i += gridDim.x * gridDim.y * kScanThreads)
@@ -201,7 +209,16 @@ __global__ __launch_bounds__(kPrefixThreads) void k_detector_prefix(const float*
                                                                      const float* __restrict__ path,
                                                                      const ViewParams* __restrict__ view, int V,
                                                                      int B, DetEntry* __restrict__ C,
-                                                                     BackClear tc) {
+                                                                     BackClear tc, const long long* __restrict__ zd) {
+    if (zd) {                                                  // batched: this slice's buffers
+        const long long d = zoff(zd, Z_BLOCK);
+        sino = zshift(sino, d);
+        path = zshift(path, d);
+        view = zshift(view, d);
+        C = zshift(C, d);
+        tc.x = zshift(tc.x, d);
+        tc.part = zshift(tc.part, d);
+    }
     clear_back_pixels(tc, blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);   // side job
     const int slot = blockIdx.x, ch = blockIdx.y;
     const bool rev = view[slot].orient < 0.0f;
@@ -237,7 +254,18 @@ __global__ __launch_bounds__(kFwdWaves * 64) void k_dd_forward(const ViewParams*
                                                          const float* __restrict__ pre_rows,
                                                          const float* __restrict__ pre_cols, int nv0,
                                                          FrameSplit fs, const int* __restrict__ order, int chunks,
-                                                         int nx, int ny, int V, int B, float* __restrict__ sino) {
+                                                         int nx, int ny, int V, int B, float* __restrict__ sino,
+                                                         const long long* __restrict__ zd) {
+    if (zd) {                                                  // batched: this slice's buffers
+        const long long d = zoff(zd, Z_BLOCK);
+        view = zshift(view, d);
+        bound = zshift(bound, d);
+        path = zshift(path, d);
+        pre_rows = zshift(pre_rows, d);
+        pre_cols = zshift(pre_cols, d);
+        order = zshift(order, d);
+        sino = zshift(sino, d);
+    }
     int frame, item;
     if (!decode_block(fs, frame, item)) return;
     item = order[(frame ? fs.n_items[0] : 0) + item];             // heaviest items first
@@ -503,7 +531,15 @@ template <int NCH, int LPW, int U, int EPL>
 __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__ line_tab, int nv0, int nv1,
                                                       FrameSplit fs, int nx, int ny, int V, int B,
                                                       const DetEntry* __restrict__ C, float* __restrict__ x,
-                                                      float* __restrict__ part, int vsplit) {
+                                                      float* __restrict__ part, int vsplit,
+                                                      const long long* __restrict__ zd) {
+    if (zd) {                                                  // batched: this slice's buffers
+        const long long d = zoff(zd, Z_BLOCK);
+        line_tab = zshift(line_tab, d);
+        C = zshift(C, d);
+        x = zshift(x, d);
+        part = zshift(part, d);
+    }
     int frame, item;
     if (!decode_block(fs, frame, item)) return;
     const int Nq = frame ? nx : ny;
@@ -776,7 +812,12 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
 
 // x = (accumulate ? x : 0) + part, elementwise over n floats.
 __global__ __launch_bounds__(kThreads) void k_add_part(int n, const float* __restrict__ part, int accumulate,
-                                                       float* __restrict__ x) {
+                                                       float* __restrict__ x, const long long* __restrict__ zd) {
+    if (zd) {                                                  // batched: this slice's buffers
+        const long long d = zoff(zd, Z_BLOCK);
+        part = zshift(part, d);
+        x = zshift(x, d);
+    }
     const int i = blockIdx.x * kThreads + threadIdx.x;
     if (i < n) x[i] = accumulate ? x[i] + part[i] : part[i];
 }
@@ -802,8 +843,9 @@ void fwd_launch(const GeomTables& t, float* sino, hipStream_t s) {
     const float* cols = t.prefix + (size_t)t.prefix_mat * t.ny * prefix_row(t.nx);
     {
         KernelTimer kt_("k_dd_forward", s);
-        hipLaunchKernelGGL(k_dd_forward<NK>, dim3(grid_blocks(fs)), dim3(kFwdWaves * 64), 0, s, t.view, t.bound,
-                           t.path, rows, cols, t.n_frame_views[0], fs, t.fwd_order, chunks, t.nx, t.ny, t.V, t.B, sino);
+        hipLaunchKernelGGL(k_dd_forward<NK>, zgrid(dim3(grid_blocks(fs))), dim3(kFwdWaves * 64), 0, s, t.view,
+                           t.bound, t.path, rows, cols, t.n_frame_views[0], fs, t.fwd_order, chunks, t.nx, t.ny, t.V,
+                           t.B, sino, zarg());
         kt_.stop();
     }
     MBMD_LAUNCHED();
@@ -860,8 +902,8 @@ void back_kernel_launch(const GeomTables& t, float* x, hipStream_t s, int vsplit
     const int u1 = nv1 ? vsplit * back_main_items(t.ny, t.nx, LPW, ppw) + back_tail_items(t.ny, t.nx, ppw) : 0;
     const FrameSplit fs = split(u0, u1);
     KernelTimer kt_("k_dd_back", s);
-    hipLaunchKernelGGL((k_dd_back<NCH, LPW, U, EPL>), dim3(grid_blocks(fs)), dim3(kThreads), 0, s, t.back_line, nv0,
-                       nv1, fs, t.nx, t.ny, t.V, t.B, t.det_prefix, x, t.back_part, vsplit);
+    hipLaunchKernelGGL((k_dd_back<NCH, LPW, U, EPL>), zgrid(dim3(grid_blocks(fs))), dim3(kThreads), 0, s,
+                       t.back_line, nv0, nv1, fs, t.nx, t.ny, t.V, t.B, t.det_prefix, x, t.back_part, vsplit, zarg());
     kt_.stop();
 }
 
@@ -936,8 +978,8 @@ const float* back_launch(const GeomTables& t, const float* sino, float* x, hipSt
     // precedes every back projection kernel (the tuner's too).
     auto prefix = [&](const BackShape& sh) {
         KernelTimer kt_("k_detector_prefix", s);
-        hipLaunchKernelGGL(k_detector_prefix, dim3(t.V, NCH), dim3(kPrefixThreads), 0, s, sino, t.path, t.view,
-                           t.V, t.B, t.det_prefix, back_clear(t, x, NCH, sh));
+        hipLaunchKernelGGL(k_detector_prefix, zgrid(dim3(t.V, NCH)), dim3(kPrefixThreads), 0, s, sino, t.path,
+                           t.view, t.V, t.B, t.det_prefix, back_clear(t, x, NCH, sh), zarg());
         kt_.stop();
         MBMD_LAUNCHED();
     };
@@ -1056,8 +1098,9 @@ void launch_project(const GeomTables& t, const float* x, float* sino, int n_mat,
         const int line1 = t.n_frame_views[1] ? t.ny + t.nx : t.ny;
         float* cols = t.prefix + (size_t)t.prefix_mat * t.ny * prefix_row(t.nx);
         KernelTimer kt_("k_line_prefix", s);
-        hipLaunchKernelGGL(k_line_prefix, dim3(line1 - line0, n_mat), dim3(kScanThreads), 0, s, x, t.prefix, cols,
-                           t.nx, t.ny, line0, sino, n_mat * t.V * t.B);
+        hipLaunchKernelGGL(k_line_prefix, zgrid(dim3(line1 - line0, n_mat)), dim3(kScanThreads), 0, s, x, t.prefix,
+                           cols, t.nx, t.ny, line0, sino, n_mat * t.V * t.B, zarg(),
+                           (int)(zarg() && x == zbatch().x0));
         kt_.stop();
     }
     MBMD_LAUNCHED();
@@ -1146,7 +1189,8 @@ void launch_backproject(const GeomTables& t, const float* sino, float* x, int n_
     if (part) {
         const int n = n_ch * t.nx * t.ny;
         KernelTimer kt_("k_add_part", s);
-        hipLaunchKernelGGL(k_add_part, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, n, part, 1, x);
+        hipLaunchKernelGGL(k_add_part, zgrid(dim3((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, n, part, 1,
+                           x, zarg());
         kt_.stop();
         MBMD_LAUNCHED();
     }

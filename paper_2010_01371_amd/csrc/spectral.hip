@@ -36,6 +36,15 @@ struct RayModel {
     const float *Q, *S, *rowS, *Qsum;
 };
 
+// The model of slice d of a batched launch (its tables lie d bytes further).
+__device__ __forceinline__ RayModel zshift_model(RayModel m, long long d) {
+    m.Q = zshift(m.Q, d);
+    m.S = zshift(m.S, d);
+    m.rowS = zshift(m.rowS, d);
+    m.Qsum = zshift(m.Qsum, d);
+    return m;
+}
+
 // t = exp(-le) with the hardware base-2 exponential (one multiply and one
 // v_exp_f32, where expf takes about ten VALU for its range reduction): the
 // rounding of le log2(e) gives a relative error of about 1.2e-7 (1 + |le|
@@ -282,9 +291,27 @@ __global__ __launch_bounds__(kRayThreads) void k_ray_grad(RayModel m, int ni, co
                                                           const float* __restrict__ gammaA,
                                                           float* __restrict__ u, float* __restrict__ v,
                                                           float* __restrict__ r_out,
-                                                          double* __restrict__ partials, StepUpdate up, int nb_ray) {
+                                                          double* __restrict__ partials, StepUpdate up, int nb_ray,
+                                                          const long long* __restrict__ zd) {
     __shared__ double sh[kRayThreads / 64];
     __shared__ SharedModel sm;
+    if (zd) {                                              // batched: this slice's buffers and image
+        const long long d = zoff(zd, Z_BLOCK);
+        m = zshift_model(m, d);
+        l = zshift(l, d);
+        y = zshift(y, d);
+        w = zshift(w, d);
+        gammaA = zshift(gammaA, d);
+        u = zshift(u, d);
+        v = zshift(v, d);
+        r_out = zshift(r_out, d);
+        partials = zshift(partials, d);
+        up.alpha = zshift(up.alpha, d);
+        up.q = zshift(up.q, d);
+        up.l = zshift(up.l, d);
+        up.p = zshift(up.p, d);
+        up.x = zshift(up.x, zoff(zd, Z_IMAGE));
+    }
     if (up.alpha && (int)blockIdx.x >= nb_ray) {           // the image part of the step: x += alpha p
         const float a = (float)*up.alpha;
         const int i = ((int)blockIdx.x - nb_ray) * kRayThreads + threadIdx.x;
@@ -422,9 +449,22 @@ __global__ __launch_bounds__(kRayThreads) void k_curvature(RayModel m, int ni, c
                                                            const float* __restrict__ q, int nb_ray,
                                                            PenaltyArgs pa, const float* __restrict__ x,
                                                            const float* __restrict__ p,
-                                                           double* __restrict__ partials) {
+                                                           double* __restrict__ partials,
+                                                           const long long* __restrict__ zd) {
     __shared__ double sh[kRayThreads / 64];
     __shared__ SharedModel sm;
+    if (zd) {                                              // batched: this slice's buffers and image
+        const long long d = zoff(zd, Z_BLOCK);
+        m = zshift_model(m, d);
+        l = zshift(l, d);
+        r = zshift(r, d);
+        w = zshift(w, d);
+        q = zshift(q, d);
+        pa.beta = zshift(pa.beta, d);
+        x = zshift(x, zoff(zd, Z_IMAGE));
+        p = zshift(p, d);
+        partials = zshift(partials, d);
+    }
     const int b = blockIdx.x;
     double acc = 0.0;
     if (b < nb_ray) {                                      // uniform over the block
@@ -741,8 +781,8 @@ int launch_ray_grad(const RayArgs& a, const float* l, float* u, float* v, float*
     }
     {
         KernelTimer kt_("k_ray_grad", s);
-#define L_(KT, CT) hipLaunchKernelGGL((k_ray_grad<KT, CT>), dim3(nb + nb_img), dim3(kRayThreads), 0, s, model_of(a), \
-                                   a.ni, l, a.y, a.w, a.gammaA, u, v, r, phi_partials, upd, nb)
+#define L_(KT, CT) hipLaunchKernelGGL((k_ray_grad<KT, CT>), zgrid(dim3(nb + nb_img)), dim3(kRayThreads), 0, s,     \
+                                   model_of(a), a.ni, l, a.y, a.w, a.gammaA, u, v, r, phi_partials, upd, nb, zarg())
         MBMD_RAY_DISPATCH(a.K, a.C, L_);
 #undef L_
         kt_.stop();
@@ -797,8 +837,8 @@ void launch_curvature(const RayArgs& a, const float* l, const float* r, const fl
     const PenaltyArgs pa = pen ? *pen : PenaltyArgs{1, 0, 0, 0, nullptr, 0.0f};
     {
         KernelTimer kt_("k_curvature", s);
-#define L_(KT, CT) hipLaunchKernelGGL((k_curvature<KT, CT>), dim3(nb_ray + nb_pen), dim3(kRayThreads), 0, s,         \
-                                   model_of(a), a.ni, l, r, a.wb, q, nb_ray, pa, x, p, partials)
+#define L_(KT, CT) hipLaunchKernelGGL((k_curvature<KT, CT>), zgrid(dim3(nb_ray + nb_pen)), dim3(kRayThreads), 0, s, \
+                                   model_of(a), a.ni, l, r, a.wb, q, nb_ray, pa, x, p, partials, zarg())
         MBMD_RAY_DISPATCH(a.K, a.C, L_);
 #undef L_
         kt_.stop();
