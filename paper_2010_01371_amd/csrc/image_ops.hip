@@ -341,12 +341,12 @@ __global__ __launch_bounds__(dev::kReduceThreads) void k_reduce_final(const doub
                                                                       int* __restrict__ flags,
                                                                       const long long* __restrict__ zd) {
     __shared__ double sh[2 * kRegions];
-    if (zd) {                                              // batched: this slice's buffers
+    {                                                      // batched: this slice's buffers
         const long long d = zoff(zd, Z_BLOCK);
-        partials = zshift(partials, d);
-        scal = zshift(scal, d);
+        partials = zadd(partials, d);
+        scal = zadd(scal, d);
         trace_slot = zshift(trace_slot, d);
-        flags = zshift(flags, d);
+        flags = zadd(flags, d);
     }
     dev::region_sums(partials, counts, sh);
     if (threadIdx.x == 0) dev::form_scalars(sh, mode, scal, trace_slot, flags, true);

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <string>
 #include <vector>
+#include <type_traits>
 
 #include "../../include/mbmd.h"
 
@@ -102,9 +103,19 @@ enum { Z_BLOCK = 0, Z_IMAGE = 1 };
 __device__ __forceinline__ long long zoff(const long long* zd, int which) {
     return zd ? zd[2 * (int)blockIdx.z + which] : 0;
 }
+// Byte arithmetic on the pointer itself (not through an integer), so that the
+// compiler still sees a global-memory pointer based on the kernel argument:
+// it keeps global (not flat) accesses and, for zadd, its no-alias reasoning,
+// which lets read-only tables stay in scalar loads.  zadd is for pointers that
+// are never null (d is 0 outside a batch); zshift keeps a null pointer null.
+template <class T>
+__device__ __forceinline__ T* zadd(T* p, long long d) {
+    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return reinterpret_cast<T*>(reinterpret_cast<B*>(p) + d);
+}
 template <class T>
 __device__ __forceinline__ T* zshift(T* p, long long d) {
-    return p ? reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + (uintptr_t)d) : p;
+    return p ? zadd(p, d) : p;
 }
 
 // ---------------------------------------------------------------- device memory arena

@@ -533,11 +533,11 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
                                                       const DetEntry* __restrict__ C, float* __restrict__ x,
                                                       float* __restrict__ part, int vsplit,
                                                       const long long* __restrict__ zd) {
-    if (zd) {                                                  // batched: this slice's buffers
+    {                                                          // batched: this slice's buffers
         const long long d = zoff(zd, Z_BLOCK);
-        line_tab = zshift(line_tab, d);
-        C = zshift(C, d);
-        x = zshift(x, d);
+        line_tab = zadd(line_tab, d);
+        C = zadd(C, d);
+        x = zadd(x, d);
         part = zshift(part, d);
     }
     int frame, item;
