@@ -51,8 +51,11 @@
 // back projection is written in image layout to a buffer of its own and added
 // by the caller (the iteration does it in the penalty pass).
 #include <cmath>
-#include <type_traits>
 #include <cstdlib>
+#include <map>
+#include <mutex>
+#include <string>
+#include <type_traits>
 
 #include "back_rows.h"
 #include "internal.h"
@@ -877,6 +880,29 @@ bool autotune_enabled() {
     return on;
 }
 
+// Shapes chosen by the tuner, by device, geometry and channel count, so that
+// problems of one geometry (the slices of a batch, repeated problems) time the
+// candidates once per process.  Every shape gives the same bits, so sharing
+// the choice only saves the timing runs.
+std::string tuned_key(const GeomTables& t, int nch) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const mbmd_geometry& g = t.g;
+    const double f[] = {(double)dev, (double)nch, (double)g.kind, (double)g.nx, (double)g.ny, g.dx, g.dy,
+                        (double)g.n_views, g.theta0, g.dtheta, (double)g.n_bins, g.du, g.u_offset, g.dso, g.dsd};
+    return std::string(reinterpret_cast<const char*>(f), sizeof(f));
+}
+std::mutex g_tuned_mu;
+std::map<std::string, int> g_tuned;
+int tuned_lookup(const GeomTables& t, int nch) {
+    std::lock_guard<std::mutex> lock(g_tuned_mu);
+    const auto it = g_tuned.find(tuned_key(t, nch));
+    return it == g_tuned.end() ? -1 : it->second;
+}
+void tuned_store(const GeomTables& t, int nch, int v) {
+    std::lock_guard<std::mutex> lock(g_tuned_mu);
+    g_tuned[tuned_key(t, nch)] = v;
+}
 
 // Relative time of a back projection launch with LPW lines per wavefront:
 // rounds of resident waves, each lasting the longer of the per-view latency
@@ -1002,7 +1028,10 @@ const float* back_launch(const GeomTables& t, const float* sino, float* x, hipSt
     if (choice < 0) {
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
         MBMD_HIP(hipStreamIsCapturing(s, &cap));
-        if (cap == hipStreamCaptureStatusNone && autotune_enabled()) {
+        const int known = autotune_enabled() ? tuned_lookup(t, NCH) : -1;
+        if (known >= 0 && known < n_cand) {
+            choice = known;                            // timed before for this geometry
+        } else if (cap == hipStreamCaptureStatusNone && autotune_enabled()) {
             hipEvent_t ev[2];
             MBMD_HIP(hipEventCreate(&ev[0]));
             MBMD_HIP(hipEventCreate(&ev[1]));
@@ -1026,6 +1055,7 @@ const float* back_launch(const GeomTables& t, const float* sino, float* x, hipSt
                 if (best[v] < best[choice]) choice = v;
             (void)hipEventDestroy(ev[0]);
             (void)hipEventDestroy(ev[1]);
+            tuned_store(t, NCH, choice);
         } else {
             int cus = 0, dev = 0;
             MBMD_HIP(hipGetDevice(&dev));
