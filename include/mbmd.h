@@ -31,6 +31,11 @@
  *   - `stream` is a hipStream_t (NULL = the default stream).  All work is
  *     enqueued on it asynchronously unless a *_host output is requested,
  *     in which case the call synchronizes that stream before returning.
+ *     Three set-up steps also wait: problem creation (for its table
+ *     uploads), the first back projection of a geometry and channel count
+ *     in the process outside graph capture (it times the candidate tile
+ *     shapes, which give identical results, on its own inputs), and a batch
+ *     call whose grouping of problems changed (for its offsets table).
  *   - Return value: MBMD_OK (0) or a negative mbmd_status.  No exception
  *     crosses this interface.  mbmd_last_error() returns a thread-local
  *     message for the last failure.  Numeric failures of kernels already

@@ -194,3 +194,27 @@ def test_back_projector_tile_shapes_agree(name, nch, monkeypatch):
     for o in outs[1:]:
         np.testing.assert_array_equal(o, outs[0])
     assert maxrel(outs[0], OP.backproject(g, s)) <= TOL_PROJ
+
+
+def test_tuned_shape_is_timed_once_per_geometry():
+    """The back projector times its candidate tile shapes on the first back
+    projection of a geometry and channel count in the process; tables built
+    again for that geometry (here after mbmd_cache_clear) take the recorded
+    choice without timing, and give the same bits."""
+    g = C.geometry("fan", 150, 140, 0.9, 0.9, 84, 2 * np.pi, 190, 1.0, dso=400.0, dsd=700.0)
+    s = dev(np.random.default_rng(11).uniform(size=(1, g["n_views"], g["n_bins"])))
+    announce("back projector tuning once per geometry")
+    mb.cache_clear()
+    with mb.KernelProfile(only=["k_dd_back"]) as prof:
+        first = host(mb.backproject(g, s))
+        torch.cuda.synchronize()
+        n_first, _ = prof.query("k_dd_back")
+    mb.cache_clear()
+    with mb.KernelProfile(only=["k_dd_back"]) as prof:
+        second = host(mb.backproject(g, s))
+        torch.cuda.synchronize()
+        n_second, _ = prof.query("k_dd_back")
+    mb.cache_clear()
+    assert n_first > 20, n_first                 # warm-up and four timed rounds of every shape
+    assert n_second == 1, n_second
+    np.testing.assert_array_equal(first, second)
