@@ -13,6 +13,7 @@
 // Block operations: per-pixel (or per-frequency) symmetric N_k x N_k
 // matrices are stored packed, component-major ([npk][n]) so that loads
 // coalesce.  Inverse square roots use FP64 cyclic Jacobi (N_k <= 4).
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 
@@ -176,8 +177,11 @@ __global__ __launch_bounds__(kThreads) void k_dot(int n, const float* __restrict
         b = zshift(b, d);
         partials = zshift(partials, d);
     }
-    const int i = blockIdx.x * kThreads + threadIdx.x;
-    const double v = i < n ? (double)a[i] * (double)b[i] : 0.0;
+    // one element per thread up to kMaxPartials blocks; longer vectors (several
+    // materials at the largest images) add further elements in a fixed order
+    double v = 0.0;
+    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads)
+        v += (double)a[i] * (double)b[i];
     const double tot = block_sum(v, sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
@@ -476,8 +480,7 @@ void launch_scale_copy(int n, const float* in, float* out, float scale, hipStrea
 }
 
 int launch_dot(int n, const float* a, const float* b, double* partials, hipStream_t s) {
-    const int nb = nblk(n);
-    MBMD_REQUIRE(nb <= kMaxPartials, MBMD_ERR_SHAPE, "vector too long for the partial-sum buffer");
+    const int nb = std::min(nblk(n), kMaxPartials);
     {
         KernelTimer kt_("k_dot", s);
         hipLaunchKernelGGL(k_dot, zgrid(dim3(nb)), dim3(kThreads), 0, s, n, a, b, partials, zarg());

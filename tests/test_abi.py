@@ -78,3 +78,21 @@ def test_workspace_bytes_without_a_gpu():
     Q5 = np.ones((3, 5))
     with pytest.raises(_lib.MbmdError):
         api.workspace_bytes(wl.geom, Q5, np.ones((1, 3)))    # five materials
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmbmd.so not built (run __graft_entry__.build())")
+def test_largest_image_is_sized_and_one_more_column_is_refused():
+    """The partial-sum buffers hold one sum per 256 pixels or rays in 16384
+    slots: 2048 x 2048 pixels is the largest image a problem accepts (its
+    workspace is sized on the host), and one more column is MBMD_ERR_SHAPE."""
+    import numpy as np
+    from paper_2010_01371_amd import api, _lib
+    from workloads import configs as C
+    g = C.geometry("parallel", 2048, 2048, 0.25, 0.25, 180, np.pi, 2900, 0.25)
+    Q, S = np.ones((4, 2)), np.ones((2, 4))
+    assert api.workspace_bytes(g, Q, S) > 2 * 2 * 2048 * 2048 * 4
+    with pytest.raises(_lib.MbmdError) as e:
+        api.workspace_bytes(dict(g, nx=2049), Q, S)
+    assert e.value.status == -2
+    with pytest.raises(_lib.MbmdError):
+        api.workspace_bytes(dict(g, n_views=1447, n_bins=2900), Q, S)   # more than 2^22 rays
