@@ -416,10 +416,9 @@ int mbmd_batch_workspace_bytes(mbmd_problem* const* probs, int n, size_t* bytes_
  * slices per call).  The problems are borrowed and must outlive the batch.
  * Problems whose launch parameters are all equal -- same geometry, sizes,
  * penalty kind and block layout (same workspace flags), no blur -- form a
- * class: for the plain, Fourier and block-diagonal iterations every kernel
- * runs once per class and iteration, each workgroup working on one member
- * (the per-member byte offsets of the problem blocks and images live in the
- * batch's workspace); other problems and other preconditioners get launches of
+ * class: every kernel of an iteration runs once per class, each workgroup
+ * working on one member (the per-member byte offsets of the problem blocks and
+ * images live in the batch's workspace); problems with a blur get launches of
  * their own.  Classes and lone problems are dealt round-robin onto up to 4
  * library-owned streams (default priority) forked from the caller's stream and
  * joined back into it.

@@ -608,9 +608,9 @@ std::string batch_class_key(const Problem& P) {
     return std::string(reinterpret_cast<const char*>(f), sizeof(f));
 }
 
-// Preconditioners whose apply kernels have the batched form.
+// Preconditioners whose apply kernels have the batched form (all of them).
 bool shares_launches(int precond) {
-    return precond == MBMD_PRECOND_NONE || precond == MBMD_PRECOND_FOURIER || precond == MBMD_PRECOND_BLOCKDIAG;
+    return precond >= MBMD_PRECOND_NONE && precond < kPreconds;
 }
 
 }  // namespace

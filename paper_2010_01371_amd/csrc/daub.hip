@@ -68,7 +68,13 @@ __device__ __forceinline__ float d4_line(const D4Filter& f, const float* src, in
 // (src and dst [K][n][n], only the block is written): along rows or along
 // columns, one thread per output, consecutive threads on consecutive columns.
 __global__ __launch_bounds__(kThreads) void k_d4_pass(D4Filter f, int n, int m, int along_rows, int inverse,
-                                                       const float* __restrict__ src, float* __restrict__ dst) {
+                                                       const float* __restrict__ src, float* __restrict__ dst,
+                                                       const long long* __restrict__ zd) {
+    {                                                      // batched: this slice's buffers
+        const long long d = zoff(zd, Z_BLOCK);
+        src = zadd(src, d);
+        dst = zadd(dst, d);
+    }
     const int t = blockIdx.x * kThreads + threadIdx.x;
     if (t >= m * m) return;
     const int r = t / m, c = t - r * m;
@@ -82,8 +88,10 @@ __global__ __launch_bounds__(kThreads) void k_d4_pass(D4Filter f, int n, int m, 
 // pass goes A -> B and its second B -> A, so a level ends in A; entries of B
 // outside the current block are stale but never read.
 __global__ __launch_bounds__(kCoarseThreads) void k_d4_coarse(D4Filter f, int n, int T, int inverse,
-                                                             float* __restrict__ a) {
+                                                             float* __restrict__ a,
+                                                             const long long* __restrict__ zd) {
     __shared__ float A[kCoarse * kCoarse], B[kCoarse * kCoarse];
+    a = zadd(a, zoff(zd, Z_BLOCK));                        // batched: this slice's buffer
     float* img = a + (size_t)blockIdx.x * n * n;
     for (int t = threadIdx.x; t < T * T; t += kCoarseThreads) A[t] = img[(size_t)(t / T) * n + t % T];
     __syncthreads();
@@ -114,8 +122,8 @@ void level(const D4Filter& f, int K, int n, int m, bool inverse, float* x, float
     for (int pass = 0; pass < 2; ++pass) {
         const bool rows = (pass == 0) != inverse;
         KernelTimer kt_("k_d4_pass", s);
-        hipLaunchKernelGGL(k_d4_pass, dim3((m * m + kThreads - 1) / kThreads, K), dim3(kThreads), 0, s, f, n, m,
-                           rows ? 1 : 0, inverse ? 1 : 0, pass == 0 ? x : y, pass == 0 ? y : x);
+        hipLaunchKernelGGL(k_d4_pass, zgrid(dim3((m * m + kThreads - 1) / kThreads, K)), dim3(kThreads), 0, s, f, n,
+                           m, rows ? 1 : 0, inverse ? 1 : 0, pass == 0 ? x : y, pass == 0 ? y : x, zarg());
         kt_.stop();
         MBMD_LAUNCHED();
     }
@@ -124,8 +132,8 @@ void level(const D4Filter& f, int K, int n, int m, bool inverse, float* x, float
 void coarse(const D4Filter& f, int K, int n, bool inverse, float* a, hipStream_t s) {
     {
         KernelTimer kt_("k_d4_coarse", s);
-        hipLaunchKernelGGL(k_d4_coarse, dim3(K), dim3(kCoarseThreads), 0, s, f, n, std::min(n, kCoarse),
-                           inverse ? 1 : 0, a);
+        hipLaunchKernelGGL(k_d4_coarse, zgrid(dim3(K)), dim3(kCoarseThreads), 0, s, f, n, std::min(n, kCoarse),
+                           inverse ? 1 : 0, a, zarg());
         kt_.stop();
     }
     MBMD_LAUNCHED();

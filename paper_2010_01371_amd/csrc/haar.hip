@@ -85,8 +85,16 @@ __device__ __forceinline__ size_t detail_index(int quad, int i, int jj, int ty, 
 __global__ __launch_bounds__(kThreads) void k_haar_fwd_tile(int K, int n, int T, const float* __restrict__ in,
                                                             const float* __restrict__ M,
                                                             float* __restrict__ coef,
-                                                            float* __restrict__ coarse) {
+                                                            float* __restrict__ coarse,
+                                                            const long long* __restrict__ zd) {
     extern __shared__ float lds[];
+    {                                                      // batched: this slice's buffers
+        const long long d = zoff(zd, Z_BLOCK);
+        in = zadd(in, d);
+        M = zshift(M, d);
+        coef = zadd(coef, d);
+        coarse = zadd(coarse, d);
+    }
     float* cur = lds;
     float* nxt = lds + K * T * T;
     const int tx = blockIdx.x, ty = blockIdx.y, nt = n / T;
@@ -124,9 +132,19 @@ __global__ __launch_bounds__(kThreads) void k_haar_inv_tile(int K, int n, int T,
                                                             const float* __restrict__ M, float sign,
                                                             float* __restrict__ out,
                                                             const float* __restrict__ g,
-                                                            double* __restrict__ partials) {
+                                                            double* __restrict__ partials,
+                                                            const long long* __restrict__ zd) {
     extern __shared__ float lds[];
     __shared__ double sh[kThreads / 64];
+    {                                                      // batched: this slice's buffers
+        const long long d = zoff(zd, Z_BLOCK);
+        coef = zadd(coef, d);
+        coarse = zadd(coarse, d);
+        M = zshift(M, d);
+        out = zadd(out, d);
+        g = zshift(g, d);
+        partials = zshift(partials, d);
+    }
     float* cur = lds;
     float* nxt = lds + K * T * T;
     const int tx = blockIdx.x, ty = blockIdx.y, nt = n / T;
@@ -166,8 +184,14 @@ __global__ __launch_bounds__(kThreads) void k_haar_inv_tile(int K, int n, int T,
 // Remaining levels on the nc x nc coarse image; its Mallat layout is the
 // top-left nc x nc block of the global one.
 __global__ __launch_bounds__(kThreads) void k_haar_coarse_fwd(int K, int n, int nc, const float* __restrict__ coarse,
-                                                              float* __restrict__ coef) {
+                                                              float* __restrict__ coef,
+                                                              const long long* __restrict__ zd) {
     extern __shared__ float lds[];
+    {                                                      // batched: this slice's buffers
+        const long long d = zoff(zd, Z_BLOCK);
+        coarse = zadd(coarse, d);
+        coef = zadd(coef, d);
+    }
     float* cur = lds;
     float* nxt = lds + K * nc * nc;
     const int nj = n * n;
@@ -181,8 +205,14 @@ __global__ __launch_bounds__(kThreads) void k_haar_coarse_fwd(int K, int n, int 
 }
 
 __global__ __launch_bounds__(kThreads) void k_haar_coarse_inv(int K, int n, int nc, const float* __restrict__ coef,
-                                                              float* __restrict__ coarse) {
+                                                              float* __restrict__ coarse,
+                                                              const long long* __restrict__ zd) {
     extern __shared__ float lds[];
+    {                                                      // batched: this slice's buffers
+        const long long d = zoff(zd, Z_BLOCK);
+        coef = zadd(coef, d);
+        coarse = zadd(coarse, d);
+    }
     float* cur = lds;
     float* nxt = lds + K * nc * nc;
     const int nj = n * n;
@@ -220,15 +250,15 @@ void launch_haar_forward(int K, int n, const float* in, const float* M, float* c
     const int T = haar_tile(n), nt = n / T;
     {
         KernelTimer kt_("k_haar_fwd_tile", s);
-        hipLaunchKernelGGL(k_haar_fwd_tile, dim3(nt, nt), dim3(kThreads), sizeof(float) * 2 * K * T * T, s, K, n, T,
-                       in, M, coef, coarse);
+        hipLaunchKernelGGL(k_haar_fwd_tile, zgrid(dim3(nt, nt)), dim3(kThreads), sizeof(float) * 2 * K * T * T, s, K, n,
+                           T, in, M, coef, coarse, zarg());
         kt_.stop();
     }
     MBMD_LAUNCHED();
     {
         KernelTimer kt_("k_haar_coarse_fwd", s);
-        hipLaunchKernelGGL(k_haar_coarse_fwd, dim3(1), dim3(kThreads), sizeof(float) * 2 * K * nt * nt, s, K, n, nt,
-                       coarse, coef);
+        hipLaunchKernelGGL(k_haar_coarse_fwd, zgrid(dim3(1)), dim3(kThreads), sizeof(float) * 2 * K * nt * nt, s, K, n,
+                           nt, coarse, coef, zarg());
         kt_.stop();
     }
     MBMD_LAUNCHED();
@@ -240,15 +270,16 @@ void launch_haar_inverse(int K, int n, const float* coef, float* coarse, const f
     const int T = haar_tile(n), nt = n / T;
     {
         KernelTimer kt_("k_haar_coarse_inv", s);
-        hipLaunchKernelGGL(k_haar_coarse_inv, dim3(1), dim3(kThreads), sizeof(float) * 2 * K * nt * nt, s, K, n, nt,
-                       coef, coarse);
+        hipLaunchKernelGGL(k_haar_coarse_inv, zgrid(dim3(1)), dim3(kThreads), sizeof(float) * 2 * K * nt * nt, s, K, n,
+                           nt, coef, coarse, zarg());
         kt_.stop();
     }
     MBMD_LAUNCHED();
     {
         KernelTimer kt_("k_haar_inv_tile", s);
-        hipLaunchKernelGGL(k_haar_inv_tile, dim3(nt, nt), dim3(kThreads), sizeof(float) * 2 * K * T * T, s, K, n, T,
-                       coef, (const float*)coarse, M, out_sign, out, (const float*)nullptr, (double*)nullptr);
+        hipLaunchKernelGGL(k_haar_inv_tile, zgrid(dim3(nt, nt)), dim3(kThreads), sizeof(float) * 2 * K * T * T, s, K, n,
+                           T, coef, (const float*)coarse, M, out_sign, out, (const float*)nullptr, (double*)nullptr,
+                           zarg());
         kt_.stop();
     }
     MBMD_LAUNCHED();
@@ -263,15 +294,15 @@ int launch_haar_apply(int K, int n, const float* in, const float* M, const float
     launch_block_apply(n * n, K, Kinv, coef, coef, 1.0f, s);
     {
         KernelTimer kt_("k_haar_coarse_inv", s);
-        hipLaunchKernelGGL(k_haar_coarse_inv, dim3(1), dim3(kThreads), sizeof(float) * 2 * K * nt * nt, s, K, n, nt,
-                       coef, coarse);
+        hipLaunchKernelGGL(k_haar_coarse_inv, zgrid(dim3(1)), dim3(kThreads), sizeof(float) * 2 * K * nt * nt, s, K, n,
+                           nt, coef, coarse, zarg());
         kt_.stop();
     }
     MBMD_LAUNCHED();
     {
         KernelTimer kt_("k_haar_inv_tile", s);
-        hipLaunchKernelGGL(k_haar_inv_tile, dim3(nt, nt), dim3(kThreads), sizeof(float) * 2 * K * T * T, s, K, n, T,
-                       coef, (const float*)coarse, M, out_sign, out, g, partials);
+        hipLaunchKernelGGL(k_haar_inv_tile, zgrid(dim3(nt, nt)), dim3(kThreads), sizeof(float) * 2 * K * T * T, s, K, n,
+                           T, coef, (const float*)coarse, M, out_sign, out, g, partials, zarg());
         kt_.stop();
     }
     MBMD_LAUNCHED();

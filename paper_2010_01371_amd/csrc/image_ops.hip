@@ -147,7 +147,13 @@ __global__ void k_fill(int n, float* __restrict__ x, float value, const long lon
     if (i < n) x[i] = value;
 }
 
-__global__ void k_scale_copy(int n, const float* __restrict__ in, float* __restrict__ out, float scale) {
+__global__ void k_scale_copy(int n, const float* __restrict__ in, float* __restrict__ out, float scale,
+                             const long long* __restrict__ zd) {
+    {                                                      // batched: this slice's buffers
+        const long long d = zoff(zd, Z_BLOCK);
+        in = zadd(in, d);
+        out = zadd(out, d);
+    }
     const int i = blockIdx.x * kThreads + threadIdx.x;
     if (i < n) out[i] = scale * in[i];
 }
@@ -473,7 +479,7 @@ void launch_block_add_column(int nj, int K, int k_col, const float* col, float* 
 void launch_scale_copy(int n, const float* in, float* out, float scale, hipStream_t s) {
     {
         KernelTimer kt_("k_scale_copy", s);
-        hipLaunchKernelGGL(k_scale_copy, dim3(nblk(n)), dim3(kThreads), 0, s, n, in, out, scale);
+        hipLaunchKernelGGL(k_scale_copy, zgrid(dim3(nblk(n))), dim3(kThreads), 0, s, n, in, out, scale, zarg());
         kt_.stop();
     }
     MBMD_LAUNCHED();

@@ -66,7 +66,8 @@ bool batched_form(const char* name) {
                                         "k_detector_prefix", "k_dd_back", "k_penalty_grad", "k_fft_rows_fwd",
                                         "k_fft_cols", "k_fft_rows_inv", "k_reduce_final", "k_axpy2_alpha",
                                         "k_fill_double", "k_block_apply", "k_dot", "k_plain_update", "k_fill",
-                                        "k_add_part"};
+                                        "k_add_part", "k_scale_copy", "k_haar_fwd_tile", "k_haar_coarse_fwd",
+                                        "k_haar_coarse_inv", "k_haar_inv_tile", "k_d4_pass", "k_d4_coarse"};
     for (const char* n : names)
         if (std::strcmp(n, name) == 0) return true;
     return false;

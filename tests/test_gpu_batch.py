@@ -43,7 +43,7 @@ def _reference(wls, kind, calls, blur=None, edit=None):
     return refs
 
 
-@pytest.mark.parametrize("kind", ["fourier", "none", "blockdiag", "daub4"])
+@pytest.mark.parametrize("kind", ["fourier", "none", "blockdiag", "haar", "daub4"])
 def test_batch_matches_single_problem_iterations(kind):
     _batch_vs_single(kind)
 
@@ -85,7 +85,7 @@ def _batch_vs_single(kind, blur=None):
         p.close()
 
 
-@pytest.mark.parametrize("kind", ["fourier", "none", "blockdiag"])
+@pytest.mark.parametrize("kind", ["fourier", "none", "blockdiag", "haar", "daub4"])
 def test_shared_launches_read_each_members_own_data(kind):
     """Members of one class (same geometry and sizes) with different penalty
     weights and spectra: the shared launches must read every member's own
