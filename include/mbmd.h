@@ -415,13 +415,14 @@ int mbmd_batch_workspace_bytes(mbmd_problem* const* probs, int n, size_t* bytes_
  * batched iteration (the serving form of the one-step MBMD iteration: many
  * slices per call).  The problems are borrowed and must outlive the batch.
  * Problems whose launch parameters are all equal -- same geometry, sizes,
- * penalty kind and block layout (same workspace flags), no blur -- form a
- * class: every kernel of an iteration runs once per class, each workgroup
- * working on one member (the per-member byte offsets of the problem blocks and
- * images live in the batch's workspace); problems with a blur get launches of
- * their own.  Classes and lone problems are dealt round-robin onto up to 4
- * library-owned streams (default priority) forked from the caller's stream and
- * joined back into it.
+ * penalty kind, blur taps and block layout (same workspace flags, every
+ * buffer inside the block) -- form a class: every kernel of an iteration runs
+ * once per class, each workgroup working on one member (the per-member byte
+ * offsets of the problem blocks and images live in the batch's workspace).  A
+ * problem whose blur buffers were grown outside its block (a library block
+ * created without MBMD_WORKSPACE_BLUR) gets launches of its own.  Classes and
+ * lone problems are dealt round-robin onto up to 4 library-owned streams
+ * (default priority) forked from the caller's stream and joined back into it.
  *   - workspace_dev: NULL (the library allocates) or caller-owned device memory
  *     of mbmd_batch_workspace_bytes, 256-byte aligned, kept until destroy;
  *   - flags: 0 or MBMD_BATCH_SEPARATE_LAUNCHES.

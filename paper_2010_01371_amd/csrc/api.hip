@@ -596,16 +596,39 @@ struct ZScope {
     ZScope& operator=(const ZScope&) = delete;
 };
 
+// Byte offset of a device buffer in the problem's block; -1 for none, and a
+// value no other problem shares when the buffer lies outside the block (blur
+// buffers grown after creation in a library block sized without their room).
+long long block_offset(const Problem& P, const void* p) {
+    if (!p) return -1;
+    const uintptr_t b = reinterpret_cast<uintptr_t>(P.arena.base), a = reinterpret_cast<uintptr_t>(p);
+    if (a >= b && a < b + P.arena.size) return (long long)(a - b);
+    return -2 - (long long)a;
+}
+
 // Problems whose iterations can share launches: every host-side launch
-// parameter equal (geometry, sizes, penalty kind and delta, block layout) and
-// no blur.  Everything else a kernel reads lives in the problem's block.
+// parameter equal (geometry, sizes, penalty kind and delta, blur taps) and
+// every device buffer at the same offset of the problem's block, so that one
+// byte offset per member moves all of the first member's pointers onto it.
 std::string batch_class_key(const Problem& P) {
     const mbmd_geometry& g = P.g;
-    const double f[] = {(double)g.kind, (double)g.nx, (double)g.ny, g.dx, g.dy, (double)g.n_views, g.theta0,
-                        g.dtheta, (double)g.n_bins, g.du, g.u_offset, g.dso, g.dsd, (double)P.K, (double)P.E,
-                        (double)P.C, (double)P.pen_kind, (double)P.has_penalty, (double)(float)P.delta,
-                        (double)P.ws_flags, (double)P.arena.used, (double)P.blur.h, (double)P.fuse_rows};
-    return std::string(reinterpret_cast<const char*>(f), sizeof(f));
+    std::vector<double> f = {(double)g.kind, (double)g.nx, (double)g.ny, g.dx, g.dy, (double)g.n_views, g.theta0,
+                             g.dtheta, (double)g.n_bins, g.du, g.u_offset, g.dso, g.dsd, (double)P.K, (double)P.E,
+                             (double)P.C, (double)P.pen_kind, (double)P.has_penalty, (double)(float)P.delta,
+                             (double)P.ws_flags, (double)P.fuse_rows, (double)P.blur.h, (double)P.blur.B};
+    for (int c = 0; c < kMaxChan; ++c)
+        for (int t = 0; t < 2 * P.blur.h + 1; ++t) f.push_back((double)P.blur.taps[c][t]);
+    const void* bufs[] = {P.geom_mem, P.Q,      P.S,      P.rowS,  P.Qsum,   P.beta_d, P.y,     P.w,
+                          P.gammaA,   P.l,      P.q,      P.u,     P.v,      P.r,      P.sino_tmp, P.g_img,
+                          P.d_img,    P.p_img,  P.t_img,  P.t2_img, P.dL_const, P.M0,  P.Linv,  P.Kinv,
+                          P.Dinv,     P.W,      P.wb,     P.J,     P.btmp0,  P.btmp1,  P.spec,  P.tw_x,
+                          P.tw_y,     P.coef,   P.coarse, P.partials, P.scal, P.flags};
+    std::string key(reinterpret_cast<const char*>(f.data()), sizeof(double) * f.size());
+    for (const void* b : bufs) {
+        const long long o = block_offset(P, b);
+        key.append(reinterpret_cast<const char*>(&o), sizeof(o));
+    }
+    return key;
 }
 
 // Preconditioners whose apply kernels have the batched form (all of them).
@@ -1029,7 +1052,7 @@ int mbmd_batch_sps_step(mbmd_batch* b, float* const* x_dev, int precond, int n_i
             b->unit_first.clear();
             std::vector<std::string> keys;         // per unit: its class key, empty for a lone problem
             for (size_t i = 0; i < n; ++i) {
-                const bool can = b->shared && shares_launches(precond) && b->probs[i]->blur.h == 0;
+                const bool can = b->shared && shares_launches(precond);
                 const std::string key = can ? batch_class_key(*b->probs[i]) : std::string();
                 size_t u = can ? (size_t)(std::find(keys.begin(), keys.end(), key) - keys.begin()) : keys.size();
                 if (u == keys.size()) {

@@ -67,7 +67,8 @@ bool batched_form(const char* name) {
                                         "k_fft_cols", "k_fft_rows_inv", "k_reduce_final", "k_axpy2_alpha",
                                         "k_fill_double", "k_block_apply", "k_dot", "k_plain_update", "k_fill",
                                         "k_add_part", "k_scale_copy", "k_haar_fwd_tile", "k_haar_coarse_fwd",
-                                        "k_haar_coarse_inv", "k_haar_inv_tile", "k_d4_pass", "k_d4_coarse"};
+                                        "k_haar_coarse_inv", "k_haar_inv_tile", "k_d4_pass", "k_d4_coarse",
+                                        "k_ray_means", "k_blur_resid", "k_ray_grad_r"};
     for (const char* n : names)
         if (std::strcmp(n, name) == 0) return true;
     return false;

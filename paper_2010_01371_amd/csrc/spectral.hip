@@ -180,8 +180,20 @@ __device__ __forceinline__ float blur_at(const BlurArgs& b, const float* __restr
 // channel means ybar0_c = sum_E S_cE t_E of every ray.
 template <int KT, int CT>
 __global__ __launch_bounds__(kRayThreads) void k_ray_means(RayModel m, int ni, const float* __restrict__ l,
-                                                           float* __restrict__ ybar0, StepUpdate up, int nb_ray) {
+                                                           float* __restrict__ ybar0, StepUpdate up, int nb_ray,
+                                                           const long long* __restrict__ zd) {
     __shared__ SharedModel sm;
+    if (zd) {                                              // batched: this slice's buffers and image
+        const long long d = zoff(zd, Z_BLOCK);
+        m = zshift_model(m, d);
+        l = zshift(l, d);
+        ybar0 = zshift(ybar0, d);
+        up.alpha = zshift(up.alpha, d);
+        up.q = zshift(up.q, d);
+        up.l = zshift(up.l, d);
+        up.p = zshift(up.p, d);
+        up.x = zshift(up.x, zoff(zd, Z_IMAGE));
+    }
     if (up.alpha && (int)blockIdx.x >= nb_ray) {           // the image part of the step: x += alpha p
         const float a = (float)*up.alpha;
         const int i = ((int)blockIdx.x - nb_ray) * kRayThreads + threadIdx.x;
@@ -206,8 +218,17 @@ __global__ __launch_bounds__(kRayThreads) void k_blur_resid(BlurArgs b, int ni, 
                                                             const float* __restrict__ y,
                                                             const float* __restrict__ w,
                                                             float* __restrict__ rres,
-                                                            double* __restrict__ partials) {
+                                                            double* __restrict__ partials,
+                                                            const long long* __restrict__ zd) {
     __shared__ double sh[kRayThreads / 64];
+    if (zd) {                                              // batched: this slice's buffers
+        const long long d = zoff(zd, Z_BLOCK);
+        ybar0 = zshift(ybar0, d);
+        y = zshift(y, d);
+        w = zshift(w, d);
+        rres = zshift(rres, d);
+        partials = zshift(partials, d);
+    }
     const int i = blockIdx.x * kRayThreads + threadIdx.x;
     double phi = 0.0;
     if (i < ni) {
@@ -231,8 +252,20 @@ __global__ __launch_bounds__(kRayThreads) void k_ray_grad_r(RayModel m, int ni, 
                                                             const float* __restrict__ wb,
                                                             const float* __restrict__ gammaA, BlurArgs b,
                                                             float* __restrict__ u, float* __restrict__ v,
-                                                            float* __restrict__ r_out) {
+                                                            float* __restrict__ r_out,
+                                                            const long long* __restrict__ zd) {
     __shared__ SharedModel sm;
+    if (zd) {                                              // batched: this slice's buffers
+        const long long d = zoff(zd, Z_BLOCK);
+        m = zshift_model(m, d);
+        l = zshift(l, d);
+        rres = zshift(rres, d);
+        wb = zshift(wb, d);
+        gammaA = zshift(gammaA, d);
+        u = zshift(u, d);
+        v = zshift(v, d);
+        r_out = zshift(r_out, d);
+    }
     stage_model<KT, CT>(m, sm);
     const int K = KT ? KT : m.K, C = CT ? CT : m.C;
     const int i = blockIdx.x * kRayThreads + threadIdx.x;
@@ -754,8 +787,8 @@ int launch_ray_grad(const RayArgs& a, const float* l, float* u, float* v, float*
                      "blurred ray pass without its buffers");
         {
             KernelTimer kt_("k_ray_means", s);
-#define L_(KT, CT) hipLaunchKernelGGL((k_ray_means<KT, CT>), dim3(nb + nb_img), dim3(kRayThreads), 0, s, \
-                                   model_of(a), a.ni, l, a.tmp0, upd, nb)
+#define L_(KT, CT) hipLaunchKernelGGL((k_ray_means<KT, CT>), zgrid(dim3(nb + nb_img)), dim3(kRayThreads), 0, s, \
+                                   model_of(a), a.ni, l, a.tmp0, upd, nb, zarg())
             MBMD_RAY_DISPATCH(a.K, a.C, L_);
 #undef L_
             kt_.stop();
@@ -763,15 +796,15 @@ int launch_ray_grad(const RayArgs& a, const float* l, float* u, float* v, float*
         MBMD_LAUNCHED();
         {
             KernelTimer kt_("k_blur_resid", s);
-            hipLaunchKernelGGL(k_blur_resid, dim3(nb), dim3(kRayThreads), 0, s, a.blur, a.ni, a.C, a.tmp0, a.y,
-                               a.w, a.tmp1, phi_partials);
+            hipLaunchKernelGGL(k_blur_resid, zgrid(dim3(nb)), dim3(kRayThreads), 0, s, a.blur, a.ni, a.C, a.tmp0,
+                               a.y, a.w, a.tmp1, phi_partials, zarg());
             kt_.stop();
         }
         MBMD_LAUNCHED();
         {
             KernelTimer kt_("k_ray_grad_r", s);
-#define L_(KT, CT) hipLaunchKernelGGL((k_ray_grad_r<KT, CT>), dim3(nb), dim3(kRayThreads), 0, s, model_of(a), \
-                                   a.ni, l, a.tmp1, a.wb, a.gammaA, a.blur, u, v, r)
+#define L_(KT, CT) hipLaunchKernelGGL((k_ray_grad_r<KT, CT>), zgrid(dim3(nb)), dim3(kRayThreads), 0, s, \
+                                   model_of(a), a.ni, l, a.tmp1, a.wb, a.gammaA, a.blur, u, v, r, zarg())
             MBMD_RAY_DISPATCH(a.K, a.C, L_);
 #undef L_
             kt_.stop();

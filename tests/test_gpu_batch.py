@@ -48,11 +48,48 @@ def test_batch_matches_single_problem_iterations(kind):
     _batch_vs_single(kind)
 
 
-@pytest.mark.parametrize("kind", ["fourier", "daub4"])
+@pytest.mark.parametrize("kind", ["fourier", "none", "daub4"])
 def test_batch_of_blurred_problems(kind):
-    """Slices with a projection-domain blur (its three ray passes inside the
-    captured graph); blurred problems never share launches."""
+    """Slices with a projection-domain blur: its three ray passes, inside the
+    captured graph, shared by the slices of one size like every other launch."""
     _batch_vs_single(kind, blur=[[0.2, 0.6, 0.2]])
+
+
+def test_blur_buffers_outside_the_block_and_different_taps():
+    """Slices of one size whose blur buffers were grown outside their blocks
+    (library blocks sized without blur room) cannot be reached by one offset
+    per slice, so they keep launches of their own; slices with different taps
+    form different classes.  Every slice matches itself run alone."""
+    wls = _slices(per_size=4)[:4]                      # four 32^2 slices
+    taps = [[[0.2, 0.6, 0.2]], [[0.2, 0.6, 0.2]], [[0.1, 0.8, 0.1]], [[0.1, 0.8, 0.1]]]
+    kw = [dict(workspace=None, blur_room=False), dict(workspace=None, blur_room=False), {}, {}]
+    calls = (6, 7)
+    announce("batch blur: grown buffers, two tap sets")
+    refs = []
+    for w, t, k in zip(wls, taps, kw):
+        p = mb.Problem.from_workload(w, **k)
+        p.set_blur(t)
+        p.precond_build("fourier")
+        x = p.zeros_image()
+        for n in calls:
+            p.sps_step(x, "fourier", n)
+        refs.append(host(x))
+        p.close()
+    probs = [mb.Problem.from_workload(w, **k) for w, k in zip(wls, kw)]
+    for p, t in zip(probs, taps):
+        p.set_blur(t)
+        p.precond_build("fourier")
+    for use_graph in (False, True):
+        xs = [p.zeros_image() for p in probs]
+        batch = mb.Batch(probs)
+        for n in calls:
+            batch.sps_step(xs, "fourier", n, use_graph=use_graph)
+        got = [host(x) for x in xs]
+        batch.close()
+        for i, (a, r) in enumerate(zip(got, refs)):
+            np.testing.assert_array_equal(a, r, err_msg="slice %d graph=%s" % (i, use_graph))
+    for p in probs:
+        p.close()
 
 
 def _batch_vs_single(kind, blur=None):
@@ -119,8 +156,9 @@ def test_shared_launches_read_each_members_own_data(kind):
 
 
 def test_batch_with_mixed_classes_and_lone_problems():
-    """A class of two, a blurred problem of the same size (alone) and a lone
-    problem of another size, with images that are views of one tensor."""
+    """A class of two, a blurred problem of the same size (a class of its own)
+    and a lone problem of another size, with images that are views of one
+    tensor."""
     wls = _slices(per_size=3)
     pick = [wls[0], wls[1], wls[2], wls[3]]             # three 32^2, one 64^2
     blur = [[0.2, 0.6, 0.2]]
