@@ -1,8 +1,10 @@
 """The boundary's device-memory and failure conventions on the GPU: a problem
 carved from a caller-owned (torch) workspace allocates nothing and iterates
 bit for bit like one in library memory; workspace size, alignment and blur-room
-errors; numeric failures (non-finite data) surface as MBMD_ERR_NUMERIC at the
-synchronizing calls; the standalone projector calls on two streams at once."""
+errors; numeric failures (non-finite data, no positive curvature along the
+direction) surface as MBMD_ERR_NUMERIC at the synchronizing calls; an iterate
+saved to the host resumes bit for bit in a fresh problem; the standalone
+projector calls on two streams at once."""
 
 import ctypes
 
@@ -121,6 +123,54 @@ def test_non_finite_data_is_a_numeric_failure(kind):
         P.gradient(P.zeros_image(), objective=True)
     assert _status(e) == MBMD_ERR_NUMERIC
     P.close()
+
+
+def test_negative_curvature_is_a_numeric_failure():
+    """A strongly negative quadratic penalty (beta = -1e12: not positive
+    semi-definite, which the interface requires but only the symmetry of beta
+    is checked) makes the 1D majoriser's curvature sum c q^2 + p^T R'' p
+    negative: the step is skipped (x stays at its start, as the oracle's
+    alpha = 0) and MBMD_FLAG_NO_CURVATURE surfaces as MBMD_ERR_NUMERIC.  The
+    block-diagonal direction does not depend on beta (the penalty's rows sum
+    to zero), so the sign of that curvature is certain; the Fourier table of
+    such a beta comes from floored negative spectra instead."""
+    kind = "blockdiag"
+    wl = C.make_small_fan(n=32, views=48, bins=64, penalty="quadratic")
+    pen = dict(kind="quadratic", beta=np.array([[-1e12]]), delta=0.0)
+    announce("negative curvature", kind)
+    P = mb.Problem(wl.geom, wl.Q, wl.S, wl.y, wl.w, pen)
+    P.precond_build(kind)
+    x = P.zeros_image()
+    P.sps_step(x, kind, 2)
+    with pytest.raises(_lib.MbmdError) as e:
+        P.check()
+    assert _status(e) == MBMD_ERR_NUMERIC
+    assert "no positive curvature" in str(e.value)
+    assert not np.any(host(x))
+    P.close()
+
+
+def test_resume_from_a_saved_iterate():
+    """The iteration's whole state between calls is x (each call recomputes the
+    line integrals from it; the tables are built deterministically from the
+    data): an iterate saved to the host after 12 iterations and resumed in a
+    fresh problem ends bit for bit where the uninterrupted two calls end."""
+    wl = _fan()
+    announce("checkpoint and resume")
+    P = mb.Problem.from_workload(wl)
+    P.precond_build("fourier")
+    x = P.zeros_image()
+    P.sps_step(x, "fourier", 12)
+    saved = x.detach().cpu().numpy().copy()                 # the checkpoint (FP32, exact)
+    P.sps_step(x, "fourier", 13)
+    straight = host(x)
+    P.close()
+    Q = mb.Problem.from_workload(wl)
+    Q.precond_build("fourier")
+    y = torch.as_tensor(saved, device="cuda")
+    Q.sps_step(y, "fourier", 13)
+    np.testing.assert_array_equal(host(y), straight)
+    Q.close()
 
 
 def test_healthy_run_raises_no_failure_flag():
