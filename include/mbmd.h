@@ -435,16 +435,21 @@ void mbmd_batch_destroy(mbmd_batch* batch);
 
 /*
  * n_iter iterations of every problem of the batch (x_dev[i] belongs to
- * problem i; distinct images).  Bit for bit the iterates of each problem
- * iterated alone.  use_graph != 0 captures one iteration over all problems in a
- * hipGraph on the first call (the geometry groups as parallel branches) and
- * replays it on `stream`; other x pointers, another preconditioner kind or a
- * member problem's blur set since the capture (mbmd_problem_set_blur) make
- * the call capture again.  Preconditioner tables rebuilt in place need no new
- * capture: a replay reads them as they are.  use_graph == 0 enqueues every iteration of each
- * geometry group on its stream.  Either way the work is ordered after what
- * `stream` held before the call and before what it receives after it.
- * Preconditioners must have been built.  No objective trace.
+ * problem i; distinct images; a preconditioner kind every problem has
+ * built).  Each problem's iterates are bit for bit those of mbmd_sps_step
+ * on that problem alone with the same n_iter (every call starts from x).
+ * use_graph != 0 captures one iteration over all problems in a hipGraph on
+ * the first call (classes and lone problems as parallel branches) and
+ * replays it on `stream`; other x pointers, another preconditioner kind or
+ * a member problem's blur set since the capture (mbmd_problem_set_blur) make
+ * the call capture again.  Preconditioner tables rebuilt in place need no
+ * new capture: a replay reads them as they are.  use_graph == 0 enqueues
+ * every iteration of each class or lone problem on its stream.  Either way
+ * the work is ordered after what `stream` held before the call and before
+ * what it receives after it.  No objective trace; each problem's numeric
+ * flags are read by mbmd_problem_check.
+ * Errors: MBMD_ERR_ARG (NULL, unknown preconditioner), MBMD_ERR_NOT_BUILT,
+ * MBMD_ERR_UNSUPPORTED, MBMD_ERR_HIP.
  */
 int mbmd_batch_sps_step(mbmd_batch* batch, float* const* x_dev, int precond, int n_iter,
                         int use_graph, void* stream);
