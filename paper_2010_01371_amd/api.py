@@ -172,6 +172,8 @@ class Problem:
 
     # ------------------------------------------------------------------
     def close(self):
+        if getattr(self, "_batches", 0):
+            raise RuntimeError("this problem belongs to %d open batch(es): close them first" % self._batches)
         if getattr(self, "_h", None):
             self._lib.mbmd_problem_destroy(self._h)
             self._h = None
@@ -294,11 +296,15 @@ class Batch:
         check(lib.mbmd_batch_create(arr, n, ws_ptr, ws_bytes, flags, ctypes.byref(h)), "mbmd_batch_create")
         self._h = h
         self._lib = lib
+        for p in self.problems:              # the C batch borrows them: no close while it is open
+            p._batches = getattr(p, "_batches", 0) + 1
 
     def close(self):
         if getattr(self, "_h", None):
             self._lib.mbmd_batch_destroy(self._h)
             self._h = None
+            for p in self.problems:
+                p._batches -= 1
 
     def __del__(self):
         try:

@@ -208,6 +208,10 @@ def test_batch_workspace_and_flag_errors():
     dup = (ctypes.c_void_p * 2)(probs[0]._h, probs[0]._h)
     st = lib.mbmd_batch_create(dup, 2, None, 0, 0, ctypes.byref(h))
     assert st == ERR_ARG and not h.value
+    batch = mb.Batch(probs)
+    with pytest.raises(RuntimeError):
+        probs[0].close()                                   # borrowed by an open batch
+    batch.close()
     for p in probs:
         p.close()
 
