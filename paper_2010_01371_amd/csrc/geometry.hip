@@ -71,7 +71,7 @@ void build_geometry_host(const mbmd_geometry& g, GeomHost& h) {
     bound.assign((size_t)V * (B + 1), make_float2(0.f, 0.f));
     const int QL = g.nx > g.ny ? g.nx : g.ny;
     std::vector<float4>& line = h.line;
-    line.assign((size_t)QL * V * 2, make_float4(0.f, 0.f, 0.f, 0.f));
+    line.assign((size_t)QL * V * 2 + 2 * kBackMaxU, make_float4(0.f, 0.f, 0.f, 0.f));   // zero padding at the end
     std::vector<float>& path = h.path;
     path.assign((size_t)V * B, 0.0f);
     std::vector<int> views[2];
@@ -253,7 +253,8 @@ static GeomLayout layout_of(const mbmd_geometry& g, int prefix_mat, int back_ch)
     L.path = al256(sizeof(float) * V * B);
     L.fv = al256(sizeof(int) * V);
     L.pre = al256(sizeof(float) * prefix_elems(g.nx, g.ny) * prefix_mat);
-    L.line = back_ch ? al256(sizeof(float4) * QL * V * 2) : 0;   // the back projector's per-line maps
+    // the back projector's per-line maps, padded for the prefetch of its last group of views
+    L.line = back_ch ? al256(sizeof(float4) * (QL * V * 2 + 2 * kBackMaxU)) : 0;
     L.order = al256(sizeof(int) * V * fwd_chunks((int)B) * 2);
     L.det = al256(sizeof(DetEntry) * (size_t)back_ch * V * det_row((int)B));
     L.part = al256(sizeof(float) * (size_t)back_ch * nj);

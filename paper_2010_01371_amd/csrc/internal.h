@@ -31,6 +31,7 @@ struct BlurArgs {
     float taps[kMaxChan][kBlurTaps] = {};
 };
 constexpr int kMaxBackCh = 10;                              // channels of one backprojection
+constexpr int kBackMaxU = 4;                                // views in flight per back projection group
 constexpr int kMaxGpus = 64;                                // devices with cached per-device launch data
 constexpr int kRefreshEvery = 25;                           // recompute l = A x this often
 constexpr int kMaxPartials = 16384;                         // per reduction region

@@ -601,14 +601,21 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
     // for all -- and land while this group's detector gathers are in flight.
     float4 tm[U][LPW];
     float tg[U][LPW];
+    // Each line's entries of the half start at lp[j]; a group's entries lie at
+    // constant offsets from its first view's, so the scalar loads take immediate
+    // offsets from one base per line (one 64-bit add per line and group).  The
+    // prefetch after the last full group reads up to 2 U - 2 entries past the
+    // half's views: they are never used, and the table is padded at its end.
+    static_assert(U <= kBackMaxU, "the per-line table is padded for kBackMaxU views in flight");
+    const float4* lp[LPW];
     auto fetch = [&](int is) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int slot = sl0 + min(is + u, nvh - 1);
+        for (int j = 0; j < LPW; ++j) {
+            const float4* grp = lp[j] + 2 * is;
 #pragma unroll
-            for (int j = 0; j < LPW; ++j) {
-                tm[u][j] = line_tab[lt0[j] + 2 * slot];                                          // {n, m, c, a}
-                tg[u][j] = reinterpret_cast<const float*>(line_tab)[4 * (lt0[j] + 2 * slot + 1)];   // g
+            for (int u = 0; u < U; ++u) {
+                tm[u][j] = grp[2 * u];                                               // {n, m, c, a}
+                tg[u][j] = reinterpret_cast<const float*>(grp + 2 * u + 1)[0];       // g
             }
         }
     };
@@ -617,6 +624,8 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
         if (iv0 >= iv1) continue;                  // no views in this half: it adds zero
         sl0 = slot0 + iv0;
         nvh = iv1 - iv0;
+#pragma unroll
+        for (int j = 0; j < LPW; ++j) lp[j] = line_tab + lt0[j] + 2 * sl0;
         const int nfull = nvh - nvh % U;
         if constexpr (EPL == 1) {
             double acc[LPW][NCH];                   // sum over views of C[b+1]
