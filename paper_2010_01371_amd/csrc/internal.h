@@ -191,7 +191,9 @@ struct GeomTables {
     // for views with orient < 0 it counts bins from the last one
     float4* back_line = nullptr;
     int back_line_q = 0;             // max(nx, ny)
-    DetEntry* det_prefix = nullptr;  // scratch: [back_ch][V][det_row(B)] detector entries
+    // scratch: detector rows of n_ch channels, [n_ch][V][det_row(B)] for one or
+    // two, else packed (det_triples, det_single_base, det_scales)
+    DetEntry* det_prefix = nullptr;
     // scratch: [back_ch][nx][ny] column-sweep part of a back projection
     float* back_part = nullptr;
     // tile shape picked for the back projector per channel count (-1: not yet tuned)
@@ -214,6 +216,26 @@ __host__ __device__ inline int prefix_row(int Np) { return (Np + 4 + 3) & ~3; }
 // [-back_shift(B), back_shift(B)] around the detector centre (shifted by
 // back_shift(B)) always lands inside the row.
 __host__ __device__ inline int det_row(int B) { return B + 2; }
+// From kPackFrom channels on, whole groups of three channels ("triples") share
+// two rows of 16-byte entries, planes A and B ([det_triples(n_ch)][2][V]
+// [det_row(B)]), so that two gathers at the same entry offset serve three
+// channels: channel k of a triple holds q = hi 2^16 + lo, a 48-bit integer
+// with C[b+1] = c0 + q 2^-s for the row's own offset c0 (not stored: it drops
+// out of every pixel) and exponent s, as hi (int32, word k of A), lo (16 bits:
+// word 3 of A, low / high half for k = 0 / 1, word 3 of B for k = 2), and its
+// width w[b] (FP32, word k of B).  The remaining channels keep rows of their
+// own (DetEntry, [n_ch - 3 T][V][det_row(B)]) after the triples, and the
+// triples' scales 2^-s (FP64, [V][3 T]) follow those.
+constexpr int kPackFrom = 3;
+__host__ __device__ inline int det_triples(int n_ch) { return n_ch >= kPackFrom ? n_ch / 3 : 0; }
+// Byte offset of the rows of the channels outside the triples.
+__host__ __device__ inline size_t det_single_base(int n_ch, int V, int B) {
+    return (size_t)2 * det_triples(n_ch) * V * det_row(B) * sizeof(DetEntry);
+}
+// Byte offset of the triples' scale table (the end of the rows).
+__host__ __device__ inline size_t det_scales(int n_ch, int V, int B) {
+    return det_single_base(n_ch, V, B) + (size_t)(n_ch - 3 * det_triples(n_ch)) * V * det_row(B) * sizeof(DetEntry);
+}
 
 // Forward projection tiling: wavefronts of two bin boundaries per lane (127 bins),
 // blocks of kFwdWaves such wavefronts along the detector ("chunks"), and each
@@ -315,7 +337,8 @@ struct BackClear {
 // rows itself (instead of the detector-prefix launch): the rows, the per-view
 // records and path lengths they are built from, and the pixels to clear for the
 // tile shape in use.  ok is false until that shape is chosen for n_ch channels
-// (the first back projection of a geometry and channel count tunes it).
+// (the first back projection of a geometry and channel count tunes it), and for
+// packed rows (kPackFrom channels or more), which only the detector prefix writes.
 struct BackRows {
     bool ok;
     DetEntry* rows;               // [n_ch][V][det_row(B)]

@@ -143,6 +143,61 @@ __device__ __forceinline__ DetValue load_det(__amdgpu_buffer_rsrc_t r, int voff,
 // Marks a register as read here (an empty instruction string: no code).
 __device__ __forceinline__ void keep(float v) { asm volatile("" ::"v"(v)); }
 
+// One view's detector values at a lane's edge for NCH channels (see
+// kPackFrom): two 16-byte gathers per triple of channels (planes A and B), one
+// per remaining channel, all at the same entry offset.
+template <int NCH>
+struct DetView {
+    static constexpr int T = NCH >= kPackFrom ? NCH / 3 : 0;     // triples
+    static constexpr int L = NCH - 3 * T;                        // channels with rows of their own
+    float4 a[T ? T : 1], b[T ? T : 1];
+    DetValue e[L ? L : 1];
+};
+// The values at entry offset off (bytes) of a view whose row starts soff bytes
+// into the first set of rows; vstride: the distance between sets of rows (V
+// rows, bytes).  Triple t takes sets 2 t and 2 t + 1, the remaining channels
+// one set each after the triples.
+template <int NCH>
+__device__ __forceinline__ void load_view(__amdgpu_buffer_rsrc_t r, int off, int soff, int vstride,
+                                          DetView<NCH>& v) {
+    constexpr int T = DetView<NCH>::T;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        v.a[t] = load_f4(r, off, soff + 2 * t * vstride);
+        v.b[t] = load_f4(r, off, soff + (2 * t + 1) * vstride);
+    }
+#pragma unroll
+    for (int j = 0; j < DetView<NCH>::L; ++j) v.e[j] = load_det(r, off, soff + (2 * T + j) * vstride);
+}
+// Adds one view: per channel the FP64 sum of C[b+1] (a triple's q 2^-s with the
+// row scale sc[c], an exact product, so the one rounding is the sum's, as for
+// an entry of its own) and the FP32 sum of (fr - 1) w[b].
+template <int NCH>
+__device__ __forceinline__ void add_view(const DetView<NCH>& v, float fr, const double* sc, double* acc,
+                                         float* accw) {
+#pragma unroll
+    for (int t = 0; t < DetView<NCH>::T; ++t) {
+        const int hi[3] = {__float_as_int(v.a[t].x), __float_as_int(v.a[t].y), __float_as_int(v.a[t].z)};
+        const unsigned l01 = __float_as_uint(v.a[t].w);
+        const unsigned lo[3] = {l01 & 0xffffu, l01 >> 16, __float_as_uint(v.b[t].w)};
+        const float w[3] = {v.b[t].x, v.b[t].y, v.b[t].z};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int c = 3 * t + k;
+            const double q = __builtin_fma((double)hi[k], 65536.0, (double)lo[k]);   // exact: |q| < 2^47
+            acc[c] = __builtin_fma(q, sc[c], acc[c]);
+            accw[c] = fmaf(fr, w[k], accw[c] - w[k]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < DetView<NCH>::L; ++j) {
+        const int c = 3 * DetView<NCH>::T + j;
+        acc[c] += v.e[j].c;                                      // C[b+1]
+        accw[c] = fmaf(fr, v.e[j].d, accw[c] - v.e[j].d);        // + (fr - 1) w[b]
+        keep(v.e[j].dn);
+    }
+}
+
 // Exclusive prefix sums F[p] = sum_{p'<p} img[p'] (FP64 accumulation, stored
 // FP32) of every sweep line of n_mat images, entries Np .. Np+3 holding the line
 // total.  One block per line: blocks [0, ny) take the rows (frame 0), blocks
@@ -202,16 +257,18 @@ __global__ __launch_bounds__(kScanThreads) void k_line_prefix(const float* __res
     if (threadIdx.x < 4) dst[Np + threadIdx.x] = (float)part[kScanThreads - 1];
 }
 
-// Per slot and channel, the row of detector entries (see build_detector_row)
-// of the widths w[b] = sino[b'] path[b'] of the bins in increasing-K order
-// (b' = b, or B - 1 - b for views with orient < 0).  One workgroup per (slot,
-// channel); every workgroup also clears its share of the pixels the back
-// projection kernel adds into.
+// Per slot, the detector rows (see build_detector_row, and build_triple_rows
+// for the channels in triples) of the widths w[b] = sino[b'] path[b'] of the
+// bins in increasing-K order (b' = b, or B - 1 - b for views with orient < 0).
+// One workgroup per (slot, triple) and per (slot, channel outside triples):
+// blockIdx.y < T takes triple blockIdx.y, the others channel 3 T + blockIdx.y -
+// T.  Every workgroup also clears its share of the pixels the back projection
+// kernel adds into.
 constexpr int kPrefixThreads = kRowThreads;
 __global__ __launch_bounds__(kPrefixThreads) void k_detector_prefix(const float* __restrict__ sino,
                                                                      const float* __restrict__ path,
                                                                      const ViewParams* __restrict__ view, int V,
-                                                                     int B, DetEntry* __restrict__ C,
+                                                                     int B, int nch, DetEntry* __restrict__ C,
                                                                      BackClear tc, const long long* __restrict__ zd) {
     if (zd) {                                                  // batched: this slice's buffers
         const long long d = zoff(zd, Z_BLOCK);
@@ -223,17 +280,34 @@ __global__ __launch_bounds__(kPrefixThreads) void k_detector_prefix(const float*
         tc.part = zshift(tc.part, d);
     }
     clear_back_pixels(tc, blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);   // side job
-    const int slot = blockIdx.x, ch = blockIdx.y;
+    const int slot = blockIdx.x, set = blockIdx.y;
     const bool rev = view[slot].orient < 0.0f;
-    const float* s = sino + ((size_t)ch * V + vp_view(view[slot])) * B;
     const float* pa = path + (size_t)slot * B;
-    __shared__ double wave_total[kPrefixThreads / 64];
-    build_detector_row(
-        [&](int b) {                                              // b in row order, < B
-            const int k = rev ? B - 1 - b : b;
-            return (float)((double)s[k] * (double)pa[k]);
-        },
-        B, C + ((size_t)ch * V + slot) * det_row(B), wave_total);
+    const int vw = vp_view(view[slot]);
+    __shared__ double lds[12 * kPrefixThreads / 64];
+    char* rows = reinterpret_cast<char*>(C);
+    const int T = det_triples(nch);
+    if (set < T) {                                                // uniform
+        const float* s = sino + ((size_t)(3 * set) * V + vw) * B;
+        const size_t cs = (size_t)V * B;                          // channel stride of sino
+        build_triple_rows(
+            [&](int k, int b) {                                   // b in row order, < B
+                const int i = rev ? B - 1 - b : b;
+                return (float)((double)s[k * cs + i] * (double)pa[i]);
+            },
+            B, C + ((size_t)2 * set * V + slot) * det_row(B), (size_t)V * det_row(B),
+            reinterpret_cast<double*>(rows + det_scales(nch, V, B)) + (size_t)slot * 3 * T + 3 * set, lds);
+    } else {
+        const int ch = 3 * T + (set - T);
+        const float* s = sino + ((size_t)ch * V + vw) * B;
+        DetEntry* single = reinterpret_cast<DetEntry*>(rows + det_single_base(nch, V, B));
+        build_detector_row(
+            [&](int b) {                                          // b in row order, < B
+                const int i = rev ? B - 1 - b : b;
+                return (float)((double)s[i] * (double)pa[i]);
+            },
+            B, single + ((size_t)(set - T) * V + slot) * det_row(B), lds);
+    }
 }
 
 // Work of the two sweep frames of one launch.
@@ -447,7 +521,8 @@ __device__ __forceinline__ EdgePair back_pair(const float4& m, float g, float K,
 template <int NCH>
 __device__ __forceinline__ void back_tail(const float4* __restrict__ line_tab, int tw, int is0, int is1, int slot0,
                                           int Np, int Nq, int V, int B, int frame, int nx, int ny, int ppw,
-                                          const __amdgpu_buffer_rsrc_t& tc, int row, float* __restrict__ dst) {
+                                          const __amdgpu_buffer_rsrc_t& tc, int row, const double* __restrict__ sct,
+                                          float* __restrict__ dst) {
     constexpr int UT = NCH <= 2 ? 4 : 2;   // keeps the tail within the main path's registers
     if (is0 >= is1) return;                // no views in this half (uniform)
     const BackTiling bt = back_tiling(Np, ppw);
@@ -486,21 +561,21 @@ __device__ __forceinline__ void back_tail(const float4* __restrict__ line_tab, i
         float fr[UT];
 #pragma unroll
         for (int u = 0; u < UT; ++u) back_locate(tm[u], tg[u], K, span, origin, off[u], fr[u]);
-        DetValue h[UT][NCH];
+        DetView<NCH> h[UT];
+#pragma unroll
+        for (int u = 0; u < UT; ++u)
+            load_view<NCH>(tc, off[u], (slot0 + min(is + u, is1 - 1)) * row, V * row, h[u]);
+        fetch(is + UT);
+        constexpr int NT = 3 * DetView<NCH>::T;                // triple channels: their rows' scales
+        double sc[UT][NT ? NT : 1];
 #pragma unroll
         for (int u = 0; u < UT; ++u)
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) h[u][c] = load_det(tc, off[u], (c * V + slot0 + min(is + u, is1 - 1)) * row);
-        fetch(is + UT);
+            for (int c = 0; c < NT; ++c) sc[u][c] = sct[(size_t)(slot0 + min(is + u, is1 - 1)) * NT + c];
 #pragma unroll
         for (int u = 0; u < UT; ++u) {
             if (is + u >= is1) break;                          // uniform
-#pragma unroll
-            for (int c = 0; c < NCH; ++c) {
-                acc[c] += h[u][c].c;                           // C[b+1]
-                accw[c] = fmaf(fr[u], h[u][c].d, accw[c] - h[u][c].d);  // + (fr - 1) w[b]
-                keep(h[u][c].dn);
-            }
+            add_view<NCH>(h[u], fr[u], sc[u], acc, accw);
         }
     }
     const size_t img_stride = (size_t)nx * ny;
@@ -550,7 +625,10 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
     const int nv = frame ? nv1 : nv0;
     const int slot0 = frame ? nv0 : 0;
     const int row = det_row(B) * (int)sizeof(DetEntry);
-    const __amdgpu_buffer_rsrc_t tc = rsrc(C, (size_t)row * NCH * V);
+    const __amdgpu_buffer_rsrc_t tc = rsrc(C, det_scales(NCH, V, B));
+    // the triples' scales [slot][3 T]
+    const double* sct = reinterpret_cast<const double*>(reinterpret_cast<const char*>(C) + det_scales(NCH, V, B));
+    constexpr int NT = 3 * DetView<NCH>::T;
     // the tail items come first: their wavefronts are the longest, so they are
     // dispatched before the main ones fill the machine
     constexpr int PPW = back_ppw(EPL);
@@ -560,7 +638,7 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
         if (tw * back_tiling(Np, PPW).tail_lines >= Nq) return;      // whole wavefront past the last line
         const int mid = nv >> 1;
         back_tail<NCH>(line_tab, tw, (item & 1) ? mid : 0, (item & 1) ? nv : mid, slot0, Np, Nq, V, B, frame, nx,
-                       ny, PPW, tc, row, frame ? part : x);
+                       ny, PPW, tc, row, sct, frame ? part : x);
         return;
     }
     item -= tail_items;
@@ -637,6 +715,7 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
                     acc[j][c] = 0.0;
                     accw[j][c] = 0.0f;
                 }
+            const double* scp = sct + (size_t)sl0 * NT;      // the half's triple scales
             fetch(0);
             for (int is = 0; is < nfull; is += U) {   // trip counts are uniform over the wavefront
                 int off[U][LPW];
@@ -646,43 +725,41 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
 #pragma unroll
                     for (int j = 0; j < LPW; ++j)
                         back_locate(tm[u][j], tg[u][j], K, span, origin, off[u][j], frs[u][j]);
-                DetValue hv[U][LPW][NCH];
+                DetView<NCH> hv[U][LPW];
 #pragma unroll
                 for (int u = 0; u < U; ++u)
 #pragma unroll
                     for (int j = 0; j < LPW; ++j)
-#pragma unroll
-                        for (int c = 0; c < NCH; ++c)
-                            hv[u][j][c] = load_det(tc, off[u][j], (c * V + sl0 + is + u) * row);
+                        load_view<NCH>(tc, off[u][j], (sl0 + is + u) * row, V * row, hv[u][j]);
+                // the scales of this group's triple rows arrive with the next group's tables
+                double sc[U][NT ? NT : 1];
                 __builtin_amdgcn_sched_barrier(0);
                 fetch(is + U);
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int c = 0; c < NT; ++c) sc[u][c] = scp[(is + u) * NT + c];
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int u = 0; u < U; ++u)
 #pragma unroll
-                    for (int j = 0; j < LPW; ++j)
-#pragma unroll
-                        for (int c = 0; c < NCH; ++c) {
-                            acc[j][c] += hv[u][j][c].c;
-                            accw[j][c] = fmaf(frs[u][j], hv[u][j][c].d, accw[j][c] - hv[u][j][c].d);
-                            keep(hv[u][j][c].dn);
-                        }
+                    for (int j = 0; j < LPW; ++j) add_view<NCH>(hv[u][j], frs[u][j], sc[u], acc[j], accw[j]);
             }
             // the remaining views (fewer than U); their tables were fetched into slots 0..
 #pragma unroll
             for (int u = 0; u < U - 1; ++u) {
                 if (nfull + u >= nvh) break;   // uniform
+                double sc[NT ? NT : 1];
+#pragma unroll
+                for (int c = 0; c < NT; ++c) sc[c] = scp[(nfull + u) * NT + c];
 #pragma unroll
                 for (int j = 0; j < LPW; ++j) {
                     int o;
                     float fr;
                     back_locate(tm[u][j], tg[u][j], K, span, origin, o, fr);
-#pragma unroll
-                    for (int c = 0; c < NCH; ++c) {
-                        const DetValue hr = load_det(tc, o, (c * V + sl0 + nfull + u) * row);
-                        acc[j][c] += hr.c;
-                        accw[j][c] = fmaf(fr, hr.d, accw[j][c] - hr.d);   // as in the main loop
-                    }
+                    DetView<NCH> hr;
+                    load_view<NCH>(tc, o, (sl0 + nfull + u) * row, V * row, hr);
+                    add_view<NCH>(hr, fr, sc, acc[j], accw[j]);   // as in the main loop
                 }
             }
 #pragma unroll
@@ -692,6 +769,7 @@ __global__ __launch_bounds__(kThreads) void k_dd_back(const float4* __restrict__
                     outa[j][c] += (float)((next_lane(acc[j][c]) - acc[j][c]) +
                                           (double)(next_lane(accw[j][c]) - accw[j][c]));
         } else {
+            static_assert(NCH < kPackFrom, "two edges per lane read unpacked rows (one or two channels)");
             double acc[LPW][NCH];                   // sum over views of C[b0+1]
             float wa[LPW][NCH], wb[LPW][NCH];       // sums over views of H(A) - C[b0+1], H(B) - C[b0+1]
             double accw64[LPW][NCH];                // the part of the latter from wide lanes' C[bB+1] - C[b0+1]
@@ -863,8 +941,8 @@ void fwd_launch(const GeomTables& t, float* sino, hipStream_t s) {
     MBMD_LAUNCHED();
 }
 
-// Wavefronts of k_dd_back<NCH, LPW, 2, 2> resident on the whole device at once.
-template <int NCH, int LPW>
+// Wavefronts of k_dd_back<NCH, LPW, 2, EPL> resident on the whole device at once.
+template <int NCH, int LPW, int EPL>
 int back_waves_per_round() {
     static int cached[kMaxGpus] = {};
     int dev = 0;
@@ -873,7 +951,7 @@ int back_waves_per_round() {
     if (!cached[dev]) {
         int cus = 0, occ = 0;
         MBMD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        MBMD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_dd_back<NCH, LPW, 2, 2>, kThreads, 0));
+        MBMD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_dd_back<NCH, LPW, 2, EPL>, kThreads, 0));
         cached[dev] = (cus > 0 ? cus : 1) * (occ > 0 ? occ : 1) * kWaves;
     }
     return cached[dev];
@@ -1013,8 +1091,9 @@ const float* back_launch(const GeomTables& t, const float* sino, float* x, hipSt
     // precedes every back projection kernel (the tuner's too).
     auto prefix = [&](const BackShape& sh) {
         KernelTimer kt_("k_detector_prefix", s);
-        hipLaunchKernelGGL(k_detector_prefix, zgrid(dim3(t.V, NCH)), dim3(kPrefixThreads), 0, s, sino, t.path,
-                           t.view, t.V, t.B, t.det_prefix, back_clear(t, x, NCH, sh), zarg());
+        constexpr int sets = NCH - 2 * (NCH >= kPackFrom ? NCH / 3 : 0);   // triples and single rows
+        hipLaunchKernelGGL(k_detector_prefix, zgrid(dim3(t.V, sets)), dim3(kPrefixThreads), 0, s, sino, t.path,
+                           t.view, t.V, t.B, NCH, t.det_prefix, back_clear(t, x, NCH, sh), zarg());
         kt_.stop();
         MBMD_LAUNCHED();
     };
@@ -1078,9 +1157,10 @@ const float* back_launch(const GeomTables& t, const float* sino, float* x, hipSt
                 return (u0 + u1) * kWaves;
             };
             // two edges: one line per wavefront (shape 0) or two (shape 2); one edge: shape 0
-            const double c1 = back_cost(waves(1), back_waves_per_round<NCH, 1>(), 1, simds);
-            constexpr int N2 = NCH <= 2 ? NCH : 1;
-            const double c2 = two_edges ? back_cost(waves(2), back_waves_per_round<N2, 2>(), 2, simds) : 1e300;
+            constexpr int N2 = NCH <= 2 ? NCH : 1;     // two edges per lane: one or two channels only
+            const int per1 = two_edges ? back_waves_per_round<N2, 1, 2>() : back_waves_per_round<NCH, 1, 1>();
+            const double c1 = back_cost(waves(1), per1, 1, simds);
+            const double c2 = two_edges ? back_cost(waves(2), back_waves_per_round<N2, 2, 2>(), 2, simds) : 1e300;
             const int pick = c2 < c1 ? 2 : 0;
             if (cap != hipStreamCaptureStatusNone) {
                 run(pick);                             // not cached: tune on a later uncaptured call
@@ -1203,12 +1283,11 @@ const float* back_kernel_n(const GeomTables& t, float* x, hipStream_t s) {
 BackRows back_rows(const GeomTables& t, float* x, int n_ch) {
     MBMD_REQUIRE(n_ch >= 1 && n_ch <= kMaxBackCh, MBMD_ERR_SHAPE, "back projection channels must be in 1..10");
     MBMD_REQUIRE(t.det_prefix != nullptr && t.back_ch >= n_ch, MBMD_ERR_ARG, "back projection scratch too small");
+    static_assert(kPackFrom == 3, "producers write the unpacked rows of one or two channels");
     switch (n_ch) {
         case 1: return back_rows_n<1>(t, x);
         case 2: return back_rows_n<2>(t, x);
-        case 3: return back_rows_n<3>(t, x);
-        case 4: return back_rows_n<4>(t, x);
-        default: return BackRows{};               // more channels: the detector-prefix path
+        default: return BackRows{};               // packed rows: the detector-prefix path
     }
 }
 
@@ -1216,9 +1295,7 @@ const float* launch_back_kernel(const GeomTables& t, float* x, int n_ch, hipStre
     switch (n_ch) {
         case 1: return back_kernel_n<1>(t, x, s);
         case 2: return back_kernel_n<2>(t, x, s);
-        case 3: return back_kernel_n<3>(t, x, s);
-        case 4: return back_kernel_n<4>(t, x, s);
-        default: MBMD_REQUIRE(false, MBMD_ERR_ARG, "detector rows are written by the caller for 1..4 channels only");
+        default: MBMD_REQUIRE(false, MBMD_ERR_ARG, "detector rows are written by the caller for 1 or 2 channels only");
     }
     return nullptr;
 }

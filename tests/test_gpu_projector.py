@@ -56,7 +56,7 @@ def test_project_matches_oracle(name, nmat):
 
 
 @pytest.mark.parametrize("name", sorted(GEOMS))
-@pytest.mark.parametrize("nch", [1, 2, 6])
+@pytest.mark.parametrize("nch", [1, 2, 3, 6])
 def test_backproject_matches_oracle(name, nch):
     g = GEOMS[name]
     rng = np.random.default_rng(2)
@@ -75,6 +75,49 @@ def test_backproject_signed_data():
     got = host(mb.backproject(g, dev(s)))
     want = OP.backproject(g, s)
     assert l2rel(got, want) <= TOL_PROJ
+
+
+@pytest.mark.parametrize("name", ["fan_ragged", "fan_c4"])
+def test_packed_rows_keep_each_channel_apart(name):
+    """From three channels on, the detector rows hold two channels per entry,
+    each row with its own power-of-two scale: a channel keeps the normwise bound
+    of its own output whatever the magnitudes of the others (here 1, 1e-6 and
+    1e6, two of them with mixed signs), an all-zero channel gives exact zeros,
+    and changing one channel's data leaves the others' outputs bitwise
+    unchanged.  (Zero-mean data would cancel in the image to where FP32 sums,
+    packed or not, reach 1.2e-5 of the largest pixel at 256^2.)"""
+    g = GEOMS[name]
+    rng = np.random.default_rng(12)
+    shape = (g["n_views"], g["n_bins"])
+    s = np.stack([rng.uniform(-0.3, 1.0, size=shape), 1e-6 * rng.uniform(size=shape),
+                  1e6 * rng.uniform(-0.3, 1.0, size=shape), np.zeros(shape)])
+    announce("packed rows per channel", name)
+    got = host(mb.backproject(g, dev(s)))
+    want = OP.backproject(g, s)
+    for c in range(3):
+        assert maxrel(got[c], want[c]) <= TOL_PROJ, (c, maxrel(got[c], want[c]))
+    assert not np.any(got[3])
+    s2 = s.copy()
+    s2[1] = rng.uniform(size=shape)
+    got2 = host(mb.backproject(g, dev(s2)))
+    for c in (0, 2, 3):
+        np.testing.assert_array_equal(got2[c], got[c])
+    assert maxrel(got2[1], OP.backproject(g, s2[1:2])[0]) <= TOL_PROJ
+
+
+def test_packed_rows_carry_a_nonfinite_value():
+    """A NaN in one channel's data (a packed row's scale becomes NaN) makes that
+    channel's output NaN where the view reaches and leaves the other channels
+    bitwise as without it."""
+    g = GEOMS["fan_ragged"]
+    s = np.random.default_rng(13).uniform(size=(3, g["n_views"], g["n_bins"]))
+    announce("packed rows nonfinite")
+    clean = host(mb.backproject(g, dev(s)))
+    s[1, 5, 150] = np.nan
+    bad = host(mb.backproject(g, dev(s)))
+    assert np.isnan(bad[1]).any()
+    np.testing.assert_array_equal(bad[0], clean[0])
+    np.testing.assert_array_equal(bad[2], clean[2])
 
 
 @pytest.mark.parametrize("name", ["fan64", "fan_ragged", "c1_parallel"])
@@ -173,7 +216,7 @@ def _back_shapes(g, nch):
 
 
 @pytest.mark.parametrize("name", ["fan_ragged", "fan_ragged_wide"])
-@pytest.mark.parametrize("nch", [1, 2, 3])
+@pytest.mark.parametrize("nch", [1, 2, 3, 6])
 def test_back_projector_tile_shapes_agree(name, nch, monkeypatch):
     """The tile shapes the autotuner chooses from (lines per wavefront, views
     in flight, views split over two wavefronts or not) sum every pixel as the
