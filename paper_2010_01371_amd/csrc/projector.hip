@@ -1125,10 +1125,13 @@ const float* back_launch(const GeomTables& t, const float* sino, float* x, hipSt
             MBMD_HIP(hipEventCreate(&ev[1]));
             // Candidates interleaved over several rounds, each keeping its best
             // round: the shapes are often within a few per cent of each other,
-            // closer than the spread of back-to-back launches.
+            // closer than the spread of back-to-back launches, and the first
+            // back projection of a process often meets the device still
+            // raising its clocks (two warm-up passes).
             float best[5] = {1e30f, 1e30f, 1e30f, 1e30f, 1e30f};
-            for (int v = 0; v < n_cand; ++v) run(v);  // warm-up
-            for (int round = 0; round < 4; ++round)
+            for (int pass = 0; pass < 2; ++pass)
+                for (int v = 0; v < n_cand; ++v) run(v);  // warm-up
+            for (int round = 0; round < 6; ++round)
                 for (int v = 0; v < n_cand; ++v) {
                     MBMD_HIP(hipEventRecord(ev[0], s));
                     for (int r = 0; r < 2; ++r) run(v);  // the prefix is the same for every candidate
