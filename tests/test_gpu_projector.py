@@ -67,6 +67,22 @@ def test_backproject_matches_oracle(name, nch):
     assert maxrel(got, want) <= TOL_PROJ, maxrel(got, want)
 
 
+@pytest.mark.parametrize("name", ["fan_ragged", "parallel_offset", "fan_ragged_wide"])
+@pytest.mark.parametrize("nch", [4, 5, 7, 10])
+def test_backproject_mixed_row_layouts(name, nch):
+    """Channel counts whose detector rows mix packed triples with rows of their
+    own (4 = 3 + 1, 5 = 3 + 2, 7 = 6 + 1, 10 = 9 + 1, the largest count):
+    every channel within the bound, each against its own largest pixel."""
+    g = GEOMS[name]
+    rng = np.random.default_rng(20 + nch)
+    s = rng.uniform(-0.2, 1.0, size=(nch, g["n_views"], g["n_bins"])) * rng.uniform(0.1, 10.0, size=(nch, 1, 1))
+    announce("backproject mixed layouts", name, nch)
+    got = host(mb.backproject(g, dev(s)))
+    want = OP.backproject(g, s)
+    for c in range(nch):
+        assert maxrel(got[c], want[c]) <= TOL_PROJ, (c, maxrel(got[c], want[c]))
+
+
 def test_backproject_signed_data():
     """Mixed-sign sinograms (residual-like) keep the same normwise bound."""
     g = GEOMS["fan64"]
