@@ -189,7 +189,12 @@ int mbmd_project(const mbmd_geometry* geom, const float* x_dev, float* sino_dev,
  * x_dev[m] = A^T sino_dev[m] for m < n_ch (matched back projection with the
  * same weights; pixel-driven, deterministic, FP64 sums over views).
  * sino_dev: [n_ch][n_views][n_bins]; x_dev: [n_ch][ny][nx] (overwritten);
- * 1 <= n_ch <= 10.  Same caching and errors as mbmd_project.
+ * 1 <= n_ch <= 10.  Each view's cumulative detector integral is FP64; from
+ * three channels on, groups of three hold it as 48-bit fixed point relative
+ * to its own range (within 2^-47 of that range, far below the FP32 widths'
+ * rounding), so that one pair of loads serves three channels.  A channel's
+ * result does not depend on the other channels' data.  Same caching and errors
+ * as mbmd_project.
  */
 int mbmd_backproject(const mbmd_geometry* geom, const float* sino_dev, float* x_dev,
                      int n_ch, void* stream);
