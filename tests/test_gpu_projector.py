@@ -83,6 +83,41 @@ def test_backproject_mixed_row_layouts(name, nch):
         assert maxrel(got[c], want[c]) <= TOL_PROJ, (c, maxrel(got[c], want[c]))
 
 
+# Degenerate shapes: one view, one or two bins, a one-pixel-wide image, a
+# 3 x 2 image, one fan-beam view.
+DEGENERATE = {
+    "one_view": C.geometry("parallel", 24, 20, 1.0, 1.0, 1, np.pi, 31, 1.0, theta0=0.3),
+    "two_bins": C.geometry("parallel", 16, 16, 1.0, 1.0, 5, np.pi, 2, 9.0, theta0=0.1),
+    "one_bin": C.geometry("parallel", 8, 8, 1.0, 1.0, 3, np.pi, 1, 12.0, theta0=0.2),
+    "one_column": C.geometry("parallel", 1, 33, 1.0, 1.0, 7, np.pi, 41, 1.0, theta0=0.05),
+    "three_by_two": C.geometry("parallel", 3, 2, 1.0, 1.0, 4, np.pi, 5, 1.0, theta0=0.4),
+    "fan_one_view": C.geometry("fan", 20, 24, 1.0, 1.0, 1, 2 * np.pi, 45, 1.2, theta0=0.7, dso=100.0,
+                               dsd=180.0),
+}
+
+
+@pytest.mark.parametrize("name", sorted(DEGENERATE))
+def test_projection_pair_at_degenerate_shapes(name):
+    """Forward (one and three materials) and back projection (one channel,
+    a packed triple, a triple and a row of its own) against the oracle at
+    degenerate shapes, where every sweep line is a tail or a frame has no
+    views."""
+    g = DEGENERATE[name]
+    rng = np.random.default_rng(30)
+    x = rng.uniform(size=(3, g["ny"], g["nx"]))
+    s = rng.uniform(size=(4, g["n_views"], g["n_bins"]))
+    announce("degenerate projection pair", name)
+    for nmat in (1, 3):
+        got = host(mb.project(g, dev(x[:nmat])))
+        want = OP.project(g, x[:nmat])
+        assert maxrel(got, want) <= TOL_PROJ, (nmat, maxrel(got, want))
+    for nch in (1, 3, 4):
+        got = host(mb.backproject(g, dev(s[:nch])))
+        want = OP.backproject(g, s[:nch])
+        for c in range(nch):
+            assert maxrel(got[c], want[c]) <= TOL_PROJ, (nch, c, maxrel(got[c], want[c]))
+
+
 def test_backproject_signed_data():
     """Mixed-sign sinograms (residual-like) keep the same normwise bound."""
     g = GEOMS["fan64"]
